@@ -1,0 +1,335 @@
+"""Pins of the CPU oracle against things other than itself (CPU only).
+
+Each test names what fixes the expected value: a closed form, a library
+routine (numpy / scipy / mpmath), an exact identity of the method (discrete
+orthonormality behind B = A^T W, Section 3.1.1; parity, Section 3.1.2;
+exactness of the phi trapezoid rule, Section 1) or brute-force integration.
+A plausible mistake in the oracle (a dropped term, a wrong sign or index, a
+transposed operand, a missing conjugation or weight) fails at least one.
+"""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+import scipy.special as sps
+
+import oracle
+from paper_2004_11346_amd import inputs
+
+
+# ---------------------------------------------------------------- GL rule
+@pytest.mark.parametrize("n", [2, 3, 8, 64, 128, 199, 200])
+def test_gl_matches_numpy_leggauss(n):
+    x, w = oracle.gauss_legendre(n)
+    xr, wr = np.polynomial.legendre.leggauss(n)
+    assert np.all(np.diff(x) > 0)
+    np.testing.assert_allclose(x, xr, rtol=0, atol=2e-15)
+    # numpy's leggauss weights carry errors up to ~2.5e-14 absolute at n = 128
+    np.testing.assert_allclose(w, wr, rtol=0, atol=4e-14)
+    np.testing.assert_array_equal(x, -x[::-1])  # exact mirror symmetry
+    np.testing.assert_array_equal(w, w[::-1])
+
+
+@pytest.mark.parametrize("n", [17, 128])
+def test_gl_vs_mpmath(n):
+    """Nodes are roots of P_n and w = 2/((1-x^2) P_n'(x)^2), checked in 60 digits."""
+    mpmath.mp.dps = 60
+    x, w = oracle.gauss_legendre(n)
+    for i in [0, 1, n // 3, n // 2, n - 1]:
+        t = mpmath.findroot(lambda u: mpmath.legendre(n, u), mpmath.mpf(x[i]), verify=False)
+        assert abs(mpmath.legendre(n, t)) < mpmath.mpf("1e-30")
+        dp = mpmath.diff(lambda u: mpmath.legendre(n, u), t)
+        assert abs(float(t) - x[i]) <= 2e-16
+        assert abs(float(2 / ((1 - t * t) * dp * dp)) - w[i]) <= 4e-16 * w[i] + 1e-18
+
+
+@pytest.mark.parametrize("n", [256, 2048])
+def test_gl_moments(n):
+    """sum w = 2 and sum w x^(2j) = 2/(2j+1) for 2j <= 2n-1 (degree of exactness)."""
+    x, w = oracle.gauss_legendre(n)
+    xl = np.array(x, dtype=np.longdouble)
+    wl = np.array(w, dtype=np.longdouble)
+    assert abs(float(wl.sum()) - 2.0) < 4e-15
+    for j in [1, 2, 5, 17, n // 3, n - 1]:
+        mom = float(np.sum(wl * xl ** (2 * j)))
+        assert abs(mom - 2.0 / (2 * j + 1)) < 4e-15 * max(1.0, 2.0 / (2 * j + 1)) * 10
+
+
+# ---------------------------------------------------------------- Pbar_k^m
+def _closed(k, m, t):
+    s = math.sqrt(1 - t * t)
+    table = {
+        (0, 0): 1 / math.sqrt(2),
+        (1, 0): math.sqrt(1.5) * t,
+        (1, 1): math.sqrt(3) / 2 * s,
+        (2, 0): math.sqrt(5 / 8) * (3 * t * t - 1),
+        (2, 1): math.sqrt(15) / 2 * t * s,
+        (2, 2): math.sqrt(15) / 4 * (1 - t * t),
+        (3, 0): math.sqrt(7 / 8) * (5 * t ** 3 - 3 * t),
+        (3, 3): math.sqrt(35 / 8) / 2 * s ** 3,
+    }
+    return table[(k, m)]
+
+
+@pytest.mark.parametrize("t", [-0.93, -0.2, 0.0, 0.37, 0.999])
+def test_plm_closed_forms(t):
+    for (k, m) in [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 3)]:
+        v = oracle.plm(m, k, t)[k - m]
+        assert abs(v - _closed(k, m, t)) < 1e-15, (k, m, t)
+
+
+def test_plm_diagonal_closed_form():
+    """Pbar_m^m = sqrt((2m+1)/2 * (2m-1)!!/(2m)!!) (1-t^2)^(m/2), via mpmath."""
+    mpmath.mp.dps = 40
+    for m in [4, 17, 60, 200, 511]:
+        for t in [0.1, 0.6, 0.95]:
+            dfact = mpmath.fprod([mpmath.mpf(2 * i - 1) / (2 * i) for i in range(1, m + 1)])
+            ref = mpmath.sqrt((2 * m + 1) * dfact / 2) * mpmath.power(1 - mpmath.mpf(t) ** 2, mpmath.mpf(m) / 2)
+            v = oracle.plm(m, m, t)[0]
+            assert abs(v - float(ref)) <= 1e-14 * abs(float(ref)), (m, t)
+
+
+@pytest.mark.parametrize("t", [-0.71, 0.05, 0.5, 0.98])
+def test_plm_m0_vs_scipy_legendre(t):
+    kmax = 300
+    v = oracle.plm(0, kmax, t)
+    k = np.arange(kmax + 1)
+    ref = np.sqrt((2 * k + 1) / 2.0) * sps.eval_legendre(k, t)
+    np.testing.assert_allclose(v, ref, rtol=0, atol=2e-13)
+
+
+def test_plm_vs_scipy_normalised_ferrers():
+    """scipy's norm=True Ferrers functions carry the Condon-Shortley phase:
+    Pbar_k^m = (-1)^m * P_scipy."""
+    for m in [0, 1, 2, 5, 13, 40]:
+        for t in [-0.8, -0.1, 0.3, 0.77]:
+            kmax = 90
+            v = oracle.plm(m, kmax, t)
+            ks = np.arange(m, kmax + 1)
+            ref = np.array([sps.assoc_legendre_p(int(kk), m, t, norm=True) for kk in ks]).ravel()
+            np.testing.assert_allclose(v, (-1) ** m * ref, rtol=0, atol=1e-13)
+
+
+def _mp_pbar(k, m, t):
+    """Independent high-precision Pbar_k^m(t) from the explicit expansion
+    d^m P_k/dx^m = 2^-k sum_j (-1)^j C(k,j) C(2k-2j,k) (k-2j)!/(k-2j-m)! x^(k-2j-m)
+    (Rodrigues' formula differentiated term by term), exact integer
+    coefficients, evaluated with enough digits to absorb the cancellation;
+    Pbar_k^m = sqrt((2k+1)/2 (k-m)!/(k+m)!) (1-x^2)^(m/2) d^m P_k/dx^m
+    (no Condon-Shortley phase)."""
+    k = int(k)
+    m = int(m)
+    mpmath.mp.dps = int(0.7 * k) + 400
+    x = mpmath.mpf(t)
+    acc = mpmath.mpf(0)
+    for j in range(0, (k - m) // 2 + 1):
+        c = math.comb(k, j) * math.comb(2 * k - 2 * j, k) * math.factorial(k - 2 * j) // math.factorial(k - 2 * j - m)
+        term = mpmath.mpf(c) * x ** (k - 2 * j - m)
+        acc += -term if j % 2 else term
+    acc /= mpmath.mpf(2) ** k
+    norm = mpmath.sqrt((2 * k + 1) / mpmath.mpf(2) * mpmath.factorial(k - m) / mpmath.factorial(k + m))
+    val = norm * (1 - x * x) ** (mpmath.mpf(m) / 2) * acc
+    mpmath.mp.dps = 30
+    return val
+
+
+@pytest.mark.parametrize("k,m,t", [
+    (1023, 700, 0.3), (1023, 700, 0.9), (1023, 1, 0.5), (1023, 511, 0.999),
+    (1023, 1000, 0.2), (2047, 1500, 0.6), (2047, 900, 0.995), (600, 599, 0.01),
+])
+def test_plm_large_degree_vs_mpmath(k, m, t):
+    """Large degrees and orders, including values far below 1 (the regime where a
+    binary64 recurrence started at Pbar_m^m would underflow)."""
+    ref = _mp_pbar(k, m, t)
+    v = oracle.plm(m, k, t)[k - m]
+    rf = float(ref)
+    if abs(ref) < mpmath.mpf("1e-300"):
+        assert abs(v) < 1e-290
+    else:
+        assert abs(v - rf) <= 1e-12 * max(abs(rf), 1e-30), (v, rf)
+
+
+@pytest.mark.parametrize("k", [3, 64, 127, 1023, 4095, 8191])
+def test_addition_identity(k):
+    """Pbar_k^0(x)^2 + 2 sum_{m=1}^k Pbar_k^m(x)^2 = (2k+1)/2 (spherical harmonic
+    addition theorem at coincident points).  Pins every order up to k,
+    including the large-m values that start far below the binary64 range."""
+    for t in [0.0123, -0.45, 0.8, 0.99991]:
+        tot = np.longdouble(0)
+        for m in range(k + 1):
+            v = np.longdouble(oracle.plm(m, k, t)[k - m])
+            tot += v * v * (1 if m == 0 else 2)
+        assert abs(float(tot) - (2 * k + 1) / 2) <= 5e-15 * (2 * k + 1), (k, t, float(tot))
+
+
+def test_parity_symmetry():
+    """Pbar_k^m(-x) = (-1)^(k+m) Pbar_k^m(x) (Section 3.1.2)."""
+    for m in [0, 1, 6, 33]:
+        for t in [0.11, 0.5, 0.93]:
+            a = oracle.plm(m, 120, t)
+            b = oracle.plm(m, 120, -t)
+            k = np.arange(m, 121)
+            np.testing.assert_allclose(b, (-1.0) ** (k + m) * a, rtol=0, atol=1e-15 * np.abs(a).max())
+
+
+# ---------------------------------------------------------------- ALT
+def _alt_matrix(N, m, x):
+    """Dense 2N x (2N-|m|) ALT matrix from the oracle's plm (Section 3.1.1)."""
+    a = abs(m)
+    return np.array([oracle.plm(a, 2 * N - 1, t) for t in x])
+
+
+@pytest.mark.parametrize("N", [4, 16, 40])
+def test_discrete_orthonormality(N):
+    """A_m^T W A_m = I for every order (Section 3.1.1: GL exactness plus
+    orthonormality gives B = A^T W)."""
+    x, w = oracle.gauss_legendre(2 * N)
+    for a in range(2 * N):
+        A = _alt_matrix(N, a, x)
+        G = A.T @ (w[:, None] * A)
+        np.testing.assert_allclose(G, np.eye(2 * N - a), rtol=0, atol=2e-14 * math.sqrt(N))
+
+
+def test_alt_forward_single_mode_and_layout():
+    """beta = e_{k0,m0} gives g(m0, theta_l) = Pbar_{k0}^{|m0|}(x_l) in column
+    m0 mod M and zeros elsewhere; slot positions come from the shared layout."""
+    N = 6
+    M = 4 * N - 1
+    x, _ = oracle.gauss_legendre(2 * N)
+    for (k0, m0) in [(0, 0), (5, 3), (5, -3), (11, -11), (11, 11), (7, 0)]:
+        beta = np.zeros(4 * N * N, complex)
+        beta[inputs.slot(N, k0, m0)] = 1.0 - 2.0j
+        g = oracle.alt_forward(N, beta)
+        col = m0 % M
+        ref = np.array([oracle.plm(abs(m0), k0, t)[k0 - abs(m0)] for t in x]) * (1.0 - 2.0j)
+        np.testing.assert_allclose(g[:, col], ref, rtol=0, atol=1e-15)
+        g[:, col] = 0
+        assert np.all(g == 0)
+
+
+def test_coef_offsets_agree_with_enumeration():
+    for N in [1, 2, 5, 17]:
+        for m in range(-(2 * N - 1), 2 * N):
+            assert oracle.coef_offset(N, m) == inputs.slot(N, abs(m), m)
+
+
+def test_alt_orders_match_grid():
+    N = 8
+    M = 4 * N - 1
+    beta = inputs.make_beta(N, 1, 91)[0]
+    g = oracle.alt_forward(N, beta)
+    absm = [0, 1, 5, 15]
+    o = oracle.alt_forward_orders(N, beta, absm)
+    for i, a in enumerate(absm):
+        np.testing.assert_array_equal(o[i, 0], g[:, a % M])
+        np.testing.assert_array_equal(o[i, 1], g[:, (-a) % M])
+    gin = np.random.default_rng(3).standard_normal((len(absm), 2, 2 * N)) * (1 + 0.5j)
+    bt = oracle.alt_transpose_orders(N, gin, absm, weights=True)
+    x, w = oracle.gauss_legendre(2 * N)
+    for i, a in enumerate(absm):
+        A = _alt_matrix(N, a, x)
+        for s in range(2):
+            ref = A.T @ (w * gin[i, s])
+            np.testing.assert_allclose(bt[i, s, : 2 * N - a], ref, rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------- phi DFT
+@pytest.mark.parametrize("N", [1, 3, 16, 64])
+def test_dft_synthesis_vs_numpy_fft(N):
+    """f[j] = sum_m g[m mod M] e^{i m phi_j}: a pre-twiddle e^{i pi m / M} with the
+    signed order, then M * numpy.fft.ifft (Section 1, phi_j formula)."""
+    M = 4 * N - 1
+    rng = np.random.default_rng(N)
+    g = rng.standard_normal((2 * N, M)) + 1j * rng.standard_normal((2 * N, M))
+    f = oracle.dft_synthesis(N, g)
+    c = np.arange(M)
+    msigned = np.where(c <= 2 * N - 1, c, c - M)
+    h = g * np.exp(1j * np.pi * msigned / M)[None, :]
+    ref = M * np.fft.ifft(h, axis=1)
+    np.testing.assert_allclose(f, ref, rtol=0, atol=1e-13 * M)
+    ga = oracle.dft_analysis(N, f)
+    np.testing.assert_allclose(ga, g, rtol=0, atol=1e-14 * M)
+    rows = [0, 2 * N - 1]
+    np.testing.assert_array_equal(oracle.dft_synthesis(N, g, rows=rows), f[rows])
+
+
+# ---------------------------------------------------------------- SHT
+@pytest.mark.parametrize("N", [2, 8, 24])
+def test_round_trip_and_parseval(N):
+    M = 4 * N - 1
+    beta = inputs.make_beta(N, 1, 77)[0]
+    f = oracle.sht_forward(N, beta)
+    back = oracle.sht_inverse(N, f)
+    np.testing.assert_allclose(back, beta, rtol=0, atol=1e-14 * math.sqrt(N))
+    _, w = oracle.gauss_legendre(2 * N)
+    lhs = float(np.sum(w[:, None] * np.abs(f) ** 2))
+    rhs = M * float(np.sum(np.abs(beta) ** 2))
+    assert abs(lhs - rhs) <= 1e-13 * rhs
+
+
+def test_single_mode_sht():
+    """beta = e_{k0,m0}  =>  f(theta_l, phi_j) = Pbar_{k0}^{|m0|}(x_l) e^{i m0 phi_j}."""
+    N = 5
+    M = 4 * N - 1
+    x, _ = oracle.gauss_legendre(2 * N)
+    phi = 2 * np.pi * (np.arange(M) + 0.5) / M
+    for (k0, m0) in [(3, -2), (9, 9), (9, -9), (4, 0)]:
+        beta = np.zeros(4 * N * N, complex)
+        beta[inputs.slot(N, k0, m0)] = 1.0
+        f = oracle.sht_forward(N, beta)
+        p = np.array([oracle.plm(abs(m0), k0, t)[k0 - abs(m0)] for t in x])
+        # numpy evaluates e^{i m0 phi_j} with phase error ~ |m0 phi| * 1e-16
+        np.testing.assert_allclose(f, p[:, None] * np.exp(1j * m0 * phi)[None, :], rtol=0, atol=4e-14)
+
+
+def test_brute_force_integration_tiny():
+    """N = 2 (degrees <= 3, M = 7): a band-limited f written in closed form;
+    beta_{k,m} = (1/2pi) int int f Pbar_k^{|m|} e^{-i m phi} by mpmath
+    quadrature with mpmath's own Ferrers functions (independent of the GL
+    rule and of the oracle's recurrence)."""
+    N = 2
+    M = 4 * N - 1
+    mpmath.mp.dps = 30
+    # x-parts of the e^{i m phi} components, degree <= 2N-1 = 3
+    parts = {
+        1: lambda t: mpmath.sqrt(1 - t * t) * t * t,
+        0: lambda t: 3 * t ** 3 - t + mpmath.mpf("0.25"),
+        -2: lambda t: (1 - t * t) * (mpmath.mpf("0.5") - 2j * t),
+    }
+    beta_ref = np.zeros(4 * N * N, complex)
+    for m, fm in parts.items():
+        for k in range(abs(m), 2 * N):
+            val = mpmath.quad(lambda t: fm(t) * _mp_pbar(k, abs(m), t), [-1, 1])
+            beta_ref[inputs.slot(N, k, m)] = complex(val)
+    x, _ = oracle.gauss_legendre(2 * N)
+    phi = 2 * np.pi * (np.arange(M) + 0.5) / M
+    f = np.zeros((2 * N, M), complex)
+    for m, fm in parts.items():
+        col = np.array([complex(fm(mpmath.mpf(t))) for t in x])
+        f += col[:, None] * np.exp(1j * m * phi)[None, :]
+    np.testing.assert_allclose(oracle.sht_inverse(N, f), beta_ref, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(oracle.sht_forward(N, beta_ref), f, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("N", [3, 10])
+def test_adjoint_dot_product(N):
+    """<S beta, y> = <beta, S^H y>: sht_adjoint is the conjugate transpose."""
+    rng = np.random.default_rng(5)
+    beta = inputs.make_beta(N, 1, 12)[0]
+    y = rng.standard_normal((2 * N, 4 * N - 1)) + 1j * rng.standard_normal((2 * N, 4 * N - 1))
+    lhs = np.vdot(y, oracle.sht_forward(N, beta))
+    rhs = np.vdot(oracle.sht_adjoint(N, y), beta)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_weighted_energy_gradient_closed_form():
+    """L = sum_{l,j} w_l |f|^2 = M ||beta||^2, so the (conjugate) gradient
+    2 S^H W S beta equals 2 M beta exactly."""
+    N = 6
+    M = 4 * N - 1
+    beta = inputs.make_beta(N, 1, 5000)[0]
+    _, w = oracle.gauss_legendre(2 * N)
+    f = oracle.sht_forward(N, beta)
+    grad = oracle.sht_adjoint(N, 2 * w[:, None] * f)
+    np.testing.assert_allclose(grad, 2 * M * beta, rtol=0, atol=1e-12)
