@@ -1,0 +1,195 @@
+/*
+ * sht.h -- C-ABI of the MI355X (gfx950) spherical harmonic transform library.
+ *
+ * The library applies the spherical harmonic transform (SHT) of degree N
+ * described in Bremer, Chen & Yang, "Rapid application of the spherical
+ * harmonic transform via interpolative decomposition butterfly
+ * factorization" (arXiv 2004.11346):
+ *
+ *   f(theta, phi) = sum_{k=0}^{2N-1} sum_{m=-k}^{k} beta_{k,m} Pbar_k^{|m|}(cos theta) e^{i m phi}
+ *
+ * (Section 1, the expansion of f), evaluated on the tensor grid of the 2N
+ * Gauss-Legendre nodes in x = cos(theta) and the M = 4N-1 equispaced
+ * phi_j = 2 pi (j + 1/2) / M (Section 1, grid definition).  The associated
+ * Legendre transform (ALT) g(m, theta_l) = sum_k beta_{k,m} Pbar_k^{|m|}(x_l)
+ * (Section 1; Section 3.1.1) is applied either densely (the plain O(N^3)
+ * form, Legendre values regenerated on the fly) or through the hierarchically
+ * partitioned interpolative decomposition butterfly factorization (IDBF) of
+ * Section 3.2-3.3; the phi sums are length-M DFTs.
+ *
+ * Conventions
+ *   Pbar_k^m   L2-normalised on [-1, 1], no Condon-Shortley phase.
+ *   beta       device buffer, complex, interleaved (re, im), element type
+ *              double (SHT_F64) or float (SHT_F32); shape [batch][4 N^2];
+ *              m-major: orders in the sequence 0, 1, -1, 2, -2, ...,
+ *              2N-1, -(2N-1); inside an order the degrees k = |m| .. 2N-1.
+ *   f          device buffer, complex interleaved, shape [batch][2N][M];
+ *              row l = l-th Gauss-Legendre node in ascending x (Section 1),
+ *              column j = phi_j.
+ *   g          (ALT-only calls) same shape as f, order m stored in column
+ *              (m mod M).
+ *   stream     a hipStream_t passed as void*; NULL is the default stream.
+ *              Every call only enqueues work on that stream (asynchronous);
+ *              the caller owns all buffers and must keep them alive until
+ *              the work has completed.
+ *
+ * Ownership: a plan owns every device array it allocates (factor streams,
+ * tables, workspace).  A plan is immutable after creation; calls that use the
+ * same plan on different streams at the same time race on its workspace and
+ * must be serialised by the caller.
+ *
+ * Errors: every int-returning call returns SHT_OK (0) or a negative SHT_ERR_*
+ * code; no exception crosses the ABI.  Kernels never abort: NaN and Inf in the
+ * inputs propagate to the outputs.  sht_strerror() gives a message, and
+ * sht_last_error_detail() the last detailed message of the calling thread.
+ */
+#ifndef SHT_H_
+#define SHT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- codes ------------------------------------------------------------- */
+#define SHT_OK 0
+#define SHT_ERR_INVALID_ARG (-1)  /* bad N, batch, range, NULL pointer, ... */
+#define SHT_ERR_UNSUPPORTED (-2)  /* dtype/method/size combination not built */
+#define SHT_ERR_OOM (-3)          /* host or device allocation failed */
+#define SHT_ERR_HIP (-4)          /* a HIP runtime call failed (detail kept) */
+#define SHT_ERR_PLAN (-5)         /* plan construction failed numerically */
+#define SHT_ERR_MISALIGNED (-6)   /* buffer not aligned to its element size */
+
+/* element types of beta / f / g */
+#define SHT_F64 0
+#define SHT_F32 1
+
+/* ALT methods */
+#define SHT_DENSE 0 /* plain form: dense per-order product, Pbar regenerated */
+#define SHT_IDBF 1  /* fast form: partitioned IDBF / low-rank / dense blocks */
+
+/* directions for sht_alt_apply */
+#define SHT_FWD 0 /* beta -> g:  g(m, theta_l) = sum_k beta_{k,m} Pbar_k^{|m|}(x_l) */
+#define SHT_INV 1 /* g -> beta:  beta = A_m^T W g  (Section 3.1.1, B = A^T W) */
+#define SHT_ADJ 2 /* g -> beta:  beta = A_m^T g    (transpose, no weights) */
+
+/* F32 arithmetic for the IDBF block products */
+#define SHT_F32_VALU 0       /* FP32 products on the vector ALUs */
+#define SHT_F32_SPLIT_BF16 1 /* split-BF16 three-product MFMA, FP32 accumulate */
+
+/* ID row sampling (Section 2.1) */
+#define SHT_SAMPLE_MOCK_CHEB 0
+#define SHT_SAMPLE_RANDOM 1
+
+typedef struct sht_plan sht_plan_t;
+
+/* Plan-construction parameters (Section 2.1, 2.3, 3.2 and Section 5).  Call
+ * sht_plan_opts_default() and change fields; a NULL opts means defaults. */
+typedef struct sht_plan_opts {
+    double eps;        /* ID / low-rank tolerance, relative to the block's
+                          largest entry (paper: 1e-10; default 1e-12) */
+    int n0;            /* partition: split turning-point blocks while
+                          max(rows, cols) > n0 (paper: 512; default 256) */
+    int leaf;          /* IDBF leaf size (default 32) */
+    int rk;            /* adaptive rank cap r_k of each ID (paper: 150) */
+    int oversample;    /* ID row oversampling t (default 2) */
+    int rsvd_r;        /* randomized-SVD rank r (paper: 30) */
+    int rsvd_q;        /* randomized-SVD oversampling q (paper: 2) */
+    int sampling;      /* SHT_SAMPLE_MOCK_CHEB or SHT_SAMPLE_RANDOM */
+    uint64_t seed;     /* seed of every random choice of the plan */
+    int threads;       /* host threads for plan construction (0 = all) */
+    int f32_mode;      /* SHT_F32_VALU or SHT_F32_SPLIT_BF16 (F32 plans) */
+    int min_idbf;      /* smallest block side given an IDBF (default 4*leaf) */
+} sht_plan_opts;
+
+void sht_plan_opts_default(sht_plan_opts *opts);
+
+/* Build a plan for degree N (2N latitudes, 4N-1 longitudes) and `batch`
+ * fields on the current HIP device.  dtype: SHT_F64 or SHT_F32; method:
+ * SHT_DENSE or SHT_IDBF.  Nodes, weights, Legendre tables and every
+ * factorisation are computed on the host in FP64 (Section 3), then uploaded
+ * once.  N >= 1, batch >= 1.  On success *out owns the plan; release it with
+ * sht_plan_destroy().  Errors: INVALID_ARG, UNSUPPORTED, OOM, HIP, PLAN. */
+int sht_plan_create(int N, int batch, int dtype, int method,
+                    const sht_plan_opts *opts, sht_plan_t **out);
+
+void sht_plan_destroy(sht_plan_t *plan);
+
+/* Forward SHT (Section 1): beta [batch][4N^2] -> f [batch][2N][M].
+ * ALT for every order, parity split (Section 3.1.2), then the phi synthesis
+ * f(theta_l, phi_j) = sum_m g(m, theta_l) e^{i m phi_j}.  `f` may not alias
+ * `beta`. */
+int sht_forward(const sht_plan_t *plan, const void *beta, void *f, void *stream);
+
+/* Inverse SHT (Section 1; Section 3.1.1): f -> beta with
+ * g = (1/M) sum_j f e^{-i m phi_j} and beta = A_m^T W g.  Exact left inverse
+ * of sht_forward.  `f` is not modified. */
+int sht_inverse(const sht_plan_t *plan, const void *f, void *beta, void *stream);
+
+/* Adjoint of sht_forward (conjugate transpose; the transposed butterfly and
+ * DFT of Section 3.1.1): grad_beta = S^H grad_f, i.e. the inverse without the
+ * 1/M and without the weights.  This is the vector-Jacobian product in
+ * PyTorch's complex convention. */
+int sht_backward(const sht_plan_t *plan, const void *grad_f, void *grad_beta, void *stream);
+
+/* ALT only, for the orders with m_lo <= |m| <= m_hi (both signs), no DFT
+ * (Section 1, ALT; Section 3.1.1).
+ *   dir = SHT_FWD: in = beta [batch][4N^2], out = g [batch][2N][M]; only the
+ *                  columns of the selected orders are written.
+ *   dir = SHT_INV / SHT_ADJ: in = g [batch][2N][M], out = beta; only the
+ *                  slots of the selected orders are written.
+ * 0 <= m_lo <= m_hi <= 2N-1.  This is the per-GPU share when the orders are
+ * distributed over several GPUs. */
+int sht_alt_apply(const sht_plan_t *plan, int m_lo, int m_hi, int dir,
+                  const void *in, void *out, void *stream);
+
+/* Plan statistics as JSON (block counts by type, ranks, stored entries,
+ * bytes, build time).  Writes at most `cap` bytes including the NUL; returns
+ * the full length needed (>= 0) or a negative error. */
+int sht_plan_stats(const sht_plan_t *plan, char *json, size_t cap);
+
+/* Sizes of the plan. */
+int sht_plan_info(const sht_plan_t *plan, int *N, int *batch, int *dtype, int *method);
+
+/* Gauss-Legendre nodes (ascending) and weights of the plan, copied to host
+ * arrays of 2N doubles. */
+int sht_plan_nodes(const sht_plan_t *plan, double *x, double *w);
+
+const char *sht_strerror(int code);
+const char *sht_last_error_detail(void);
+
+/* ---- plan verification on the host (no GPU needed) --------------------
+ * These calls build the same FP64 plan as sht_plan_create without touching
+ * a device, and apply it with a plain host loop over the packed factor
+ * stream in the order the kernels use.  They exist so that the plan builder
+ * can be checked on a machine without a GPU; the transform entry points
+ * above never call them. */
+typedef struct sht_host_plan sht_host_plan_t;
+
+int sht_host_plan_create(int N, int method, const sht_plan_opts *opts, sht_host_plan_t **out);
+void sht_host_plan_destroy(sht_host_plan_t *hp);
+
+/* Apply the packed ALT program of order |m| and parity (0 even: k-|m| even,
+ * 1 odd) to R real right-hand sides.  dir = SHT_FWD: in [cols][R] ->
+ * out [N][R] (half-grid rows, row r = node 2N-1-r, i.e. theta ascending);
+ * dir = SHT_ADJ: in [N][R] -> out [cols][R].  cols = N - ceil(|m|/2) (odd)
+ * or N - floor(|m|/2) (even), Section 3.1.2. */
+int sht_host_plan_apply(const sht_host_plan_t *hp, int absm, int parity, int dir,
+                        int R, const double *in, double *out);
+
+/* Dense half-grid matrix of (|m|, parity) from the plan builder's own
+ * Legendre recurrence: out [N][cols] row-major. */
+int sht_host_alt_matrix(const sht_host_plan_t *hp, int absm, int parity, double *out);
+
+int sht_host_plan_stats(const sht_host_plan_t *hp, char *json, size_t cap);
+
+/* The library's own 2N-point Gauss-Legendre rule (ascending). */
+int sht_host_gauss_legendre(int n, double *x, double *w);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHT_H_ */

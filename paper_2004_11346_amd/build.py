@@ -1,0 +1,103 @@
+"""Build the native library ``libsht.so`` in-tree with hipcc for gfx950.
+
+Usage: ``python -m paper_2004_11346_amd.build [--jobs J] [--debug]``.
+Every HIP source is compiled with packed FP32 instructions disabled
+(``-Xclang -target-feature -Xclang -packed-fp32-ops``).
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INC = os.path.join(ROOT, "include")
+OUT = os.path.join(PKG, "libsht.so")
+BUILD = os.path.join(PKG, "_build")
+
+ARCH = "gfx950"
+
+
+def sources():
+    skip = {"idbf_stub.cpp", "host_plan_stub.cpp"}
+    have = set(os.listdir(CSRC))
+    out = []
+    for f in sorted(have):
+        if f.endswith((".hip", ".cpp")):
+            if f in skip:
+                # stubs are only used while the real module is absent
+                real = {"idbf_stub.cpp": "idbf_plan.cpp", "host_plan_stub.cpp": "host_plan.cpp"}[f]
+                if real in have:
+                    continue
+            out.append(os.path.join(CSRC, f))
+    return out
+
+
+def hipcc():
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def compile_one(src: str, debug: bool) -> str:
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if os.path.exists(obj) and os.path.getmtime(obj) >= max(
+        os.path.getmtime(src),
+        *[os.path.getmtime(os.path.join(CSRC, h)) for h in os.listdir(CSRC) if h.endswith(".h")],
+        os.path.getmtime(os.path.join(INC, "sht.h")),
+    ):
+        return obj
+    flags = [
+        "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        "-I", INC, "-I", CSRC, "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+        "-Wno-unused-command-line-argument",
+    ]
+    flags += ["-O1", "-g"] if debug else ["-O3"]
+    if src.endswith(".hip"):
+        cmd = [hipcc(), "-x", "hip", "-c", src, "-o", obj] + flags
+    else:
+        cmd = [hipcc(), "-c", src, "-o", obj, "-pthread"] + flags
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError(f"compile failed: {os.path.basename(src)}")
+    warn = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip())
+    if warn.strip():
+        sys.stderr.write(warn + "\n")
+    return obj
+
+
+def build(jobs: int | None = None, debug: bool = False, force: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    if force:
+        for f in os.listdir(BUILD):
+            if f.endswith(".o"):
+                os.remove(os.path.join(BUILD, f))
+    srcs = sources()
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda s: compile_one(s, debug), srcs))
+    tmp = OUT + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-pthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("link failed")
+    os.replace(tmp, OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--debug", action="store_true")
+    ap.add_argument("--force", action="store_true")
+    a = ap.parse_args()
+    print(build(a.jobs, a.debug, a.force))

@@ -1,0 +1,359 @@
+// C-ABI entry points (include/sht.h): plan construction, upload and the
+// forward / inverse / adjoint / ALT-only calls.  Every transform call only
+// enqueues HIP kernels on the caller's stream; nothing here computes a
+// transform on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "idbf.h"
+#include "kernels.h"
+#include "sht_internal.h"
+
+namespace sht {
+
+static thread_local std::string g_detail;
+void set_error_detail(const std::string &msg) { g_detail = msg; }
+
+}  // namespace sht
+
+using namespace sht;
+
+struct sht_plan {
+    int N = 0, M = 0, batch = 0, dtype = 0, method = 0, device = 0;
+    sht_plan_opts opts{};
+    std::vector<double> x, w;  // full rule, ascending
+    // device tables
+    double *d_xh = nullptr, *d_wh = nullptr, *d_dmant = nullptr, *d_coef = nullptr;
+    int *d_dexp = nullptr;
+    double *d_tw2 = nullptr;
+    float *d_tw2f = nullptr;
+    dev::DenseTables dense;
+    dev::DftPlan dft;
+    // workspace
+    void *d_g = nullptr;         // [batch][2N][M] complex (dtype)
+    double *d_hbuf = nullptr;    // dense transposed-ALT fold buffer
+    double *d_part = nullptr;    // dense transposed-ALT chunk partials
+    // IDBF program (device)
+    idbf::DeviceProgram prog;
+    std::string stats;
+    double build_seconds = 0.0;
+    ~sht_plan();
+};
+
+static void dfree(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+sht_plan::~sht_plan() {
+    dfree(d_xh);
+    dfree(d_wh);
+    dfree(d_dmant);
+    dfree(d_coef);
+    dfree(d_dexp);
+    dfree(d_tw2);
+    dfree(d_tw2f);
+    dfree(d_g);
+    dfree(d_hbuf);
+    dfree(d_part);
+    prog.release();
+}
+
+namespace {
+
+int hip_fail(hipError_t e, const char *what) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    set_error_detail(buf);
+    return e == hipErrorOutOfMemory ? SHT_ERR_OOM : SHT_ERR_HIP;
+}
+
+#define HIP_TRY(expr, what)                       \
+    do {                                          \
+        hipError_t _e = (expr);                   \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+template <typename V>
+int upload(const std::vector<V> &h, V **d, const char *what) {
+    HIP_TRY(hipMalloc((void **)d, std::max<size_t>(1, h.size() * sizeof(V))), what);
+    if (!h.empty()) HIP_TRY(hipMemcpy(*d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice), what);
+    return SHT_OK;
+}
+
+std::vector<int> prime_factors(int M) {
+    std::vector<int> f;
+    for (int p = 2; (long long)p * p <= M; ++p)
+        while (M % p == 0) {
+            f.push_back(p);
+            M /= p;
+        }
+    if (M > 1) f.push_back(M);
+    std::sort(f.rbegin(), f.rend());
+    return f;
+}
+
+int check_ptr(const void *p, size_t align) {
+    if (!p) {
+        set_error_detail("null buffer");
+        return SHT_ERR_INVALID_ARG;
+    }
+    if (reinterpret_cast<uintptr_t>(p) % align) {
+        set_error_detail("buffer not aligned to its element size");
+        return SHT_ERR_MISALIGNED;
+    }
+    return SHT_OK;
+}
+
+size_t elt_size(int dtype) { return dtype == SHT_F64 ? 8 : 4; }
+
+}  // namespace
+
+extern "C" {
+
+void sht_plan_opts_default(sht_plan_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->eps = 1e-12;
+    o->n0 = 256;
+    o->leaf = 32;
+    o->rk = 150;
+    o->oversample = 2;
+    o->rsvd_r = 30;
+    o->rsvd_q = 2;
+    o->sampling = SHT_SAMPLE_MOCK_CHEB;
+    o->seed = 20200423ULL;
+    o->threads = 0;
+    o->f32_mode = SHT_F32_VALU;
+    o->min_idbf = 0;
+}
+
+const char *sht_strerror(int code) {
+    switch (code) {
+        case SHT_OK: return "ok";
+        case SHT_ERR_INVALID_ARG: return "invalid argument";
+        case SHT_ERR_UNSUPPORTED: return "unsupported configuration";
+        case SHT_ERR_OOM: return "out of memory";
+        case SHT_ERR_HIP: return "HIP runtime error";
+        case SHT_ERR_PLAN: return "plan construction failed";
+        case SHT_ERR_MISALIGNED: return "misaligned buffer";
+        default: return "unknown error";
+    }
+}
+
+const char *sht_last_error_detail(void) { return g_detail.c_str(); }
+
+int sht_host_gauss_legendre(int n, double *x, double *w) {
+    if (n < 1 || !x || !w) return SHT_ERR_INVALID_ARG;
+    gauss_legendre(n, x, w);
+    return SHT_OK;
+}
+
+int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts *opts,
+                    sht_plan_t **out) {
+    if (!out) return SHT_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (N < 1 || N > 8192 || batch < 1 || batch > 4096) {
+        set_error_detail("N must be in [1, 8192] and batch in [1, 4096]");
+        return SHT_ERR_INVALID_ARG;
+    }
+    if (dtype != SHT_F64 && dtype != SHT_F32) return SHT_ERR_UNSUPPORTED;
+    if (method != SHT_DENSE && method != SHT_IDBF) return SHT_ERR_UNSUPPORTED;
+    auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<sht_plan> p(new (std::nothrow) sht_plan);
+    if (!p) return SHT_ERR_OOM;
+    p->N = N;
+    p->M = 4 * N - 1;
+    p->batch = batch;
+    p->dtype = dtype;
+    p->method = method;
+    sht_plan_opts_default(&p->opts);
+    if (opts) p->opts = *opts;
+    HIP_TRY(hipGetDevice(&p->device), "hipGetDevice");
+    if (!dev::dft_supported(p->M, dtype)) {
+        set_error_detail("phi DFT row does not fit in LDS for this N and dtype");
+        return SHT_ERR_UNSUPPORTED;
+    }
+    if (method == SHT_DENSE && 4 * batch > 128) {
+        set_error_detail("dense transposed ALT supports at most 32 fields per call");
+        return SHT_ERR_UNSUPPORTED;
+    }
+
+    LegendreTables lt;
+    try {
+        build_legendre_tables(N, lt);
+    } catch (const std::bad_alloc &) {
+        return SHT_ERR_OOM;
+    }
+    p->x.resize(2 * N);
+    p->w.resize(2 * N);
+    gauss_legendre(2 * N, p->x.data(), p->w.data());
+
+    int rc;
+    if ((rc = upload(lt.xh, &p->d_xh, "upload nodes"))) return rc;
+    if ((rc = upload(lt.wh, &p->d_wh, "upload weights"))) return rc;
+    if ((rc = upload(lt.diag_m, &p->d_dmant, "upload diag"))) return rc;
+    if ((rc = upload(lt.diag_e, &p->d_dexp, "upload diag exponents"))) return rc;
+    if ((rc = upload(lt.coef, &p->d_coef, "upload recurrence coefficients"))) return rc;
+    p->dense.N = N;
+    p->dense.M = p->M;
+    p->dense.xh = p->d_xh;
+    p->dense.wh = p->d_wh;
+    p->dense.dmant = p->d_dmant;
+    p->dense.dexp = p->d_dexp;
+    p->dense.coef = p->d_coef;
+
+    // phi DFT: radices and the e^{i pi r / M} table (long double, rounded)
+    {
+        std::vector<int> f = prime_factors(p->M);
+        p->dft.N = N;
+        p->dft.M = p->M;
+        p->dft.nrad = (int)f.size();
+        for (size_t i = 0; i < f.size(); ++i) p->dft.radix[i] = f[i];
+        std::vector<double> tw(4 * (size_t)p->M);
+        std::vector<float> twf(4 * (size_t)p->M);
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (int r = 0; r < 2 * p->M; ++r) {
+            long double ph = pi * r / p->M;
+            tw[2 * r] = (double)cosl(ph);
+            tw[2 * r + 1] = (double)sinl(ph);
+            twf[2 * r] = (float)cosl(ph);
+            twf[2 * r + 1] = (float)sinl(ph);
+        }
+        if ((rc = upload(tw, &p->d_tw2, "upload twiddles"))) return rc;
+        if ((rc = upload(twf, &p->d_tw2f, "upload twiddles"))) return rc;
+        p->dft.tw2 = p->d_tw2;
+        p->dft.tw2f = p->d_tw2f;
+    }
+
+    // workspace
+    const size_t gbytes = 2 * elt_size(dtype) * (size_t)batch * 2 * N * p->M;
+    HIP_TRY(hipMalloc(&p->d_g, gbytes), "workspace g");
+    if (method == SHT_DENSE) {
+        const size_t hb = sizeof(double) * (size_t)2 * N * 2 * N * 4 * batch;
+        HIP_TRY(hipMalloc((void **)&p->d_hbuf, hb), "workspace fold");
+        size_t pb = dev::dense_part_bytes(N, batch);
+        if (pb) HIP_TRY(hipMalloc((void **)&p->d_part, pb), "workspace partials");
+    } else {
+        idbf::HostProgram hp;
+        int brc = idbf::build_program(N, lt, p->opts, hp);
+        if (brc) return brc;
+        brc = idbf::upload_program(hp, dtype, batch, p->opts, p->prog);
+        if (brc) return brc;
+        p->stats = hp.stats_json;
+    }
+    p->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    HIP_TRY(hipDeviceSynchronize(), "plan upload");
+    *out = p.release();
+    return SHT_OK;
+}
+
+void sht_plan_destroy(sht_plan_t *plan) { delete plan; }
+
+int sht_plan_info(const sht_plan_t *p, int *N, int *batch, int *dtype, int *method) {
+    if (!p) return SHT_ERR_INVALID_ARG;
+    if (N) *N = p->N;
+    if (batch) *batch = p->batch;
+    if (dtype) *dtype = p->dtype;
+    if (method) *method = p->method;
+    return SHT_OK;
+}
+
+int sht_plan_nodes(const sht_plan_t *p, double *x, double *w) {
+    if (!p || !x || !w) return SHT_ERR_INVALID_ARG;
+    std::copy(p->x.begin(), p->x.end(), x);
+    std::copy(p->w.begin(), p->w.end(), w);
+    return SHT_OK;
+}
+
+int sht_plan_stats(const sht_plan_t *p, char *json, size_t cap) {
+    if (!p) return SHT_ERR_INVALID_ARG;
+    std::ostringstream os;
+    os << "{\"N\":" << p->N << ",\"batch\":" << p->batch << ",\"dtype\":\""
+       << (p->dtype == SHT_F64 ? "f64" : "f32") << "\",\"method\":\""
+       << (p->method == SHT_DENSE ? "dense" : "idbf") << "\",\"build_seconds\":" << p->build_seconds;
+    if (p->method == SHT_IDBF && !p->stats.empty()) os << ",\"program\":" << p->stats;
+    os << "}";
+    std::string s = os.str();
+    if (json && cap) {
+        size_t n = std::min(cap - 1, s.size());
+        std::memcpy(json, s.data(), n);
+        json[n] = 0;
+    }
+    return (int)s.size() + 1;
+}
+
+static int run_alt(const sht_plan_t *p, int a_lo, int a_hi, int dir, const void *in, void *out,
+                   hipStream_t s) {
+    hipError_t e;
+    if (p->method == SHT_DENSE) {
+        if (dir == SHT_FWD)
+            e = dev::alt_dense_forward(p->dense, p->dtype, p->batch, a_lo, a_hi, in, out, s);
+        else
+            e = dev::alt_dense_transpose(p->dense, p->dtype, p->batch, a_lo, a_hi, dir == SHT_INV, in, out,
+                                         p->d_hbuf, p->d_part, s);
+    } else {
+        e = idbf::run(p->prog, p->dense, p->dtype, p->batch, a_lo, a_hi, dir, in, out, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "ALT launch");
+    return SHT_OK;
+}
+
+int sht_alt_apply(const sht_plan_t *p, int m_lo, int m_hi, int dir, const void *in, void *out,
+                  void *stream) {
+    if (!p) return SHT_ERR_INVALID_ARG;
+    if (m_lo < 0 || m_hi < m_lo || m_hi > 2 * p->N - 1 || (dir != SHT_FWD && dir != SHT_INV && dir != SHT_ADJ)) {
+        set_error_detail("order range or direction out of bounds");
+        return SHT_ERR_INVALID_ARG;
+    }
+    int rc;
+    if ((rc = check_ptr(in, elt_size(p->dtype)))) return rc;
+    if ((rc = check_ptr(out, elt_size(p->dtype)))) return rc;
+    return run_alt(p, m_lo, m_hi, dir, in, out, (hipStream_t)stream);
+}
+
+int sht_forward(const sht_plan_t *p, const void *beta, void *f, void *stream) {
+    if (!p) return SHT_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_ptr(beta, elt_size(p->dtype)))) return rc;
+    if ((rc = check_ptr(f, elt_size(p->dtype)))) return rc;
+    if (beta == f) {
+        set_error_detail("f may not alias beta");
+        return SHT_ERR_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = run_alt(p, 0, 2 * p->N - 1, SHT_FWD, beta, f, s))) return rc;
+    hipError_t e = dev::dft_synthesis(p->dft, p->dtype, p->batch, f, s);
+    if (e != hipSuccess) return hip_fail(e, "DFT synthesis");
+    return SHT_OK;
+}
+
+static int transposed(const sht_plan_t *p, const void *f, void *beta, void *stream, bool inverse) {
+    if (!p) return SHT_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_ptr(beta, elt_size(p->dtype)))) return rc;
+    if ((rc = check_ptr(f, elt_size(p->dtype)))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = dev::dft_analysis(p->dft, p->dtype, p->batch, inverse ? 1.0 / p->M : 1.0, f, p->d_g, s);
+    if (e != hipSuccess) return hip_fail(e, "DFT analysis");
+    return run_alt(p, 0, 2 * p->N - 1, inverse ? SHT_INV : SHT_ADJ, p->d_g, beta, s);
+}
+
+int sht_inverse(const sht_plan_t *p, const void *f, void *beta, void *stream) {
+    return transposed(p, f, beta, stream, true);
+}
+
+int sht_backward(const sht_plan_t *p, const void *grad_f, void *grad_beta, void *stream) {
+    return transposed(p, grad_f, grad_beta, stream, false);
+}
+
+}  // extern "C"

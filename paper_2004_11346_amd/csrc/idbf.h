@@ -1,0 +1,38 @@
+// Fast form of the ALT: hierarchical block partitioning (Section 3.2) with an
+// interpolative decomposition butterfly factorization (IDBF, Section 2.2) of
+// every oscillatory block, a randomized-sampling low-rank factorization
+// (Section 2.3, Algorithm 1) of every non-oscillatory block and a trimmed
+// dense product for every block that contains turning points (Section 3.3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "sht.h"
+#include "sht_internal.h"
+
+namespace sht {
+namespace idbf {
+
+struct HostProgram {
+    int N = 0;
+    std::string stats_json;
+};
+
+struct DeviceProgram {
+    bool valid = false;
+    void release() {}
+};
+
+int build_program(int N, const LegendreTables &lt, const sht_plan_opts &opts, HostProgram &out);
+int upload_program(const HostProgram &hp, int dtype, int batch, const sht_plan_opts &opts,
+                   DeviceProgram &out);
+hipError_t run(const DeviceProgram &prog, const dev::DenseTables &t, int dtype, int batch, int a_lo,
+               int a_hi, int dir, const void *in, void *out, hipStream_t s);
+
+}  // namespace idbf
+}  // namespace sht

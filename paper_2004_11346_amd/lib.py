@@ -1,0 +1,126 @@
+"""ctypes binding of ``libsht.so`` (the C-ABI in ``include/sht.h``).
+
+Argument marshalling only.  The library is loaded from the package directory;
+if it is missing this module raises -- there is no fallback implementation.
+``torch`` is imported first so that the library binds to the same HIP runtime
+as torch (both are ``libamdhip64.so.7``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch  # noqa: F401  (must be loaded before libsht.so, see module doc)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsht.so")
+
+SHT_OK = 0
+SHT_F64, SHT_F32 = 0, 1
+SHT_DENSE, SHT_IDBF = 0, 1
+SHT_FWD, SHT_INV, SHT_ADJ = 0, 1, 2
+SHT_F32_VALU, SHT_F32_SPLIT_BF16 = 0, 1
+SHT_SAMPLE_MOCK_CHEB, SHT_SAMPLE_RANDOM = 0, 1
+
+EXPORTED = [
+    "sht_plan_opts_default", "sht_plan_create", "sht_plan_destroy", "sht_forward", "sht_inverse",
+    "sht_backward", "sht_alt_apply", "sht_plan_stats", "sht_plan_info", "sht_plan_nodes",
+    "sht_strerror", "sht_last_error_detail", "sht_host_plan_create", "sht_host_plan_destroy",
+    "sht_host_plan_apply", "sht_host_alt_matrix", "sht_host_plan_stats", "sht_host_gauss_legendre",
+]
+
+
+class ShtError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str):
+        super().__init__(f"{what}: {detail or 'error'} (code {code})")
+        self.code = code
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [
+        ("eps", ctypes.c_double),
+        ("n0", ctypes.c_int),
+        ("leaf", ctypes.c_int),
+        ("rk", ctypes.c_int),
+        ("oversample", ctypes.c_int),
+        ("rsvd_r", ctypes.c_int),
+        ("rsvd_q", ctypes.c_int),
+        ("sampling", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+        ("threads", ctypes.c_int),
+        ("f32_mode", ctypes.c_int),
+        ("min_idbf", ctypes.c_int),
+    ]
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"native library {LIB_PATH} is missing; build it with "
+                "`python -m paper_2004_11346_amd.build` (there is no non-native fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        lib.sht_plan_opts_default.argtypes = [ctypes.POINTER(PlanOpts)]
+        lib.sht_plan_opts_default.restype = None
+        lib.sht_plan_create.argtypes = [I, I, I, I, ctypes.POINTER(PlanOpts), PP]
+        lib.sht_plan_destroy.argtypes = [P]
+        lib.sht_plan_destroy.restype = None
+        for n in ("sht_forward", "sht_inverse", "sht_backward"):
+            getattr(lib, n).argtypes = [P, P, P, P]
+        lib.sht_alt_apply.argtypes = [P, I, I, I, P, P, P]
+        lib.sht_plan_stats.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
+        lib.sht_plan_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
+                                      ctypes.POINTER(I)]
+        lib.sht_plan_nodes.argtypes = [P, P, P]
+        lib.sht_strerror.argtypes = [I]
+        lib.sht_strerror.restype = ctypes.c_char_p
+        lib.sht_last_error_detail.argtypes = []
+        lib.sht_last_error_detail.restype = ctypes.c_char_p
+        lib.sht_host_plan_create.argtypes = [I, I, ctypes.POINTER(PlanOpts), PP]
+        lib.sht_host_plan_destroy.argtypes = [P]
+        lib.sht_host_plan_destroy.restype = None
+        lib.sht_host_plan_apply.argtypes = [P, I, I, I, I, P, P]
+        lib.sht_host_alt_matrix.argtypes = [P, I, I, P]
+        lib.sht_host_plan_stats.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
+        lib.sht_host_gauss_legendre.argtypes = [I, P, P]
+        for n in EXPORTED:
+            f = getattr(lib, n)
+            if f.restype is ctypes.c_int or n in ("sht_plan_create", "sht_forward", "sht_inverse",
+                                                   "sht_backward", "sht_alt_apply", "sht_plan_stats",
+                                                   "sht_plan_info", "sht_plan_nodes",
+                                                   "sht_host_plan_create", "sht_host_plan_apply",
+                                                   "sht_host_alt_matrix", "sht_host_plan_stats",
+                                                   "sht_host_gauss_legendre"):
+                f.restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+def check(rc: int, what: str):
+    if rc < 0:
+        lib = load()
+        detail = lib.sht_last_error_detail().decode(errors="replace")
+        msg = lib.sht_strerror(rc).decode()
+        raise ShtError(rc, what, f"{msg}; {detail}")
+    return rc
+
+
+def default_opts(**kw) -> PlanOpts:
+    o = PlanOpts()
+    load().sht_plan_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown plan option {k}")
+        setattr(o, k, v)
+    return o

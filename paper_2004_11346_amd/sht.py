@@ -1,0 +1,151 @@
+"""Python front end: a plan object wrapping the C-ABI, operating on torch
+tensors that live on the GPU.  Every transform runs in the native HIP
+library; this module only checks shapes/dtypes and passes pointers and the
+current stream.
+
+Tensor conventions (see ``include/sht.h``):
+  beta : complex [batch, 4N^2], m-major (orders 0, 1, -1, 2, -2, ...;
+         degrees k = |m| .. 2N-1 inside an order)
+  f, g : complex [batch, 2N, 4N-1], rows = Gauss-Legendre nodes ascending in
+         x = cos(theta), columns = phi_j = 2 pi (j + 1/2)/(4N - 1)
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+
+import torch
+
+from . import lib as _l
+
+_DT = {torch.complex128: _l.SHT_F64, torch.complex64: _l.SHT_F32}
+_METHOD = {"dense": _l.SHT_DENSE, "idbf": _l.SHT_IDBF}
+
+
+def _stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Plan:
+    """A transform plan of degree N for ``batch`` fields.
+
+    method: "dense" (plain form) or "idbf" (fast form).
+    dtype:  torch.complex128 (FP64) or torch.complex64 (FP32).
+    Extra keyword arguments set ``sht_plan_opts`` fields (eps, n0, leaf, rk,
+    oversample, rsvd_r, rsvd_q, sampling, seed, threads, f32_mode, min_idbf).
+    """
+
+    def __init__(self, N: int, batch: int = 1, dtype=torch.complex128, method: str = "dense", **opts):
+        self._lib = _l.load()
+        self.N = int(N)
+        self.batch = int(batch)
+        self.dtype = dtype
+        self.method = method
+        self.M = 4 * self.N - 1
+        o = _l.default_opts(**opts)
+        h = ctypes.c_void_p()
+        _l.check(self._lib.sht_plan_create(self.N, self.batch, _DT[dtype], _METHOD[method],
+                                           ctypes.byref(o), ctypes.byref(h)), "sht_plan_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sht_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ shapes
+    @property
+    def coef_shape(self):
+        return (self.batch, 4 * self.N * self.N)
+
+    @property
+    def grid_shape(self):
+        return (self.batch, 2 * self.N, self.M)
+
+    def _check(self, t: torch.Tensor, shape, name):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if t.dtype != self.dtype:
+            raise TypeError(f"{name} must have dtype {self.dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+
+    def empty_coefs(self, device="cuda"):
+        return torch.empty(self.coef_shape, dtype=self.dtype, device=device)
+
+    def empty_grid(self, device="cuda"):
+        return torch.empty(self.grid_shape, dtype=self.dtype, device=device)
+
+    # ------------------------------------------------------------- transforms
+    def forward(self, beta: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Forward SHT: coefficients -> grid values."""
+        self._check(beta, self.coef_shape, "beta")
+        out = self.empty_grid(beta.device) if out is None else out
+        self._check(out, self.grid_shape, "out")
+        _l.check(self._lib.sht_forward(self._h, beta.data_ptr(), out.data_ptr(),
+                                       ctypes.c_void_p(_stream_ptr(stream))), "sht_forward")
+        return out
+
+    def inverse(self, f: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Inverse SHT: grid values -> coefficients."""
+        self._check(f, self.grid_shape, "f")
+        out = self.empty_coefs(f.device) if out is None else out
+        self._check(out, self.coef_shape, "out")
+        _l.check(self._lib.sht_inverse(self._h, f.data_ptr(), out.data_ptr(),
+                                       ctypes.c_void_p(_stream_ptr(stream))), "sht_inverse")
+        return out
+
+    def backward(self, grad_f: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Adjoint of forward (conjugate transpose): grad_f -> grad_beta."""
+        self._check(grad_f, self.grid_shape, "grad_f")
+        out = self.empty_coefs(grad_f.device) if out is None else out
+        self._check(out, self.coef_shape, "out")
+        _l.check(self._lib.sht_backward(self._h, grad_f.data_ptr(), out.data_ptr(),
+                                        ctypes.c_void_p(_stream_ptr(stream))), "sht_backward")
+        return out
+
+    def alt(self, m_lo: int, m_hi: int, direction: str, inp: torch.Tensor, out: torch.Tensor, stream=None):
+        """ALT only for orders m_lo <= |m| <= m_hi.  direction: "fwd" (beta -> g),
+        "inv" (g -> beta, A^T W) or "adj" (g -> beta, A^T)."""
+        d = {"fwd": _l.SHT_FWD, "inv": _l.SHT_INV, "adj": _l.SHT_ADJ}[direction]
+        if d == _l.SHT_FWD:
+            self._check(inp, self.coef_shape, "beta")
+            self._check(out, self.grid_shape, "g")
+        else:
+            self._check(inp, self.grid_shape, "g")
+            self._check(out, self.coef_shape, "beta")
+        _l.check(self._lib.sht_alt_apply(self._h, int(m_lo), int(m_hi), d, inp.data_ptr(), out.data_ptr(),
+                                         ctypes.c_void_p(_stream_ptr(stream))), "sht_alt_apply")
+        return out
+
+    # ------------------------------------------------------------------ info
+    def stats(self) -> dict:
+        n = _l.check(self._lib.sht_plan_stats(self._h, None, 0), "sht_plan_stats")
+        buf = ctypes.create_string_buffer(n)
+        _l.check(self._lib.sht_plan_stats(self._h, buf, n), "sht_plan_stats")
+        return json.loads(buf.value.decode())
+
+    def nodes(self):
+        import numpy as np
+        x = np.empty(2 * self.N)
+        w = np.empty(2 * self.N)
+        _l.check(self._lib.sht_plan_nodes(self._h, x.ctypes.data, w.ctypes.data), "sht_plan_nodes")
+        return x, w
+
+
+def host_gauss_legendre(n: int):
+    """The library's own Gauss-Legendre rule (host code, no GPU needed)."""
+    import numpy as np
+    x = np.empty(n)
+    w = np.empty(n)
+    _l.check(_l.load().sht_host_gauss_legendre(n, x.ctypes.data, w.ctypes.data), "sht_host_gauss_legendre")
+    return x, w
