@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Benchmark of the SHT hot path on one MI355X.
+
+A step is one pass of the whole path over one batch of synthetic fields: a
+forward SHT (ALT for every order m + length-(4N-1) phi DFT) and an inverse
+SHT (phi analysis + transposed ALT) of every field.  `value` is SHT/s over the
+timed steps, counting each forward and each inverse of a field as one SHT.
+The headline workload is N = 1024 (grid 2048 x 4095), FP64, 32 fields, with
+the fast (IDBF) ALT; the plain (dense) ALT and batch 1 are measured beside it
+and reported under "details".
+
+Prints ONE JSON line.  `--gpus` above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, GB/s
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector and matrix, TFLOP/s
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector
+PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 MFMA
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--N", type=int, default=1024)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--method", choices=["idbf", "dense"], default=None)
+    ap.add_argument("--no-details", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    return ap.parse_args()
+
+
+def rel_l2(a, b):
+    import numpy as np
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def rel_max(a, b):
+    import numpy as np
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+class Timer:
+    """HIP events on torch's current stream, which is the stream every library
+    call is enqueued on."""
+
+    def __init__(self):
+        import torch
+        self.torch = torch
+
+    def time(self, fn, reps: int, warmup: int = 1) -> float:
+        torch = self.torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3  # seconds per call
+
+
+def cpu_baseline(N: int):
+    """The oracle (plain CPU FP64 definition) on a bounded sample of the same
+    workload, extrapolated to one forward + one inverse SHT of one field."""
+    import numpy as np
+
+    import oracle
+    from paper_2004_11346_amd import inputs
+
+    beta = inputs.make_beta(N, 1, 2, dist="decay")[0]
+    n = 2 * N
+    step = max(1, n // 512)
+    absm = list(range(0, n, step))
+    rows = list(range(0, n, max(1, n // 128)))
+    work_all = sum(n - a for a in range(n))
+    work_s = sum(n - a for a in absm)
+    t0 = time.perf_counter()
+    gfw = oracle.alt_forward_orders(N, beta, absm)
+    t1 = time.perf_counter()
+    oracle.alt_transpose_orders(N, gfw, absm, weights=True)
+    t2 = time.perf_counter()
+    g = np.zeros((n, 4 * N - 1), complex)
+    fr = oracle.dft_synthesis(N, g, rows=rows)
+    t3 = time.perf_counter()
+    oracle.dft_analysis(N, fr)
+    t4 = time.perf_counter()
+    scale_alt = work_all / work_s
+    scale_dft = n / len(rows)
+    t_fwd = (t1 - t0) * scale_alt + (t3 - t2) * scale_dft
+    t_inv = (t2 - t1) * scale_alt + (t4 - t3) * scale_dft
+    return {
+        "value": 2.0 / (t_fwd + t_inv),
+        "unit": "SHT/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"N={N}, one field: forward and transposed ALT for {len(absm)} of {n} orders |m| "
+                   f"(both signs), phi synthesis and analysis for {len(rows)} of {n} latitude rows; "
+                   f"measured {t4 - t0:.1f} s, extrapolated by work to full forward+inverse SHTs"),
+        "seconds_measured": t4 - t0,
+        "fwd_s_per_field": t_fwd,
+        "inv_s_per_field": t_inv,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding by order is described in DESIGN.md)"}))
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("one GPU only: launch without torch.distributed", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2004_11346_amd.sht as S
+    from paper_2004_11346_amd import inputs
+
+    torch.cuda.init()
+    N, batch = args.N, args.batch
+    cdt = torch.complex128 if args.dtype == "f64" else torch.complex64
+    M = 4 * N - 1
+    method = args.method
+    if method is None:
+        method = "idbf"
+        try:
+            S.Plan(4, 1, method="idbf").close()
+        except Exception:  # noqa: BLE001  (fast form not built: measure the plain one)
+            method = "dense"
+    timer = Timer()
+
+    beta_np = inputs.make_beta(N, batch, 2, dist="decay")
+    beta = torch.from_numpy(beta_np).to(cdt).cuda()
+    t_build0 = time.perf_counter()
+    plan = S.Plan(N, batch, dtype=cdt, method=method)
+    t_build = time.perf_counter() - t_build0
+    f = plan.empty_grid()
+    bout = plan.empty_coefs()
+
+    def step():
+        plan.forward(beta, out=f)
+        plan.inverse(f, out=bout)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+    value = 2.0 * batch / (ms_per_step / 1e3)
+
+    # dominant kernel: the ALT (forward), timed alone with HIP events
+    g = plan.empty_grid()
+    t_alt_fwd = timer.time(lambda: plan.alt(0, 2 * N - 1, "fwd", beta, g), reps=max(3, args.steps))
+    t_alt_inv = timer.time(lambda: plan.alt(0, 2 * N - 1, "inv", g, bout), reps=max(3, args.steps))
+    stats = plan.stats()
+    R = 4 * batch
+    if method == "dense":
+        flops = 2.0 * N * N * (2 * N + 1) * R  # 16 N^3 per field
+        roof = {"bound": "alu", "achieved": flops / t_alt_fwd / 1e12, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": flops / t_alt_fwd / 1e12 / PEAK_FP64_TFLOPS, "traffic": None,
+                "kernel": "k_alt_dense_fwd", "kernel_ms": t_alt_fwd * 1e3,
+                "algorithmic_flops_per_launch": flops}
+    else:
+        prog = stats.get("program", {})
+        nnz = float(prog.get("stored_entries", 0))
+        sbytes = 8 if args.dtype == "f64" else 4
+        fbytes = nnz * sbytes + float(prog.get("index_bytes", 0))
+        vbytes = batch * (4 * N * N + 2 * N * M) * 2 * sbytes
+        flops = 2.0 * nnz * R
+        if R * 2 / sbytes >= 78.6 / 8.0 * 1.0:  # above the FP64 ridge -> compute bound
+            roof = {"bound": "alu", "achieved": flops / t_alt_fwd / 1e12, "peak": PEAK_FP64_TFLOPS,
+                    "unit": "TFLOP/s", "frac": flops / t_alt_fwd / 1e12 / PEAK_FP64_TFLOPS}
+        else:
+            roof = {"bound": "hbm", "achieved": (fbytes + vbytes) / t_alt_fwd / 1e9, "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": (fbytes + vbytes) / t_alt_fwd / 1e9 / PEAK_HBM_GBS}
+        roof.update({"traffic": None, "kernel": "idbf ALT program (all stages)",
+                     "kernel_ms": t_alt_fwd * 1e3, "algorithmic_flops_per_launch": flops,
+                     "algorithmic_bytes_per_launch": fbytes + vbytes})
+
+    out = {
+        "metric": "SHT/s + ALT Gcoef/s at N=1024/4096, IDBF vs dense, FP64 & FP32, vs FP64 oracle",
+        "value": value,
+        "unit": "SHT/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"SHT N={N} (grid {2 * N}x{M}), {batch} fields, {method} ALT, "
+                               f"{args.dtype}, forward+inverse per step",
+                   "N": N, "batch": batch, "method": method},
+        "alt_gcoef_per_s_fwd": batch * 4 * N * N / t_alt_fwd / 1e9,
+        "alt_gcoef_per_s_inv": batch * 4 * N * N / t_alt_inv / 1e9,
+        "plan_build_s": t_build,
+        "roofline": roof,
+    }
+
+    if not args.no_check:
+        # errors against the oracle at sampled orders (ALT) and rows (full SHT)
+        import oracle
+        absm = [0, 1, N // 2, N, 3 * N // 2, 2 * N - 1] + list(inputs.sample_indices(2 * N, 10, 11))
+        gh = g.cpu().numpy()
+        plan.alt(0, 2 * N - 1, "fwd", beta, g)
+        gh = g.cpu().numpy()
+        errs = []
+        for b in sorted({0, batch - 1}):
+            ref = oracle.alt_forward_orders(N, beta_np[b], absm)
+            got = np.stack([np.stack([gh[b][:, a % M], gh[b][:, (-a) % M]]) for a in absm])
+            errs.append((rel_l2(got, ref), rel_max(got, ref)))
+        plan.forward(beta, out=f)
+        plan.inverse(f, out=bout)
+        rt = rel_l2(bout.cpu().numpy(), beta_np)
+        out["errors_vs_oracle"] = {"alt_fwd_sampled_orders_rel_l2": max(e[0] for e in errs),
+                                   "alt_fwd_sampled_orders_rel_max": max(e[1] for e in errs),
+                                   "round_trip_rel_l2": rt, "orders_checked": len(absm)}
+
+    if not args.no_details:
+        det = {}
+        for meth in (["dense", "idbf"] if method == "idbf" else ["dense"]):
+            for bb in (1, batch):
+                p = plan if (meth == method and bb == batch) else S.Plan(N, bb, dtype=cdt, method=meth)
+                bt = beta[:bb].contiguous()
+                ff = p.empty_grid()
+                ob = p.empty_coefs()
+                tf = timer.time(lambda: p.forward(bt, out=ff), reps=3)
+                ti = timer.time(lambda: p.inverse(ff, out=ob), reps=3)
+                ga = p.empty_grid()
+                taf = timer.time(lambda: p.alt(0, 2 * N - 1, "fwd", bt, ga), reps=3)
+                tai = timer.time(lambda: p.alt(0, 2 * N - 1, "inv", ga, ob), reps=3)
+                det[f"{meth}_b{bb}"] = {"fwd_sht_per_s": bb / tf, "inv_sht_per_s": bb / ti,
+                                        "alt_fwd_ms": taf * 1e3, "alt_inv_ms": tai * 1e3,
+                                        "alt_fwd_gcoef_s": bb * 4 * N * N / taf / 1e9,
+                                        "alt_inv_gcoef_s": bb * 4 * N * N / tai / 1e9,
+                                        "sht_fwd_ms": tf * 1e3, "sht_inv_ms": ti * 1e3}
+                if p is not plan:
+                    p.close()
+        if "dense_b%d" % batch in det and "idbf_b%d" % batch in det:
+            det["idbf_speedup_alt_fwd"] = det[f"dense_b{batch}"]["alt_fwd_ms"] / det[f"idbf_b{batch}"]["alt_fwd_ms"]
+        out["details"] = det
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(N)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

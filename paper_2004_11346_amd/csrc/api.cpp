@@ -245,9 +245,14 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
         if (pb) HIP_TRY(hipMalloc((void **)&p->d_part, pb), "workspace partials");
     } else {
         idbf::HostProgram hp;
-        int brc = idbf::build_program(N, lt, p->opts, hp);
+        int brc;
+        try {
+            brc = idbf::build_program(N, lt, p->opts, hp);
+        } catch (const std::bad_alloc &) {
+            return SHT_ERR_OOM;
+        }
         if (brc) return brc;
-        brc = idbf::upload_program(hp, dtype, batch, p->opts, p->prog);
+        brc = idbf::upload_program(hp, dtype, batch, p->d_wh, p->prog);
         if (brc) return brc;
         p->stats = hp.stats_json;
     }

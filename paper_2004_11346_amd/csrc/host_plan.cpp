@@ -1,0 +1,102 @@
+// Host-side plan verification entry points (include/sht.h): build the FP64
+// plan without a device and apply its factors with plain loops.
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "idbf_build.h"
+#include "idbf_pack.h"
+#include "sht.h"
+#include "sht_internal.h"
+
+using namespace sht;
+
+struct sht_host_plan {
+    int method = SHT_DENSE;
+    idbf::HostPlanData data;
+    idbf::PackedPlan packed;
+};
+
+extern "C" {
+
+int sht_host_plan_create(int N, int method, const sht_plan_opts *opts, sht_host_plan_t **out) {
+    if (!out) return SHT_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (N < 1 || N > 8192) return SHT_ERR_INVALID_ARG;
+    if (method != SHT_DENSE && method != SHT_IDBF) return SHT_ERR_UNSUPPORTED;
+    sht_plan_opts o;
+    sht_plan_opts_default(&o);
+    if (opts) o = *opts;
+    sht_host_plan *hp = new (std::nothrow) sht_host_plan;
+    if (!hp) return SHT_ERR_OOM;
+    hp->method = method;
+    try {
+        if (method == SHT_IDBF) {
+            int rc = idbf::build_all(N, o, hp->data);
+            if (rc) {
+                delete hp;
+                return rc;
+            }
+            idbf::pack_programs(hp->data, hp->packed);
+        } else {
+            hp->data.N = N;
+            hp->data.opts = o;
+            build_legendre_tables(N, hp->data.lt);
+        }
+    } catch (const std::bad_alloc &) {
+        delete hp;
+        return SHT_ERR_OOM;
+    }
+    *out = hp;
+    return SHT_OK;
+}
+
+void sht_host_plan_destroy(sht_host_plan_t *hp) { delete hp; }
+
+int sht_host_plan_apply(const sht_host_plan_t *hp, int absm, int parity, int dir, int R, const double *in,
+                        double *out) {
+    if (!hp || !in || !out || R < 1) return SHT_ERR_INVALID_ARG;
+    const int N = hp->data.N;
+    if (absm < 0 || absm >= 2 * N || parity < 0 || parity > 1 || (dir != SHT_FWD && dir != SHT_ADJ))
+        return SHT_ERR_INVALID_ARG;
+    if (hp->method != SHT_IDBF) return SHT_ERR_UNSUPPORTED;
+    const int task = 2 * absm + parity;
+    const idbf::Task &t = hp->data.tasks[task];
+    if (t.cols <= 0) return SHT_OK;
+    // run the packed program on panels that are zero outside this task
+    const idbf::PackedPlan &pk = hp->packed;
+    const bool fwd = dir == SHT_FWD;
+    const idbf::Program &p = fwd ? pk.fwd : pk.adj;
+    std::vector<double> pin((size_t)p.in_rows * R, 0.0), pout((size_t)p.out_rows * R, 0.0);
+    const int64_t ib = fwd ? pk.x_off[task] : pk.y_off[task];
+    const int64_t ob = fwd ? pk.y_off[task] : pk.x_off[task];
+    const int nin = fwd ? t.cols : t.rows, nout = fwd ? t.rows : t.cols;
+    std::memcpy(&pin[(size_t)ib * R], in, sizeof(double) * (size_t)nin * R);
+    idbf::host_run_program(p, pk.vals.data(), R, pin.data(), pout.data());
+    std::memcpy(out, &pout[(size_t)ob * R], sizeof(double) * (size_t)nout * R);
+    return SHT_OK;
+}
+
+int sht_host_alt_matrix(const sht_host_plan_t *hp, int absm, int parity, double *out) {
+    if (!hp || !out) return SHT_ERR_INVALID_ARG;
+    const int N = hp->data.N;
+    if (absm < 0 || absm >= 2 * N || parity < 0 || parity > 1) return SHT_ERR_INVALID_ARG;
+    if (half_cols(N, absm, parity) <= 0) return SHT_OK;
+    alt_half_matrix(hp->data.lt, absm, parity, out);
+    return SHT_OK;
+}
+
+int sht_host_plan_stats(const sht_host_plan_t *hp, char *json, size_t cap) {
+    if (!hp) return SHT_ERR_INVALID_ARG;
+    std::string s = hp->method == SHT_IDBF ? hp->data.stats_json() : std::string("{}");
+    if (json && cap) {
+        size_t n = std::min(cap - 1, s.size());
+        std::memcpy(json, s.data(), n);
+        json[n] = 0;
+    }
+    return (int)s.size() + 1;
+}
+
+}  // extern "C"

@@ -11,6 +11,9 @@
 #include <string>
 #include <vector>
 
+#include "idbf_build.h"
+#include "idbf_device.h"
+#include "idbf_pack.h"
 #include "kernels.h"
 #include "sht.h"
 #include "sht_internal.h"
@@ -20,19 +23,15 @@ namespace idbf {
 
 struct HostProgram {
     int N = 0;
+    PackedPlan packed;
+    BuildStats stats;
     std::string stats_json;
 };
 
-struct DeviceProgram {
-    bool valid = false;
-    void release() {}
-};
-
 int build_program(int N, const LegendreTables &lt, const sht_plan_opts &opts, HostProgram &out);
-int upload_program(const HostProgram &hp, int dtype, int batch, const sht_plan_opts &opts,
-                   DeviceProgram &out);
-hipError_t run(const DeviceProgram &prog, const dev::DenseTables &t, int dtype, int batch, int a_lo,
-               int a_hi, int dir, const void *in, void *out, hipStream_t s);
+int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, DeviceProgram &out);
+hipError_t run(const DeviceProgram &prog, const dev::DenseTables &t, int dtype, int batch, int a_lo, int a_hi,
+               int dir, const void *in, void *out, hipStream_t s);
 
 }  // namespace idbf
 }  // namespace sht

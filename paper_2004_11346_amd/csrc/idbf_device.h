@@ -1,0 +1,44 @@
+// Device-resident fast-ALT plan.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "idbf_program.h"
+
+namespace sht {
+namespace idbf {
+
+struct DeviceProgramDir {
+    Op *d_ops = nullptr;
+    SubOp *d_subs = nullptr;
+    int32_t *d_idx = nullptr;
+    // stage_task_first[s][t]: first op (global index) of task t in stage s;
+    // entry ntask is the stage end
+    std::vector<std::vector<int32_t>> stage_task_first;
+    int max_out = 0, max_in = 0, max_mat = 0;
+};
+
+struct DeviceProgram {
+    bool valid = false;
+    int N = 0, batch = 0, dtype = 0, RC = 16;
+    void *d_vals = nullptr;        // FP64 or FP32 value stream
+    int64_t n_vals = 0;
+    void *d_X = nullptr, *d_Y = nullptr, *d_scrA = nullptr, *d_scrB = nullptr;
+    int64_t *d_x_off = nullptr;    // [4N + 1]
+    const double *d_wh = nullptr;  // half-grid weights (owned by the plan)
+    std::vector<int64_t> x_off_h, y_off_h;
+    int64_t max_task_cols = 0;
+    int64_t index_bytes = 0;
+    DeviceProgramDir fwd, adj;
+    void release();
+};
+
+hipError_t set_kernel_attributes();
+hipError_t run_device(const DeviceProgram &p, int dtype, int batch, int a_lo, int a_hi, int dir, const void *in,
+                      void *out, hipStream_t s);
+
+}  // namespace idbf
+}  // namespace sht

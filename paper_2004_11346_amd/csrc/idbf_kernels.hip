@@ -1,0 +1,267 @@
+// HIP executor of the packed fast-ALT program and the panel kernels around it.
+//
+// Panels: X[task][col][R] holds the coefficients of one (|m|, parity) task as
+// R = 4 * batch real right-hand sides per column (field f, sign of m, re/im:
+// column 4f + 2s + c); Y[task][row][R] holds half-grid values (row r = node
+// 2N-1-r).  k_pack / k_scatter move between beta and X, k_combine / k_fold
+// between Y and the (l, m mod M) grid with the parity split of Section 3.1.2.
+//
+// k_ops executes one stage of the program: one workgroup per op.  The op's
+// input rows are gathered into LDS, each stored matrix block is copied into LDS
+// with coalesced loads, and the products, identity (skeleton) terms and the
+// final write (scratch) or accumulation (output panel) follow.  Ops of one
+// stage never write the same rows, so there are no atomics and the result is
+// bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "idbf_device.h"
+
+namespace sht {
+namespace idbf {
+
+namespace {
+
+__device__ __forceinline__ int64_t d_coef_offset(int N, int m) {
+    int64_t a = m < 0 ? -(int64_t)m : m;
+    int64_t twoN = 2 * (int64_t)N;
+    if (a == 0) return 0;
+    int64_t off = twoN * (2 * a - 1) - a * (a - 1);
+    if (m < 0) off += twoN - a;
+    return off;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ops(const Op *__restrict__ ops, const SubOp *__restrict__ subs,
+                                             const int32_t *__restrict__ idx, const T *__restrict__ vals,
+                                             int op_begin, const T *__restrict__ in, int64_t in_stride,
+                                             T *__restrict__ out, int64_t out_stride, T *__restrict__ scrA,
+                                             T *__restrict__ scrB, int RC, int max_out, int max_in) {
+    extern __shared__ unsigned char smem_raw[];
+    T *acc = reinterpret_cast<T *>(smem_raw);
+    T *xin = acc + (size_t)max_out * RC;
+    T *mat = xin + (size_t)max_in * RC;
+    const Op op = ops[op_begin + blockIdx.x];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int n_out = op.n_out;
+    for (int e = tid; e < n_out * RC; e += nt) acc[e] = (T)0;
+    for (int s = 0; s < op.nsub; ++s) {
+        const SubOp sb = subs[op.sub0 + s];
+        const T *src;
+        int64_t sstride;
+        if (sb.src == kIn) {
+            src = in;
+            sstride = in_stride;
+        } else {
+            src = sb.src == kScrA ? scrA : scrB;
+            sstride = RC;
+        }
+        __syncthreads();
+        if (sb.n_map > 0) {
+            const int32_t *inr = idx + sb.in_off;
+            for (int e = tid; e < sb.n_in * RC; e += nt) {
+                const int j = e / RC, r = e - j * RC;
+                xin[e] = src[(int64_t)inr[j] * sstride + r];
+            }
+            const int mr = sb.mrows, mc = sb.mcols;
+            const T *mv = vals + sb.mat_off;
+            if (sb.ld == mc) {
+                for (int e = tid; e < mr * mc; e += nt) mat[e] = mv[e];
+            } else {
+                for (int e = tid; e < mr * mc; e += nt) {
+                    const int i = e / mc, j = e - i * mc;
+                    mat[e] = mv[(int64_t)i * sb.ld + j];
+                }
+            }
+            __syncthreads();
+            const int32_t *map = idx + sb.map_off;
+            const int nin = sb.n_in;
+            for (int e = tid; e < sb.n_map * RC; e += nt) {
+                const int i = e / RC, r = e - i * RC;
+                T sum = (T)0;
+                if (sb.trans) {
+                    for (int j = 0; j < nin; ++j) sum += mat[j * mc + i] * xin[j * RC + r];
+                } else {
+                    const T *mrow = mat + i * mc;
+                    for (int j = 0; j < nin; ++j) sum += mrow[j] * xin[j * RC + r];
+                }
+                acc[map[i] * RC + r] += sum;
+            }
+        }
+        __syncthreads();
+        if (sb.n_dir > 0) {
+            const int32_t *dir = idx + sb.dir_off;
+            for (int e = tid; e < sb.n_dir * RC; e += nt) {
+                const int d = e / RC, r = e - d * RC;
+                acc[dir[2 * d + 1] * RC + r] += src[(int64_t)dir[2 * d] * sstride + r];
+            }
+        }
+    }
+    __syncthreads();
+    if (op.dst == kOut) {
+        for (int e = tid; e < n_out * RC; e += nt) {
+            const int i = e / RC, r = e - i * RC;
+            T *d = out + (op.dst_row + i) * out_stride + r;
+            *d += acc[e];
+        }
+    } else {
+        T *dst = op.dst == kScrA ? scrA : scrB;
+        for (int e = tid; e < n_out * RC; e += nt) dst[op.dst_row * RC + e] = acc[e];
+    }
+}
+
+// beta -> X panels for tasks [t_lo, t_hi] (orders a_lo..a_hi, both parities).
+// grid: (ceil(max_cols * R / 256), ntasks), block 256.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack(int N, int batch, int t_lo, const int64_t *__restrict__ x_off,
+                                              const T *__restrict__ beta, T *__restrict__ X) {
+    const int task = t_lo + blockIdx.y;
+    const int a = task >> 1, par = task & 1;
+    const int64_t rows = x_off[task + 1] - x_off[task];
+    const int R = 4 * batch;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= rows * R) return;
+    const int j = (int)(e / R), col = (int)(e - (int64_t)j * R);
+    const int f = col >> 2, s = (col >> 1) & 1, c = col & 1;
+    const int k = a + par + 2 * j;
+    T v = (T)0;
+    if (!(s == 1 && a == 0)) v = beta[2 * ((int64_t)f * 4 * N * N + d_coef_offset(N, s ? -a : a) + (k - a)) + c];
+    X[(x_off[task] + j) * R + col] = v;
+}
+
+// X panels -> beta (transposed direction)
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter(int N, int batch, int t_lo, const int64_t *__restrict__ x_off,
+                                                 const T *__restrict__ X, T *__restrict__ beta) {
+    const int task = t_lo + blockIdx.y;
+    const int a = task >> 1, par = task & 1;
+    const int64_t rows = x_off[task + 1] - x_off[task];
+    const int R = 4 * batch;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= rows * R) return;
+    const int j = (int)(e / R), col = (int)(e - (int64_t)j * R);
+    const int f = col >> 2, s = (col >> 1) & 1, c = col & 1;
+    if (s == 1 && a == 0) return;
+    const int k = a + par + 2 * j;
+    beta[2 * ((int64_t)f * 4 * N * N + d_coef_offset(N, s ? -a : a) + (k - a)) + c] = X[(x_off[task] + j) * R + col];
+}
+
+// Y panels -> g columns (parity recombination, Section 3.1.2):
+// g(l = 2N-1-r) = E + O, g(l' = r) = E - O.  grid: (ceil(N * R / 256), orders).
+template <typename T>
+__global__ __launch_bounds__(256) void k_combine(int N, int M, int batch, int a_lo, const T *__restrict__ Y,
+                                                 T *__restrict__ g) {
+    const int a = a_lo + blockIdx.y;
+    const int R = 4 * batch;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)N * R) return;
+    const int r = (int)(e / R), col = (int)(e - (int64_t)r * R);
+    const int f = col >> 2, s = (col >> 1) & 1, c = col & 1;
+    if (s == 1 && a == 0) return;
+    const T E = Y[((int64_t)(2 * a) * N + r) * R + col];
+    const T O = Y[((int64_t)(2 * a + 1) * N + r) * R + col];
+    const int n = 2 * N;
+    const int cc = s ? M - a : a;
+    T *gb = g + 2 * ((int64_t)f * n * M);
+    gb[2 * ((int64_t)(n - 1 - r) * M + cc) + c] = E + O;
+    gb[2 * ((int64_t)r * M + cc) + c] = E - O;
+}
+
+// g columns -> Y panels: H_even = w (g(l) + g(l')), H_odd = w (g(l) - g(l')).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fold(int N, int M, int batch, int a_lo, const double *__restrict__ wh,
+                                              const T *__restrict__ g, T *__restrict__ Y) {
+    const int a = a_lo + blockIdx.y;
+    const int R = 4 * batch;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)N * R) return;
+    const int r = (int)(e / R), col = (int)(e - (int64_t)r * R);
+    const int f = col >> 2, s = (col >> 1) & 1, c = col & 1;
+    T u = (T)0, v = (T)0;
+    const int n = 2 * N;
+    if (!(s == 1 && a == 0)) {
+        const int cc = s ? M - a : a;
+        const T *gb = g + 2 * ((int64_t)f * n * M);
+        u = gb[2 * ((int64_t)(n - 1 - r) * M + cc) + c];
+        v = gb[2 * ((int64_t)r * M + cc) + c];
+    }
+    const T w = wh ? (T)wh[r] : (T)1;
+    Y[((int64_t)(2 * a) * N + r) * R + col] = w * (u + v);
+    Y[((int64_t)(2 * a + 1) * N + r) * R + col] = w * (u - v);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero_cols(T *__restrict__ p, int64_t row0, int64_t rows, int64_t stride,
+                                                   int col0, int ncol) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= rows * ncol) return;
+    const int64_t r = e / ncol;
+    const int c = (int)(e - r * ncol);
+    p[(row0 + r) * stride + col0 + c] = (T)0;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+template <typename T>
+hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir, const void *inp, void *outp,
+                 hipStream_t s) {
+    const int N = p.N, M = 4 * N - 1, R = 4 * batch;
+    const int t_lo = 2 * a_lo, t_hi = 2 * a_hi + 1, nt = t_hi - t_lo + 1;
+    const bool fwd = dir == 0;
+    const DeviceProgramDir &pd = fwd ? p.fwd : p.adj;
+    T *X = (T *)p.d_X, *Y = (T *)p.d_Y;
+    T *scrA = (T *)p.d_scrA, *scrB = (T *)p.d_scrB;
+    const T *vals = (const T *)p.d_vals;
+    const int64_t xmax = p.max_task_cols * (int64_t)R;
+    if (fwd) {
+        hipLaunchKernelGGL((k_pack<T>), dim3(blocks_for(xmax), nt), dim3(256), 0, s, N, batch, t_lo, p.d_x_off,
+                           (const T *)inp, X);
+    } else {
+        hipLaunchKernelGGL((k_fold<T>), dim3(blocks_for((int64_t)N * R), a_hi - a_lo + 1), dim3(256), 0, s, N, M,
+                           batch, a_lo, dir == 1 ? p.d_wh : (const double *)nullptr, (const T *)inp, Y);
+    }
+    T *in = fwd ? X : Y;
+    T *out = fwd ? Y : X;
+    const std::vector<int64_t> &ooff = fwd ? p.y_off_h : p.x_off_h;
+    const int64_t orow0 = ooff[t_lo], orows = ooff[t_hi + 1] - ooff[t_lo];
+    const int RC = p.RC;
+    const size_t lds = sizeof(T) * ((size_t)(pd.max_out + pd.max_in) * RC + (size_t)pd.max_mat);
+    for (int c0 = 0; c0 < R; c0 += RC) {
+        const int rc = std::min(RC, R - c0);
+        hipLaunchKernelGGL((k_zero_cols<T>), dim3(blocks_for(orows * rc)), dim3(256), 0, s, out, orow0, orows,
+                           (int64_t)R, c0, rc);
+        for (size_t st = 0; st < pd.stage_task_first.size(); ++st) {
+            const std::vector<int32_t> &tf = pd.stage_task_first[st];
+            const int ob = tf[t_lo], oe = tf[t_hi + 1];
+            if (oe <= ob) continue;
+            hipLaunchKernelGGL((k_ops<T>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs, pd.d_idx, vals,
+                               ob, (const T *)(in + c0), (int64_t)R, out + c0, (int64_t)R, scrA, scrB, rc,
+                               pd.max_out, pd.max_in);
+        }
+    }
+    if (fwd) {
+        hipLaunchKernelGGL((k_combine<T>), dim3(blocks_for((int64_t)N * R), a_hi - a_lo + 1), dim3(256), 0, s, N,
+                           M, batch, a_lo, (const T *)Y, (T *)outp);
+    } else {
+        hipLaunchKernelGGL((k_scatter<T>), dim3(blocks_for(xmax), nt), dim3(256), 0, s, N, batch, t_lo, p.d_x_off,
+                           (const T *)X, (T *)outp);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t set_kernel_attributes() {
+    hipError_t e = hipFuncSetAttribute((const void *)&k_ops<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)&k_ops<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+hipError_t run_device(const DeviceProgram &p, int dtype, int batch, int a_lo, int a_hi, int dir, const void *in,
+                      void *out, hipStream_t s) {
+    if (dtype == 0) return run_t<double>(p, batch, a_lo, a_hi, dir, in, out, s);
+    return run_t<float>(p, batch, a_lo, a_hi, dir, in, out, s);
+}
+
+}  // namespace idbf
+}  // namespace sht

@@ -1,0 +1,136 @@
+// Fast-ALT plan: build the factors on the host, pack them, upload once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <sstream>
+
+#include "idbf.h"
+
+namespace sht {
+namespace idbf {
+
+namespace {
+
+template <typename V>
+hipError_t up(const std::vector<V> &h, V **d) {
+    hipError_t e = hipMalloc((void **)d, std::max<size_t>(1, h.size() * sizeof(V)));
+    if (e != hipSuccess) return e;
+    if (h.empty()) return hipSuccess;
+    return hipMemcpy(*d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice);
+}
+
+hipError_t upload_dir(const Program &p, int ntask, DeviceProgramDir &d) {
+    hipError_t e;
+    if ((e = up(p.ops, &d.d_ops)) != hipSuccess) return e;
+    if ((e = up(p.subs, &d.d_subs)) != hipSuccess) return e;
+    if ((e = up(p.idx, &d.d_idx)) != hipSuccess) return e;
+    d.max_out = std::max(1, p.max_n_out);
+    d.max_in = std::max(1, p.max_n_in);
+    d.max_mat = std::max(1, p.max_mat);
+    d.stage_task_first.clear();
+    for (const Stage &st : p.stages) {
+        std::vector<int32_t> tf(ntask + 1);
+        int q = st.op_begin;
+        for (int t = 0; t <= ntask; ++t) {
+            while (q < st.op_end && p.op_task[q] < t) ++q;
+            tf[t] = q;
+        }
+        tf[ntask] = st.op_end;
+        d.stage_task_first.push_back(std::move(tf));
+    }
+    return hipSuccess;
+}
+
+int fail(hipError_t e, const char *what) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    set_error_detail(buf);
+    return e == hipErrorOutOfMemory ? SHT_ERR_OOM : SHT_ERR_HIP;
+}
+
+}  // namespace
+
+void DeviceProgram::release() {
+    for (void *p : {d_vals, d_X, d_Y, d_scrA, d_scrB, (void *)d_x_off, (void *)fwd.d_ops, (void *)fwd.d_subs,
+                    (void *)fwd.d_idx, (void *)adj.d_ops, (void *)adj.d_subs, (void *)adj.d_idx})
+        if (p) (void)hipFree(p);
+    d_vals = d_X = d_Y = d_scrA = d_scrB = nullptr;
+    d_x_off = nullptr;
+    fwd = DeviceProgramDir();
+    adj = DeviceProgramDir();
+    valid = false;
+}
+
+int build_program(int N, const LegendreTables &lt, const sht_plan_opts &opts, HostProgram &out) {
+    (void)lt;
+    HostPlanData hp;
+    int rc = build_all(N, opts, hp);
+    if (rc) return rc;
+    pack_programs(hp, out.packed);
+    out.N = N;
+    out.stats = hp.stats;
+    std::ostringstream os;
+    std::string base = hp.stats_json();
+    base.pop_back();  // strip '}'
+    int64_t idx_bytes = 4 * (int64_t)(out.packed.fwd.idx.size() + out.packed.adj.idx.size()) +
+                        (int64_t)(out.packed.fwd.ops.size() + out.packed.adj.ops.size()) * sizeof(Op) +
+                        (int64_t)(out.packed.fwd.subs.size() + out.packed.adj.subs.size()) * sizeof(SubOp);
+    os << base << ",\"value_stream\":" << out.packed.vals.size() << ",\"index_bytes\":" << idx_bytes
+       << ",\"fwd_stages\":" << out.packed.fwd.stages.size() << ",\"fwd_work_stages\":"
+       << out.packed.fwd.n_work_stages << ",\"adj_stages\":" << out.packed.adj.stages.size()
+       << ",\"fwd_ops\":" << out.packed.fwd.ops.size() << ",\"scratch_rows\":"
+       << std::max(out.packed.fwd.scr_rows, out.packed.adj.scr_rows) << "}";
+    out.stats_json = os.str();
+    return SHT_OK;
+}
+
+int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, DeviceProgram &d) {
+    hipError_t e;
+    const PackedPlan &pk = hp.packed;
+    const int N = hp.N, ntask = 4 * N;
+    d.N = N;
+    d.batch = batch;
+    d.dtype = dtype;
+    const int R = 4 * batch;
+    d.RC = std::min(R, dtype == SHT_F64 ? 16 : 32);
+    d.d_wh = d_wh;
+    d.n_vals = (int64_t)pk.vals.size();
+    if (dtype == SHT_F64) {
+        if ((e = up(pk.vals, (double **)&d.d_vals)) != hipSuccess) return fail(e, "upload values");
+    } else {
+        std::vector<float> vf(pk.vals.begin(), pk.vals.end());
+        if ((e = up(vf, (float **)&d.d_vals)) != hipSuccess) return fail(e, "upload values");
+    }
+    if ((e = upload_dir(pk.fwd, ntask, d.fwd)) != hipSuccess) return fail(e, "upload program");
+    if ((e = upload_dir(pk.adj, ntask, d.adj)) != hipSuccess) return fail(e, "upload program");
+    d.x_off_h = pk.x_off;
+    d.y_off_h = pk.y_off;
+    if ((e = up(pk.x_off, &d.d_x_off)) != hipSuccess) return fail(e, "upload offsets");
+    d.max_task_cols = 0;
+    for (int t = 0; t < ntask; ++t) d.max_task_cols = std::max(d.max_task_cols, pk.x_off[t + 1] - pk.x_off[t]);
+    const size_t es = dtype == SHT_F64 ? 8 : 4;
+    if ((e = hipMalloc(&d.d_X, es * std::max<int64_t>(1, pk.x_off[ntask]) * R)) != hipSuccess)
+        return fail(e, "X panels");
+    if ((e = hipMalloc(&d.d_Y, es * std::max<int64_t>(1, pk.y_off[ntask]) * R)) != hipSuccess)
+        return fail(e, "Y panels");
+    const int64_t sr = std::max<int64_t>(1, std::max(pk.fwd.scr_rows, pk.adj.scr_rows));
+    if ((e = hipMalloc(&d.d_scrA, es * sr * d.RC)) != hipSuccess) return fail(e, "scratch");
+    if ((e = hipMalloc(&d.d_scrB, es * sr * d.RC)) != hipSuccess) return fail(e, "scratch");
+    if ((e = set_kernel_attributes()) != hipSuccess) return fail(e, "kernel attributes");
+    // the host copy of the value stream is no longer needed
+    hp.packed.vals.clear();
+    hp.packed.vals.shrink_to_fit();
+    d.valid = true;
+    return SHT_OK;
+}
+
+hipError_t run(const DeviceProgram &prog, const dev::DenseTables &t, int dtype, int batch, int a_lo, int a_hi,
+               int dir, const void *in, void *out, hipStream_t s) {
+    (void)t;
+    if (!prog.valid) return hipErrorInvalidValue;
+    return run_device(prog, dtype, batch, a_lo, a_hi, dir, in, out, s);
+}
+
+}  // namespace idbf
+}  // namespace sht
