@@ -1,6 +1,9 @@
 // Host-side plan verification entry points (include/sht.h): build the FP64
 // plan without a device and apply its factors with plain loops.
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -39,7 +42,11 @@ int sht_host_plan_create(int N, int method, const sht_plan_opts *opts, sht_host_
                 delete hp;
                 return rc;
             }
+            auto tp = std::chrono::steady_clock::now();
             idbf::pack_programs(hp->data, hp->packed);
+            if (std::getenv("SHT_VERBOSE"))
+                std::fprintf(stderr, "[sht] factors %.2fs, packing %.2fs\n", hp->data.stats.seconds,
+                             std::chrono::duration<double>(std::chrono::steady_clock::now() - tp).count());
         } else {
             hp->data.N = N;
             hp->data.opts = o;
@@ -74,7 +81,7 @@ int sht_host_plan_apply(const sht_host_plan_t *hp, int absm, int parity, int dir
     const int64_t ob = fwd ? pk.y_off[task] : pk.x_off[task];
     const int nin = fwd ? t.cols : t.rows, nout = fwd ? t.rows : t.cols;
     std::memcpy(&pin[(size_t)ib * R], in, sizeof(double) * (size_t)nin * R);
-    idbf::host_run_program(p, pk.vals.data(), R, pin.data(), pout.data());
+    idbf::host_run_program(p, R, pin.data(), pout.data());
     std::memcpy(out, &pout[(size_t)ob * R], sizeof(double) * (size_t)nout * R);
     return SHT_OK;
 }
@@ -90,7 +97,18 @@ int sht_host_alt_matrix(const sht_host_plan_t *hp, int absm, int parity, double 
 
 int sht_host_plan_stats(const sht_host_plan_t *hp, char *json, size_t cap) {
     if (!hp) return SHT_ERR_INVALID_ARG;
-    std::string s = hp->method == SHT_IDBF ? hp->data.stats_json() : std::string("{}");
+    std::string s = "{}";
+    if (hp->method == SHT_IDBF) {
+        s = hp->data.stats_json();
+        s.pop_back();
+        const idbf::PackedPlan &pk = hp->packed;
+        s += ",\"fwd_stages\":" + std::to_string(pk.fwd.stages.size()) + ",\"fwd_work_stages\":" +
+             std::to_string(pk.fwd.n_work_stages) + ",\"fwd_ops\":" + std::to_string(pk.fwd.ops.size()) +
+             ",\"adj_stages\":" + std::to_string(pk.adj.stages.size()) + ",\"scratch_rows\":" +
+             std::to_string(std::max(pk.fwd.scr_rows, pk.adj.scr_rows)) + ",\"max_n_out\":" +
+             std::to_string(pk.fwd.max_n_out) + ",\"max_n_in\":" + std::to_string(pk.fwd.max_n_in) +
+             ",\"fwd_values\":" + std::to_string(pk.fwd.vals.size()) + ",\"adj_values\":" + std::to_string(pk.adj.vals.size()) + "}";
+    }
     if (json && cap) {
         size_t n = std::min(cap - 1, s.size());
         std::memcpy(json, s.data(), n);

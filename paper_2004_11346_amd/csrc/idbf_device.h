@@ -12,20 +12,20 @@ namespace sht {
 namespace idbf {
 
 struct DeviceProgramDir {
+    void *d_vals = nullptr;  // output-major value stream (FP64 or FP32)
+    int64_t n_vals = 0;
     Op *d_ops = nullptr;
     SubOp *d_subs = nullptr;
     int32_t *d_idx = nullptr;
     // stage_task_first[s][t]: first op (global index) of task t in stage s;
     // entry ntask is the stage end
     std::vector<std::vector<int32_t>> stage_task_first;
-    int max_out = 0, max_in = 0, max_mat = 0;
+    std::vector<Stage> stages;  // host copy (LDS sizing per stage)
 };
 
 struct DeviceProgram {
     bool valid = false;
     int N = 0, batch = 0, dtype = 0, RC = 16;
-    void *d_vals = nullptr;        // FP64 or FP32 value stream
-    int64_t n_vals = 0;
     void *d_X = nullptr, *d_Y = nullptr, *d_scrA = nullptr, *d_scrB = nullptr;
     int64_t *d_x_off = nullptr;    // [4N + 1]
     const double *d_wh = nullptr;  // half-grid weights (owned by the plan)

@@ -6,7 +6,7 @@
 // 2N-1-r).  k_pack / k_scatter move between beta and X, k_combine / k_fold
 // between Y and the (l, m mod M) grid with the parity split of Section 3.1.2.
 //
-// k_ops executes one stage of the program: one workgroup per op.  The op's
+// k_ops executes one stage of the program: one wave per op (see below); ops of
 // input rows are gathered into LDS, each stored matrix block is copied into LDS
 // with coalesced loads, and the products, identity (skeleton) terms and the
 // final write (scratch) or accumulation (output panel) follow.  Ops of one
@@ -30,20 +30,23 @@ __device__ __forceinline__ int64_t d_coef_offset(int N, int m) {
     return off;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_ops(const Op *__restrict__ ops, const SubOp *__restrict__ subs,
-                                             const int32_t *__restrict__ idx, const T *__restrict__ vals,
-                                             int op_begin, const T *__restrict__ in, int64_t in_stride,
-                                             T *__restrict__ out, int64_t out_stride, T *__restrict__ scrA,
-                                             T *__restrict__ scrB, int RC, int max_out, int max_in) {
+// One wave per op.  Lanes own matrix outputs: lane q of a sub-op streams
+// column q of its output-major matrix (consecutive lanes, consecutive words)
+// and keeps the RC right-hand-side sums in registers; the gathered input rows
+// sit in LDS and are read as wave-wide broadcasts.
+template <typename T, int RC>
+__global__ __launch_bounds__(64) void k_ops(const Op *__restrict__ ops, const SubOp *__restrict__ subs,
+                                            const int32_t *__restrict__ idx, const T *__restrict__ vals,
+                                            int op_begin, const T *__restrict__ in, int64_t in_stride,
+                                            T *__restrict__ out, int64_t out_stride, T *__restrict__ scrA,
+                                            T *__restrict__ scrB, int rc, int max_out) {
     extern __shared__ unsigned char smem_raw[];
     T *acc = reinterpret_cast<T *>(smem_raw);
     T *xin = acc + (size_t)max_out * RC;
-    T *mat = xin + (size_t)max_in * RC;
     const Op op = ops[op_begin + blockIdx.x];
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = threadIdx.x;
     const int n_out = op.n_out;
-    for (int e = tid; e < n_out * RC; e += nt) acc[e] = (T)0;
+    for (int e = lane; e < n_out * RC; e += 64) acc[e] = (T)0;
     for (int s = 0; s < op.nsub; ++s) {
         const SubOp sb = subs[op.sub0 + s];
         const T *src;
@@ -56,56 +59,65 @@ __global__ __launch_bounds__(256) void k_ops(const Op *__restrict__ ops, const S
             sstride = RC;
         }
         __syncthreads();
-        if (sb.n_map > 0) {
+        const int nin = sb.n_in, nmap = sb.n_map;
+        if (nmap > 0) {
             const int32_t *inr = idx + sb.in_off;
-            for (int e = tid; e < sb.n_in * RC; e += nt) {
+            for (int e = lane; e < nin * RC; e += 64) {
                 const int j = e / RC, r = e - j * RC;
-                xin[e] = src[(int64_t)inr[j] * sstride + r];
-            }
-            const int mr = sb.mrows, mc = sb.mcols;
-            const T *mv = vals + sb.mat_off;
-            if (sb.ld == mc) {
-                for (int e = tid; e < mr * mc; e += nt) mat[e] = mv[e];
-            } else {
-                for (int e = tid; e < mr * mc; e += nt) {
-                    const int i = e / mc, j = e - i * mc;
-                    mat[e] = mv[(int64_t)i * sb.ld + j];
-                }
+                xin[e] = r < rc ? src[(int64_t)inr[j] * sstride + r] : (T)0;
             }
             __syncthreads();
             const int32_t *map = idx + sb.map_off;
-            const int nin = sb.n_in;
-            for (int e = tid; e < sb.n_map * RC; e += nt) {
-                const int i = e / RC, r = e - i * RC;
-                T sum = (T)0;
-                if (sb.trans) {
-                    for (int j = 0; j < nin; ++j) sum += mat[j * mc + i] * xin[j * RC + r];
-                } else {
-                    const T *mrow = mat + i * mc;
-                    for (int j = 0; j < nin; ++j) sum += mrow[j] * xin[j * RC + r];
+            for (int q0 = 0; q0 < nmap; q0 += 64) {
+                const int q = q0 + lane;
+                if (q < nmap) {
+                    T a[RC];
+#pragma unroll
+                    for (int r = 0; r < RC; ++r) a[r] = (T)0;
+                    const T *mp = vals + sb.mat_off + q;
+                    int j = 0;
+                    for (; j + 4 <= nin; j += 4) {
+                        const T m0 = mp[(int64_t)(j + 0) * nmap];
+                        const T m1 = mp[(int64_t)(j + 1) * nmap];
+                        const T m2 = mp[(int64_t)(j + 2) * nmap];
+                        const T m3 = mp[(int64_t)(j + 3) * nmap];
+#pragma unroll
+                        for (int r = 0; r < RC; ++r) {
+                            a[r] += m0 * xin[(j + 0) * RC + r];
+                            a[r] += m1 * xin[(j + 1) * RC + r];
+                            a[r] += m2 * xin[(j + 2) * RC + r];
+                            a[r] += m3 * xin[(j + 3) * RC + r];
+                        }
+                    }
+                    for (; j < nin; ++j) {
+                        const T m0 = mp[(int64_t)j * nmap];
+#pragma unroll
+                        for (int r = 0; r < RC; ++r) a[r] += m0 * xin[j * RC + r];
+                    }
+                    const int pos = map[q];
+#pragma unroll
+                    for (int r = 0; r < RC; ++r) acc[pos * RC + r] += a[r];
                 }
-                acc[map[i] * RC + r] += sum;
             }
         }
         __syncthreads();
         if (sb.n_dir > 0) {
             const int32_t *dir = idx + sb.dir_off;
-            for (int e = tid; e < sb.n_dir * RC; e += nt) {
+            for (int e = lane; e < sb.n_dir * RC; e += 64) {
                 const int d = e / RC, r = e - d * RC;
-                acc[dir[2 * d + 1] * RC + r] += src[(int64_t)dir[2 * d] * sstride + r];
+                if (r < rc) acc[dir[2 * d + 1] * RC + r] += src[(int64_t)dir[2 * d] * sstride + r];
             }
         }
     }
     __syncthreads();
     if (op.dst == kOut) {
-        for (int e = tid; e < n_out * RC; e += nt) {
+        for (int e = lane; e < n_out * RC; e += 64) {
             const int i = e / RC, r = e - i * RC;
-            T *d = out + (op.dst_row + i) * out_stride + r;
-            *d += acc[e];
+            if (r < rc) out[(op.dst_row + i) * out_stride + r] = acc[e];
         }
     } else {
         T *dst = op.dst == kScrA ? scrA : scrB;
-        for (int e = tid; e < n_out * RC; e += nt) dst[op.dst_row * RC + e] = acc[e];
+        for (int e = lane; e < n_out * RC; e += 64) dst[op.dst_row * RC + e] = acc[e];
     }
 }
 
@@ -210,7 +222,6 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
     const DeviceProgramDir &pd = fwd ? p.fwd : p.adj;
     T *X = (T *)p.d_X, *Y = (T *)p.d_Y;
     T *scrA = (T *)p.d_scrA, *scrB = (T *)p.d_scrB;
-    const T *vals = (const T *)p.d_vals;
     const int64_t xmax = p.max_task_cols * (int64_t)R;
     if (fwd) {
         hipLaunchKernelGGL((k_pack<T>), dim3(blocks_for(xmax), nt), dim3(256), 0, s, N, batch, t_lo, p.d_x_off,
@@ -221,21 +232,27 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
     }
     T *in = fwd ? X : Y;
     T *out = fwd ? Y : X;
-    const std::vector<int64_t> &ooff = fwd ? p.y_off_h : p.x_off_h;
-    const int64_t orow0 = ooff[t_lo], orows = ooff[t_hi + 1] - ooff[t_lo];
+    const T *vals = (const T *)pd.d_vals;
     const int RC = p.RC;
-    const size_t lds = sizeof(T) * ((size_t)(pd.max_out + pd.max_in) * RC + (size_t)pd.max_mat);
     for (int c0 = 0; c0 < R; c0 += RC) {
         const int rc = std::min(RC, R - c0);
-        hipLaunchKernelGGL((k_zero_cols<T>), dim3(blocks_for(orows * rc)), dim3(256), 0, s, out, orow0, orows,
-                           (int64_t)R, c0, rc);
         for (size_t st = 0; st < pd.stage_task_first.size(); ++st) {
             const std::vector<int32_t> &tf = pd.stage_task_first[st];
             const int ob = tf[t_lo], oe = tf[t_hi + 1];
             if (oe <= ob) continue;
-            hipLaunchKernelGGL((k_ops<T>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs, pd.d_idx, vals,
-                               ob, (const T *)(in + c0), (int64_t)R, out + c0, (int64_t)R, scrA, scrB, rc,
-                               pd.max_out, pd.max_in);
+            const Stage &sg = pd.stages[st];
+            const int mo = std::max(1, (int)sg.max_out), mi = std::max(1, (int)sg.max_in);
+            const size_t lds = sizeof(T) * (size_t)(mo + mi) * RC;
+#define SHT_OPS_LAUNCH(RCV)                                                                                      \
+    hipLaunchKernelGGL((k_ops<T, RCV>), dim3(oe - ob), dim3(64), lds, s, pd.d_ops, pd.d_subs, pd.d_idx, vals, ob, \
+                       (const T *)(in + c0), (int64_t)R, out + c0, (int64_t)R, scrA, scrB, rc, mo)
+            if (RC == 4)
+                SHT_OPS_LAUNCH(4);
+            else if (RC == 8)
+                SHT_OPS_LAUNCH(8);
+            else
+                SHT_OPS_LAUNCH(16);
+#undef SHT_OPS_LAUNCH
         }
     }
     if (fwd) {
@@ -251,10 +268,14 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
 }  // namespace
 
 hipError_t set_kernel_attributes() {
-    hipError_t e = hipFuncSetAttribute((const void *)&k_ops<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)&k_ops<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    const void *fns[] = {(const void *)&k_ops<double, 4>, (const void *)&k_ops<double, 8>,
+                         (const void *)&k_ops<double, 16>, (const void *)&k_ops<float, 4>,
+                         (const void *)&k_ops<float, 8>, (const void *)&k_ops<float, 16>};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t run_device(const DeviceProgram &p, int dtype, int batch, int a_lo, int a_hi, int dir, const void *in,

@@ -11,8 +11,7 @@ namespace sht {
 namespace idbf {
 
 struct PackedPlan {
-    std::vector<double> vals;
-    Program fwd, adj;
+    Program fwd, adj;  // each with its own output-major value stream
     std::vector<int64_t> x_off, y_off;  // panel row offsets per task (+ total)
 };
 

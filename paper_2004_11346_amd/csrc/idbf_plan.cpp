@@ -20,14 +20,21 @@ hipError_t up(const std::vector<V> &h, V **d) {
     return hipMemcpy(*d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice);
 }
 
-hipError_t upload_dir(const Program &p, int ntask, DeviceProgramDir &d) {
+hipError_t upload_dir(Program &p, int ntask, int dtype, DeviceProgramDir &d) {
     hipError_t e;
+    d.n_vals = (int64_t)p.vals.size();
+    if (dtype == SHT_F64) {
+        if ((e = up(p.vals, (double **)&d.d_vals)) != hipSuccess) return e;
+    } else {
+        std::vector<float> vf(p.vals.begin(), p.vals.end());
+        if ((e = up(vf, (float **)&d.d_vals)) != hipSuccess) return e;
+    }
+    p.vals.clear();
+    p.vals.shrink_to_fit();
     if ((e = up(p.ops, &d.d_ops)) != hipSuccess) return e;
     if ((e = up(p.subs, &d.d_subs)) != hipSuccess) return e;
     if ((e = up(p.idx, &d.d_idx)) != hipSuccess) return e;
-    d.max_out = std::max(1, p.max_n_out);
-    d.max_in = std::max(1, p.max_n_in);
-    d.max_mat = std::max(1, p.max_mat);
+    d.stages = p.stages;
     d.stage_task_first.clear();
     for (const Stage &st : p.stages) {
         std::vector<int32_t> tf(ntask + 1);
@@ -52,10 +59,10 @@ int fail(hipError_t e, const char *what) {
 }  // namespace
 
 void DeviceProgram::release() {
-    for (void *p : {d_vals, d_X, d_Y, d_scrA, d_scrB, (void *)d_x_off, (void *)fwd.d_ops, (void *)fwd.d_subs,
-                    (void *)fwd.d_idx, (void *)adj.d_ops, (void *)adj.d_subs, (void *)adj.d_idx})
+    for (void *p : {d_X, d_Y, d_scrA, d_scrB, (void *)d_x_off, fwd.d_vals, (void *)fwd.d_ops, (void *)fwd.d_subs,
+                    (void *)fwd.d_idx, adj.d_vals, (void *)adj.d_ops, (void *)adj.d_subs, (void *)adj.d_idx})
         if (p) (void)hipFree(p);
-    d_vals = d_X = d_Y = d_scrA = d_scrB = nullptr;
+    d_X = d_Y = d_scrA = d_scrB = nullptr;
     d_x_off = nullptr;
     fwd = DeviceProgramDir();
     adj = DeviceProgramDir();
@@ -76,7 +83,8 @@ int build_program(int N, const LegendreTables &lt, const sht_plan_opts &opts, Ho
     int64_t idx_bytes = 4 * (int64_t)(out.packed.fwd.idx.size() + out.packed.adj.idx.size()) +
                         (int64_t)(out.packed.fwd.ops.size() + out.packed.adj.ops.size()) * sizeof(Op) +
                         (int64_t)(out.packed.fwd.subs.size() + out.packed.adj.subs.size()) * sizeof(SubOp);
-    os << base << ",\"value_stream\":" << out.packed.vals.size() << ",\"index_bytes\":" << idx_bytes
+    os << base << ",\"fwd_values\":" << out.packed.fwd.vals.size() << ",\"adj_values\":" << out.packed.adj.vals.size()
+       << ",\"index_bytes\":" << idx_bytes
        << ",\"fwd_stages\":" << out.packed.fwd.stages.size() << ",\"fwd_work_stages\":"
        << out.packed.fwd.n_work_stages << ",\"adj_stages\":" << out.packed.adj.stages.size()
        << ",\"fwd_ops\":" << out.packed.fwd.ops.size() << ",\"scratch_rows\":"
@@ -87,23 +95,16 @@ int build_program(int N, const LegendreTables &lt, const sht_plan_opts &opts, Ho
 
 int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, DeviceProgram &d) {
     hipError_t e;
-    const PackedPlan &pk = hp.packed;
+    PackedPlan &pk = hp.packed;
     const int N = hp.N, ntask = 4 * N;
     d.N = N;
     d.batch = batch;
     d.dtype = dtype;
     const int R = 4 * batch;
-    d.RC = std::min(R, dtype == SHT_F64 ? 16 : 32);
+    d.RC = R <= 4 ? 4 : R <= 8 ? 8 : 16;
     d.d_wh = d_wh;
-    d.n_vals = (int64_t)pk.vals.size();
-    if (dtype == SHT_F64) {
-        if ((e = up(pk.vals, (double **)&d.d_vals)) != hipSuccess) return fail(e, "upload values");
-    } else {
-        std::vector<float> vf(pk.vals.begin(), pk.vals.end());
-        if ((e = up(vf, (float **)&d.d_vals)) != hipSuccess) return fail(e, "upload values");
-    }
-    if ((e = upload_dir(pk.fwd, ntask, d.fwd)) != hipSuccess) return fail(e, "upload program");
-    if ((e = upload_dir(pk.adj, ntask, d.adj)) != hipSuccess) return fail(e, "upload program");
+    if ((e = upload_dir(hp.packed.fwd, ntask, dtype, d.fwd)) != hipSuccess) return fail(e, "upload program");
+    if ((e = upload_dir(hp.packed.adj, ntask, dtype, d.adj)) != hipSuccess) return fail(e, "upload program");
     d.x_off_h = pk.x_off;
     d.y_off_h = pk.y_off;
     if ((e = up(pk.x_off, &d.d_x_off)) != hipSuccess) return fail(e, "upload offsets");
@@ -118,9 +119,6 @@ int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, De
     if ((e = hipMalloc(&d.d_scrA, es * sr * d.RC)) != hipSuccess) return fail(e, "scratch");
     if ((e = hipMalloc(&d.d_scrB, es * sr * d.RC)) != hipSuccess) return fail(e, "scratch");
     if ((e = set_kernel_attributes()) != hipSuccess) return fail(e, "kernel attributes");
-    // the host copy of the value stream is no longer needed
-    hp.packed.vals.clear();
-    hp.packed.vals.shrink_to_fit();
     d.valid = true;
     return SHT_OK;
 }
