@@ -121,6 +121,106 @@ __global__ __launch_bounds__(64) void k_ops(const Op *__restrict__ ops, const Su
     }
 }
 
+// FP64 matrix-core variant for many right-hand sides (RCW columns per pass):
+// v_mfma_f64_16x16x4f64 with A = 16 outputs x 4 inputs of the output-major
+// matrix (read straight from HBM, 4 x 128-byte segments per wave) and B = 4
+// gathered input rows x 16 columns from LDS.  Wave w owns output tiles
+// w, w + 4, ... of a sub-op and all RCW / 16 column blocks, so each A fragment
+// feeds RCW / 16 MFMAs; the sub-op's A fragments (n_in <= 64, i.e. at most 16
+// k-steps) are loaded before the first MFMA.  Result element i of lane l is
+// output row l/16 + 4 i, column l % 16.
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <int RCW>
+__global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, const SubOp *__restrict__ subs,
+                                                  const int32_t *__restrict__ idx, const double *__restrict__ vals,
+                                                  int op_begin, const double *__restrict__ in, int64_t in_stride,
+                                                  double *__restrict__ out, int64_t out_stride,
+                                                  double *__restrict__ scrA, double *__restrict__ scrB, int rc,
+                                                  int max_out) {
+    constexpr int NCB = RCW / 16;
+    extern __shared__ unsigned char smem_raw[];
+    double *acc = reinterpret_cast<double *>(smem_raw);
+    double *xin = acc + (size_t)max_out * RCW;
+    const Op op = ops[op_begin + blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n_out = op.n_out;
+    for (int e = tid; e < n_out * RCW; e += 256) acc[e] = 0.0;
+    for (int s = 0; s < op.nsub; ++s) {
+        const SubOp sb = subs[op.sub0 + s];
+        const double *src;
+        int64_t sstride;
+        if (sb.src == kIn) {
+            src = in;
+            sstride = in_stride;
+        } else {
+            src = sb.src == kScrA ? scrA : scrB;
+            sstride = RCW;
+        }
+        __syncthreads();
+        const int nin = sb.n_in, nmap = sb.n_map;
+        if (nmap > 0) {
+            const int32_t *inr = idx + sb.in_off;
+            const int nin4 = (nin + 3) & ~3;
+            for (int e = tid; e < nin4 * RCW; e += 256) {
+                const int j = e / RCW, c = e - j * RCW;
+                xin[e] = (j < nin && c < rc) ? src[(int64_t)inr[j] * sstride + c] : 0.0;
+            }
+            __syncthreads();
+            const int32_t *map = idx + sb.map_off;
+            const int ntile = (nmap + 15) >> 4;
+            const int jl = lane >> 4, cl = lane & 15;
+            for (int t = wave; t < ntile; t += 4) {
+                const int q = t * 16 + cl;
+                double areg[16];
+#pragma unroll
+                for (int st = 0; st < 16; ++st) {
+                    const int j = 4 * st + jl;
+                    areg[st] = (q < nmap && j < nin) ? vals[sb.mat_off + (int64_t)j * nmap + q] : 0.0;
+                }
+                d4v D[NCB];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) D[cb] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int st = 0; st < 16; ++st) {
+                    if (4 * st >= nin) break;
+                    const double *xr = xin + (4 * st + jl) * RCW + cl;
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb)
+                        D[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[st], xr[cb * 16], D[cb], 0, 0, 0);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int qq = t * 16 + jl + 4 * i;
+                    if (qq < nmap) {
+                        double *ar = acc + map[qq] * RCW + cl;
+#pragma unroll
+                        for (int cb = 0; cb < NCB; ++cb) ar[cb * 16] += D[cb][i];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (sb.n_dir > 0) {
+            const int32_t *dir = idx + sb.dir_off;
+            for (int e = tid; e < sb.n_dir * RCW; e += 256) {
+                const int d = e / RCW, c = e - d * RCW;
+                if (c < rc) acc[dir[2 * d + 1] * RCW + c] += src[(int64_t)dir[2 * d] * sstride + c];
+            }
+        }
+    }
+    __syncthreads();
+    if (op.dst == kOut) {
+        for (int e = tid; e < n_out * RCW; e += 256) {
+            const int i = e / RCW, c = e - i * RCW;
+            if (c < rc) out[(op.dst_row + i) * out_stride + c] = acc[e];
+        }
+    } else {
+        double *dst = op.dst == kScrA ? scrA : scrB;
+        for (int e = tid; e < n_out * RCW; e += 256) dst[op.dst_row * RCW + e] = acc[e];
+    }
+}
+
 // beta -> X panels for tasks [t_lo, t_hi] (orders a_lo..a_hi, both parities).
 // grid: (ceil(max_cols * R / 256), ntasks), block 256.
 template <typename T>
@@ -233,7 +333,8 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
     T *in = fwd ? X : Y;
     T *out = fwd ? Y : X;
     const T *vals = (const T *)pd.d_vals;
-    const int RC = p.RC;
+    const bool mfma = sizeof(T) == 8 && p.RCW > 0;
+    const int RC = mfma ? p.RCW : p.RC;
     for (int c0 = 0; c0 < R; c0 += RC) {
         const int rc = std::min(RC, R - c0);
         for (size_t st = 0; st < pd.stage_task_first.size(); ++st) {
@@ -241,8 +342,26 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
             const int ob = tf[t_lo], oe = tf[t_hi + 1];
             if (oe <= ob) continue;
             const Stage &sg = pd.stages[st];
-            const int mo = std::max(1, (int)sg.max_out), mi = std::max(1, (int)sg.max_in);
+            const int mo = std::max(1, (int)sg.max_out), mi = std::max(4, ((int)sg.max_in + 3) & ~3);
             const size_t lds = sizeof(T) * (size_t)(mo + mi) * RC;
+            if (mfma) {
+                const double *vd = (const double *)vals;
+                const double *ind = (const double *)(in + c0);
+                double *outd = (double *)(out + c0);
+                if (RC == 128)
+                    hipLaunchKernelGGL((k_ops_mfma<128>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
+                                       pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
+                                       (double *)scrB, rc, mo);
+                else if (RC == 64)
+                    hipLaunchKernelGGL((k_ops_mfma<64>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
+                                       pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
+                                       (double *)scrB, rc, mo);
+                else
+                    hipLaunchKernelGGL((k_ops_mfma<32>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
+                                       pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
+                                       (double *)scrB, rc, mo);
+                continue;
+            }
 #define SHT_OPS_LAUNCH(RCV)                                                                                      \
     hipLaunchKernelGGL((k_ops<T, RCV>), dim3(oe - ob), dim3(64), lds, s, pd.d_ops, pd.d_subs, pd.d_idx, vals, ob, \
                        (const T *)(in + c0), (int64_t)R, out + c0, (int64_t)R, scrA, scrB, rc, mo)
@@ -268,9 +387,11 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
 }  // namespace
 
 hipError_t set_kernel_attributes() {
-    const void *fns[] = {(const void *)&k_ops<double, 4>, (const void *)&k_ops<double, 8>,
-                         (const void *)&k_ops<double, 16>, (const void *)&k_ops<float, 4>,
-                         (const void *)&k_ops<float, 8>, (const void *)&k_ops<float, 16>};
+    const void *fns[] = {(const void *)&k_ops<double, 4>,   (const void *)&k_ops<double, 8>,
+                         (const void *)&k_ops<double, 16>,  (const void *)&k_ops<float, 4>,
+                         (const void *)&k_ops<float, 8>,    (const void *)&k_ops<float, 16>,
+                         (const void *)&k_ops_mfma<32>,     (const void *)&k_ops_mfma<64>,
+                         (const void *)&k_ops_mfma<128>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;

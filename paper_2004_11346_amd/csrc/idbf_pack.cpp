@@ -29,7 +29,7 @@ namespace idbf {
 namespace {
 
 constexpr int kTile = 64;     // output rows per final op
-constexpr int kMaxIn = 128;   // gathered rows per sub-op
+constexpr int kMaxIn = 64;    // gathered rows per sub-op
 
 // A product M(:, :) x with M(i, j) = trans ? mb[j * ld + i] : mb[i * ld + j]
 // restricted to the outputs out_idx, landing at positions map (level-local
@@ -456,24 +456,33 @@ void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t>
             Level &lv = b.levels[l];
             for (size_t q = 0; q < lv.ops.size(); ++q) {
                 const LOp &lo = lv.ops[q];
-                Op op{};
-                op.n_out = lo.n_out;
-                op.dst = (s & 1) ? kScrB : kScrA;
-                op.dst_row = bbase[bi][l] + lv.off[q];
-                std::vector<SubOp> subs;
-                for (const LSub &ls : lo.subs) {
-                    int buf;
-                    int64_t base;
-                    srcinfo(bi, ls.src_level, buf, base);
-                    std::vector<int> sel(ls.out_idx.size()), dsel(ls.dir.size());
-                    for (size_t i = 0; i < sel.size(); ++i) sel[i] = (int)i;
-                    for (size_t i = 0; i < dsel.size(); ++i) dsel[i] = (int)i;
-                    em.emit(ls, sel, dsel, buf, base, 0, subs);
+                // outputs in chunks of at most kTile rows; every chunk keeps the
+                // matrix outputs and identity terms that land in it
+                for (int p0 = 0; p0 < std::max(lo.n_out, 1); p0 += kTile) {
+                    const int p1 = std::min(lo.n_out, p0 + kTile);
+                    Op op{};
+                    op.n_out = std::max(0, p1 - p0);
+                    op.dst = (s & 1) ? kScrB : kScrA;
+                    op.dst_row = bbase[bi][l] + lv.off[q] + p0;
+                    std::vector<SubOp> subs;
+                    for (const LSub &ls : lo.subs) {
+                        int buf;
+                        int64_t base;
+                        srcinfo(bi, ls.src_level, buf, base);
+                        std::vector<int> sel, dsel;
+                        for (size_t i = 0; i < ls.map.size(); ++i)
+                            if (ls.map[i] >= p0 && ls.map[i] < p1) sel.push_back((int)i);
+                        for (size_t i = 0; i < ls.dir.size(); ++i)
+                            if (ls.dir[i].second >= p0 && ls.dir[i].second < p1) dsel.push_back((int)i);
+                        if (sel.empty() && dsel.empty()) continue;
+                        em.emit(ls, sel, dsel, buf, base, p0, subs);
+                    }
+                    op.nsub = (int32_t)subs.size();
+                    st_ops[s].push_back(op);
+                    st_task[s].push_back(b.task);
+                    st_subs[s].push_back(std::move(subs));
+                    if (lo.n_out == 0) break;
                 }
-                op.nsub = (int32_t)subs.size();
-                st_ops[s].push_back(op);
-                st_task[s].push_back(b.task);
-                st_subs[s].push_back(std::move(subs));
             }
         }
     }

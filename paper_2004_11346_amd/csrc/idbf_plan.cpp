@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstdio>
 #include <sstream>
 
@@ -102,6 +103,14 @@ int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, De
     d.dtype = dtype;
     const int R = 4 * batch;
     d.RC = R <= 4 ? 4 : R <= 8 ? 8 : 16;
+    // FP64 with many right-hand sides: matrix-core executor, 32/64/128 columns
+    // per pass (SHT_IDBF_RCW overrides the choice; 0 disables)
+    d.RCW = 0;
+    if (dtype == SHT_F64 && R >= 32) d.RCW = R >= 128 ? 64 : 32;
+    if (const char *e = std::getenv("SHT_IDBF_RCW")) {
+        int v = std::atoi(e);
+        d.RCW = (dtype == SHT_F64 && (v == 32 || v == 64 || v == 128)) ? v : 0;
+    }
     d.d_wh = d_wh;
     if ((e = upload_dir(hp.packed.fwd, ntask, dtype, d.fwd)) != hipSuccess) return fail(e, "upload program");
     if ((e = upload_dir(hp.packed.adj, ntask, dtype, d.adj)) != hipSuccess) return fail(e, "upload program");
@@ -116,8 +125,9 @@ int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, De
     if ((e = hipMalloc(&d.d_Y, es * std::max<int64_t>(1, pk.y_off[ntask]) * R)) != hipSuccess)
         return fail(e, "Y panels");
     const int64_t sr = std::max<int64_t>(1, std::max(pk.fwd.scr_rows, pk.adj.scr_rows));
-    if ((e = hipMalloc(&d.d_scrA, es * sr * d.RC)) != hipSuccess) return fail(e, "scratch");
-    if ((e = hipMalloc(&d.d_scrB, es * sr * d.RC)) != hipSuccess) return fail(e, "scratch");
+    const int64_t sw = std::max(d.RC, d.RCW);
+    if ((e = hipMalloc(&d.d_scrA, es * sr * sw)) != hipSuccess) return fail(e, "scratch");
+    if ((e = hipMalloc(&d.d_scrB, es * sr * sw)) != hipSuccess) return fail(e, "scratch");
     if ((e = set_kernel_attributes()) != hipSuccess) return fail(e, "kernel attributes");
     d.valid = true;
     return SHT_OK;

@@ -122,3 +122,20 @@ def test_idbf_n1024_sampled():
             sel = m_of == m
             worst = max(worst, rel_l2(bo[sel], bref[i, s, : 2 * N - a]))
     assert worst <= 1e-11, worst
+
+
+@pytest.mark.parametrize("N,batch,rcw", [(64, 8, None), (40, 33, None), (64, 32, "128"), (64, 9, "64")])
+def test_idbf_matrix_core_path(N, batch, rcw, monkeypatch):
+    """Many right-hand sides take the FP64 MFMA executor (32/64/128 columns per
+    pass, partial last pass when 4*batch is not a multiple)."""
+    print(f"idbf mfma N={N} batch={batch} rcw={rcw}", flush=True)
+    if rcw:
+        monkeypatch.setenv("SHT_IDBF_RCW", rcw)
+    p = _plan(N, batch, n0=32, leaf=8)
+    beta = inputs.make_beta(N, batch, 6)
+    f = p.forward(_dev(beta)).cpu().numpy()
+    grid = inputs.make_grid(N, batch, 6)
+    bi = p.inverse(_dev(grid)).cpu().numpy()
+    for b in sorted({0, batch // 2, batch - 1}):
+        assert rel_l2(f[b], oracle.sht_forward(N, beta[b])) <= 1e-11
+        assert rel_l2(bi[b], oracle.sht_inverse(N, grid[b])) <= 1e-11
