@@ -41,8 +41,10 @@ struct sht_plan {
     dev::DftPlan dft;
     // workspace
     void *d_g = nullptr;         // [batch][2N][M] complex (dtype)
-    double *d_hbuf = nullptr;    // dense transposed-ALT fold buffer
-    double *d_part = nullptr;    // dense transposed-ALT chunk partials
+    void *d_X = nullptr;         // dense path FP64 panels
+    void *d_Y = nullptr;
+    int64_t *d_x_off = nullptr;
+    dev::DensePanels panels;
     // IDBF program (device)
     idbf::DeviceProgram prog;
     std::string stats;
@@ -63,8 +65,9 @@ sht_plan::~sht_plan() {
     dfree(d_tw2);
     dfree(d_tw2f);
     dfree(d_g);
-    dfree(d_hbuf);
-    dfree(d_part);
+    dfree(d_X);
+    dfree(d_Y);
+    dfree(d_x_off);
     prog.release();
 }
 
@@ -183,10 +186,6 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
         set_error_detail("phi DFT row does not fit in LDS for this N and dtype");
         return SHT_ERR_UNSUPPORTED;
     }
-    if (method == SHT_DENSE && 4 * batch > 128) {
-        set_error_detail("dense transposed ALT supports at most 32 fields per call");
-        return SHT_ERR_UNSUPPORTED;
-    }
 
     LegendreTables lt;
     try {
@@ -239,10 +238,22 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
     const size_t gbytes = 2 * elt_size(dtype) * (size_t)batch * 2 * N * p->M;
     HIP_TRY(hipMalloc(&p->d_g, gbytes), "workspace g");
     if (method == SHT_DENSE) {
-        const size_t hb = sizeof(double) * (size_t)2 * N * 2 * N * 4 * batch;
-        HIP_TRY(hipMalloc((void **)&p->d_hbuf, hb), "workspace fold");
-        size_t pb = dev::dense_part_bytes(N, batch);
-        if (pb) HIP_TRY(hipMalloc((void **)&p->d_part, pb), "workspace partials");
+        // FP64 panels: X [sum of half-matrix columns][R], Y [4N^2][R]
+        std::vector<int64_t> xo(4 * (size_t)N + 1, 0);
+        int64_t maxc = 0;
+        for (int t = 0; t < 4 * N; ++t) {
+            const int c = half_cols(N, t / 2, t % 2);
+            xo[t + 1] = xo[t] + std::max(0, c);
+            maxc = std::max<int64_t>(maxc, c);
+        }
+        const size_t R = 4 * (size_t)batch;
+        HIP_TRY(hipMalloc(&p->d_X, sizeof(double) * std::max<int64_t>(1, xo[4 * N]) * R), "dense X panels");
+        HIP_TRY(hipMalloc(&p->d_Y, sizeof(double) * (size_t)4 * N * N * R), "dense Y panels");
+        if ((rc = upload(xo, &p->d_x_off, "upload panel offsets"))) return rc;
+        p->panels.X = p->d_X;
+        p->panels.Y = p->d_Y;
+        p->panels.x_off = p->d_x_off;
+        p->panels.max_cols = maxc;
     } else {
         idbf::HostProgram hp;
         int brc;
@@ -302,10 +313,10 @@ static int run_alt(const sht_plan_t *p, int a_lo, int a_hi, int dir, const void 
     hipError_t e;
     if (p->method == SHT_DENSE) {
         if (dir == SHT_FWD)
-            e = dev::alt_dense_forward(p->dense, p->dtype, p->batch, a_lo, a_hi, in, out, s);
+            e = dev::alt_dense_forward(p->dense, p->panels, p->dtype, p->batch, a_lo, a_hi, in, out, s);
         else
-            e = dev::alt_dense_transpose(p->dense, p->dtype, p->batch, a_lo, a_hi, dir == SHT_INV, in, out,
-                                         p->d_hbuf, p->d_part, s);
+            e = dev::alt_dense_transpose(p->dense, p->panels, p->dtype, p->batch, a_lo, a_hi, dir == SHT_INV, in,
+                                         out, s);
     } else {
         e = idbf::run(p->prog, p->dense, p->dtype, p->batch, a_lo, a_hi, dir, in, out, s);
     }

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include "idbf_device.h"
+#include "kernels.h"
 
 namespace sht {
 namespace idbf {
@@ -221,96 +222,6 @@ __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, co
     }
 }
 
-// beta -> X panels for tasks [t_lo, t_hi] (orders a_lo..a_hi, both parities).
-// grid: (ceil(max_cols * R / 256), ntasks), block 256.
-template <typename T>
-__global__ __launch_bounds__(256) void k_pack(int N, int batch, int t_lo, const int64_t *__restrict__ x_off,
-                                              const T *__restrict__ beta, T *__restrict__ X) {
-    const int task = t_lo + blockIdx.y;
-    const int a = task >> 1, par = task & 1;
-    const int64_t rows = x_off[task + 1] - x_off[task];
-    const int R = 4 * batch;
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= rows * R) return;
-    const int j = (int)(e / R), col = (int)(e - (int64_t)j * R);
-    const int f = col >> 2, s = (col >> 1) & 1, c = col & 1;
-    const int k = a + par + 2 * j;
-    T v = (T)0;
-    if (!(s == 1 && a == 0)) v = beta[2 * ((int64_t)f * 4 * N * N + d_coef_offset(N, s ? -a : a) + (k - a)) + c];
-    X[(x_off[task] + j) * R + col] = v;
-}
-
-// X panels -> beta (transposed direction)
-template <typename T>
-__global__ __launch_bounds__(256) void k_scatter(int N, int batch, int t_lo, const int64_t *__restrict__ x_off,
-                                                 const T *__restrict__ X, T *__restrict__ beta) {
-    const int task = t_lo + blockIdx.y;
-    const int a = task >> 1, par = task & 1;
-    const int64_t rows = x_off[task + 1] - x_off[task];
-    const int R = 4 * batch;
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= rows * R) return;
-    const int j = (int)(e / R), col = (int)(e - (int64_t)j * R);
-    const int f = col >> 2, s = (col >> 1) & 1, c = col & 1;
-    if (s == 1 && a == 0) return;
-    const int k = a + par + 2 * j;
-    beta[2 * ((int64_t)f * 4 * N * N + d_coef_offset(N, s ? -a : a) + (k - a)) + c] = X[(x_off[task] + j) * R + col];
-}
-
-// Y panels -> g columns (parity recombination, Section 3.1.2):
-// g(l = 2N-1-r) = E + O, g(l' = r) = E - O.  grid: (ceil(N * R / 256), orders).
-template <typename T>
-__global__ __launch_bounds__(256) void k_combine(int N, int M, int batch, int a_lo, const T *__restrict__ Y,
-                                                 T *__restrict__ g) {
-    const int a = a_lo + blockIdx.y;
-    const int R = 4 * batch;
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (int64_t)N * R) return;
-    const int r = (int)(e / R), col = (int)(e - (int64_t)r * R);
-    const int f = col >> 2, s = (col >> 1) & 1, c = col & 1;
-    if (s == 1 && a == 0) return;
-    const T E = Y[((int64_t)(2 * a) * N + r) * R + col];
-    const T O = Y[((int64_t)(2 * a + 1) * N + r) * R + col];
-    const int n = 2 * N;
-    const int cc = s ? M - a : a;
-    T *gb = g + 2 * ((int64_t)f * n * M);
-    gb[2 * ((int64_t)(n - 1 - r) * M + cc) + c] = E + O;
-    gb[2 * ((int64_t)r * M + cc) + c] = E - O;
-}
-
-// g columns -> Y panels: H_even = w (g(l) + g(l')), H_odd = w (g(l) - g(l')).
-template <typename T>
-__global__ __launch_bounds__(256) void k_fold(int N, int M, int batch, int a_lo, const double *__restrict__ wh,
-                                              const T *__restrict__ g, T *__restrict__ Y) {
-    const int a = a_lo + blockIdx.y;
-    const int R = 4 * batch;
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (int64_t)N * R) return;
-    const int r = (int)(e / R), col = (int)(e - (int64_t)r * R);
-    const int f = col >> 2, s = (col >> 1) & 1, c = col & 1;
-    T u = (T)0, v = (T)0;
-    const int n = 2 * N;
-    if (!(s == 1 && a == 0)) {
-        const int cc = s ? M - a : a;
-        const T *gb = g + 2 * ((int64_t)f * n * M);
-        u = gb[2 * ((int64_t)(n - 1 - r) * M + cc) + c];
-        v = gb[2 * ((int64_t)r * M + cc) + c];
-    }
-    const T w = wh ? (T)wh[r] : (T)1;
-    Y[((int64_t)(2 * a) * N + r) * R + col] = w * (u + v);
-    Y[((int64_t)(2 * a + 1) * N + r) * R + col] = w * (u - v);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_zero_cols(T *__restrict__ p, int64_t row0, int64_t rows, int64_t stride,
-                                                   int col0, int ncol) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= rows * ncol) return;
-    const int64_t r = e / ncol;
-    const int c = (int)(e - r * ncol);
-    p[(row0 + r) * stride + col0 + c] = (T)0;
-}
-
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 template <typename T>
@@ -322,14 +233,13 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
     const DeviceProgramDir &pd = fwd ? p.fwd : p.adj;
     T *X = (T *)p.d_X, *Y = (T *)p.d_Y;
     T *scrA = (T *)p.d_scrA, *scrB = (T *)p.d_scrB;
-    const int64_t xmax = p.max_task_cols * (int64_t)R;
-    if (fwd) {
-        hipLaunchKernelGGL((k_pack<T>), dim3(blocks_for(xmax), nt), dim3(256), 0, s, N, batch, t_lo, p.d_x_off,
-                           (const T *)inp, X);
-    } else {
-        hipLaunchKernelGGL((k_fold<T>), dim3(blocks_for((int64_t)N * R), a_hi - a_lo + 1), dim3(256), 0, s, N, M,
-                           batch, a_lo, dir == 1 ? p.d_wh : (const double *)nullptr, (const T *)inp, Y);
-    }
+    const int dt = sizeof(T) == 8 ? 0 : 1;
+    hipError_t pe;
+    if (fwd)
+        pe = dev::panel_pack(dt, false, N, batch, a_lo, a_hi, p.d_x_off, p.max_task_cols, inp, X, s);
+    else
+        pe = dev::panel_fold(dt, false, N, batch, a_lo, a_hi, dir == 1 ? p.d_wh : nullptr, inp, Y, s);
+    if (pe != hipSuccess) return pe;
     T *in = fwd ? X : Y;
     T *out = fwd ? Y : X;
     const T *vals = (const T *)pd.d_vals;
@@ -374,14 +284,8 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
 #undef SHT_OPS_LAUNCH
         }
     }
-    if (fwd) {
-        hipLaunchKernelGGL((k_combine<T>), dim3(blocks_for((int64_t)N * R), a_hi - a_lo + 1), dim3(256), 0, s, N,
-                           M, batch, a_lo, (const T *)Y, (T *)outp);
-    } else {
-        hipLaunchKernelGGL((k_scatter<T>), dim3(blocks_for(xmax), nt), dim3(256), 0, s, N, batch, t_lo, p.d_x_off,
-                           (const T *)X, (T *)outp);
-    }
-    return hipGetLastError();
+    if (fwd) return dev::panel_combine(dt, false, N, batch, a_lo, a_hi, Y, outp, s);
+    return dev::panel_scatter(dt, false, N, batch, a_lo, a_hi, p.d_x_off, p.max_task_cols, X, outp, s);
 }
 
 }  // namespace

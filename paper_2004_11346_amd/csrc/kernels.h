@@ -20,17 +20,35 @@ struct DenseTables {
     const double *coef = nullptr;   // [tri][2]
 };
 
+// FP64 panels used by the plain path when it runs on the matrix cores.
+struct DensePanels {
+    void *X = nullptr;             // [N (2N + 1)][R] coefficient panels
+    void *Y = nullptr;             // [4 N^2][R] half-grid panels
+    const int64_t *x_off = nullptr;  // device [4N + 1]
+    int64_t max_cols = 0;
+};
+bool dense_uses_panels(int batch);
+
 // Dense forward ALT for orders a_lo..a_hi (both signs): beta -> g columns.
-hipError_t alt_dense_forward(const DenseTables &t, int dtype, int batch, int a_lo, int a_hi,
+hipError_t alt_dense_forward(const DenseTables &t, const DensePanels &pn, int dtype, int batch, int a_lo, int a_hi,
                              const void *beta, void *g, hipStream_t s);
 
 // Dense transposed ALT (weights = true: inverse A^T W; false: adjoint A^T):
-// g columns -> beta.  hbuf: scratch of 2N*(a_hi-a_lo+1)*4*batch doubles;
-// part: scratch of dense_part_bytes(N, batch) bytes (may be null if 0).
-hipError_t alt_dense_transpose(const DenseTables &t, int dtype, int batch, int a_lo, int a_hi,
-                               bool weights, const void *g, void *beta, double *hbuf, double *part,
-                               hipStream_t s);
-size_t dense_part_bytes(int N, int batch);
+// g columns -> beta.
+hipError_t alt_dense_transpose(const DenseTables &t, const DensePanels &pn, int dtype, int batch, int a_lo,
+                               int a_hi, bool weights, const void *g, void *beta, hipStream_t s);
+
+// Panels (see kernels_panels.hip).  x_off: device [4N + 1] row offsets of
+// the X panels; the Y panel of task t starts at row t * N.
+// dtype: element type of beta / g; panel64: panels in FP64 (else same type).
+hipError_t panel_pack(int dtype, bool panel64, int N, int batch, int a_lo, int a_hi, const int64_t *x_off,
+                      int64_t max_cols, const void *beta, void *X, hipStream_t s);
+hipError_t panel_scatter(int dtype, bool panel64, int N, int batch, int a_lo, int a_hi, const int64_t *x_off,
+                         int64_t max_cols, const void *X, void *beta, hipStream_t s);
+hipError_t panel_combine(int dtype, bool panel64, int N, int batch, int a_lo, int a_hi, const void *Y, void *g,
+                         hipStream_t s);
+hipError_t panel_fold(int dtype, bool panel64, int N, int batch, int a_lo, int a_hi, const double *wh,
+                      const void *g, void *Y, hipStream_t s);
 
 // Length-M DFT of every grid row (Section 1, phi sums), LDS resident.
 struct DftPlan {
