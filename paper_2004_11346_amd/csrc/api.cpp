@@ -37,6 +37,7 @@ struct sht_plan {
     int *d_dexp = nullptr;
     double *d_tw2 = nullptr;
     float *d_tw2f = nullptr;
+    int *d_src_pos = nullptr;
     dev::DenseTables dense;
     dev::DftPlan dft;
     // workspace
@@ -64,6 +65,7 @@ sht_plan::~sht_plan() {
     dfree(d_dexp);
     dfree(d_tw2);
     dfree(d_tw2f);
+    dfree(d_src_pos);
     dfree(d_g);
     dfree(d_X);
     dfree(d_Y);
@@ -91,18 +93,6 @@ int upload(const std::vector<V> &h, V **d, const char *what) {
     HIP_TRY(hipMalloc((void **)d, std::max<size_t>(1, h.size() * sizeof(V))), what);
     if (!h.empty()) HIP_TRY(hipMemcpy(*d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice), what);
     return SHT_OK;
-}
-
-std::vector<int> prime_factors(int M) {
-    std::vector<int> f;
-    for (int p = 2; (long long)p * p <= M; ++p)
-        while (M % p == 0) {
-            f.push_back(p);
-            M /= p;
-        }
-    if (M > 1) f.push_back(M);
-    std::sort(f.rbegin(), f.rend());
-    return f;
 }
 
 int check_ptr(const void *p, size_t align) {
@@ -213,11 +203,17 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
 
     // phi DFT: radices and the e^{i pi r / M} table (long double, rounded)
     {
-        std::vector<int> f = prime_factors(p->M);
+        std::vector<int> f, bl, sp;
+        dev::dft_passes(p->M, f, bl, sp);
         p->dft.N = N;
         p->dft.M = p->M;
         p->dft.nrad = (int)f.size();
-        for (size_t i = 0; i < f.size(); ++i) p->dft.radix[i] = f[i];
+        for (size_t i = 0; i < f.size(); ++i) {
+            p->dft.radix[i] = f[i];
+            p->dft.blen[i] = bl[i];
+        }
+        if ((rc = upload(sp, &p->d_src_pos, "upload DFT positions"))) return rc;
+        p->dft.src_pos = p->d_src_pos;
         std::vector<double> tw(4 * (size_t)p->M);
         std::vector<float> twf(4 * (size_t)p->M);
         const long double pi = 3.141592653589793238462643383279502884L;

@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace sht {
 namespace dev {
@@ -54,11 +55,15 @@ hipError_t panel_fold(int dtype, bool panel64, int N, int batch, int a_lo, int a
 struct DftPlan {
     int N = 0, M = 0;
     int nrad = 0;
-    int radix[24] = {0};
+    int radix[24] = {0};          // prime factors of M, largest first
+    int blen[24] = {0};           // block length before each pass
     const double *tw2 = nullptr;  // [2M][2]: exp(i pi r / M), r in [0, 2M)
     const float *tw2f = nullptr;  // same in float
+    const int *src_pos = nullptr;  // [M]: LDS slot holding output index c
 };
 bool dft_supported(int M, int dtype);
+// host: radices, block lengths and the output position table for length M
+void dft_passes(int M, std::vector<int> &radix, std::vector<int> &blen, std::vector<int> &src_pos);
 // synthesis in place on f: f[l][j] = sum_m g[l][m mod M] e^{i m phi_j}
 hipError_t dft_synthesis(const DftPlan &p, int dtype, int batch, void *f, hipStream_t s);
 // analysis f -> g: g[l][m mod M] = scale * sum_j f[l][j] e^{-i m phi_j}
