@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-details", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--profile-target", action="store_true",
+                    help="only a 1 GiB device copy (counter scale) and a few ALT calls, for rocprofv3 runs")
     return ap.parse_args()
 
 
@@ -119,6 +121,111 @@ def cpu_baseline(N: int):
     }
 
 
+# HBM bytes per ALT call read from rocprofv3 counters (FETCH_SIZE and
+# WRITE_SIZE in separate runs, see profiles/), scaled by the ratio that the
+# same counters give for a 1 GiB device copy.  Each entry is keyed on the
+# SHA-256 of the kernel sources it was measured with; a changed source makes
+# the figure stale and it is reported as null.
+TRAFFIC = {
+    ("dense", 1024, 32, "f64", "k_dense_fwd_mfma"): {"bytes_per_call": 24.066e9, "sha": "6c367b5d614a6eb1",
+                                                     "profile": "profiles/alt_fwd_dense_n1024_b32_f64.md"},
+    ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7339e9, "sha": "6c367b5d614a6eb1",
+                                                    "profile": "profiles/alt_fwd_dense_n1024_b1_f64.md"},
+    ("idbf", 1024, 32, "f64", "k_ops_mfma"): {"bytes_per_call": 67.708e9, "sha": "9c31bca4b508372d",
+                                               "profile": "profiles/alt_fwd_idbf_n1024_b32_f64.md"},
+    ("idbf", 1024, 1, "f64", "k_ops"): {"bytes_per_call": 11.774e9, "sha": "9c31bca4b508372d",
+                                         "profile": "profiles/alt_fwd_idbf_n1024_b1_f64.md"},
+}
+
+
+def kernel_source_sha(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2004_11346_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+DOMINANT = {
+    # method, uses matrix cores -> (kernel label, source files)
+    ("dense", True): ("k_dense_fwd_mfma", ["kernels_dense.hip"]),
+    ("dense", False): ("k_dense_fwd_valu", ["kernels_dense.hip"]),
+    ("idbf", True): ("k_ops_mfma", ["idbf_kernels.hip", "idbf_pack.cpp"]),
+    ("idbf", False): ("k_ops", ["idbf_kernels.hip", "idbf_pack.cpp"]),
+}
+
+
+def roofline(method, N, batch, dtype, stats, kern, reps):
+    """Roofline object for the dominant kernel of the forward ALT.
+
+    Algorithmic work per ALT call (all orders, one batch):
+      plain form:  flops = 2 R N^2 (2N + 1)  (every entry of every half matrix
+                   times R = 4 batch real right-hand sides; FP64 MFMA bound)
+      fast form:   flops = 2 R nnz_plan; bytes = nnz_plan s + index bytes +
+                   batch (4N^2 + 2N M) c_s  (factor stream read once, vectors
+                   in and out; HBM bound below the FP64 ridge, R < 40)
+    The fast form runs as one launch per program stage; its "launch" here is
+    the sum over the stage launches of one call."""
+    M = 4 * N - 1
+    R = 4 * batch
+    sb = 8 if dtype == "f64" else 4
+    mfma_name = "k_dense_fwd_mfma" if method == "dense" else "k_ops_mfma"
+    uses_mfma = mfma_name in kern
+    label, files = DOMINANT[(method, uses_mfma)]
+    k = kern.get(label, {"launches": 0, "total_ms": float("nan")})
+    per_call_s = k["total_ms"] / reps / 1e3
+    launches_per_call = k["launches"] / reps
+    if method == "dense":
+        flops = 2.0 * R * N * N * (2 * N + 1)
+        bytes_ = batch * (4 * N * N + 2 * N * M) * 2 * sb
+    else:
+        prog = stats.get("program", {})
+        nnz = float(prog.get("stored_entries", 0))
+        flops = 2.0 * R * nnz
+        bytes_ = nnz * sb + float(prog.get("index_bytes", 0)) + batch * (4 * N * N + 2 * N * M) * 2 * sb
+    compute_bound = method == "dense" or (2.0 * R / sb) >= PEAK_FP64_TFLOPS / (PEAK_HBM_GBS / 1e3)
+    if compute_bound:
+        ach = flops / per_call_s / 1e12
+        peak = PEAK_FP64_TFLOPS
+        r = {"bound": "mfma" if uses_mfma else "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+             "frac": ach / peak}
+    else:
+        ach = bytes_ / per_call_s / 1e9
+        r = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS}
+    sha = kernel_source_sha(files)
+    t = TRAFFIC.get((method, N, batch, dtype, label))
+    r["traffic"] = t["bytes_per_call"] if t and t["sha"] == sha else None
+    r.update({"kernel": label, "launches_per_call": launches_per_call, "kernel_ms_per_call": per_call_s * 1e3,
+              "algorithmic_flops_per_call": flops, "algorithmic_bytes_per_call": bytes_, "kernel_src_sha": sha})
+    return r
+
+
+def profile_target(args):
+    """What the rocprofv3 counter runs measure: a plain 1 GiB device copy
+    (the counter scale), then `steps` forward ALT calls of the workload."""
+    import torch
+
+    import paper_2004_11346_amd.sht as S
+    from paper_2004_11346_amd import inputs
+    torch.cuda.init()
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    cdt = torch.complex128 if args.dtype == "f64" else torch.complex64
+    method = args.method or "idbf"
+    N, batch = args.N, args.batch
+    beta = torch.from_numpy(inputs.make_beta(N, batch, 2, dist="decay")).to(cdt).cuda()
+    plan = S.Plan(N, batch, dtype=cdt, method=method)
+    g = plan.empty_grid()
+    for _ in range(args.steps):
+        plan.alt(0, 2 * N - 1, "fwd", beta, g)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_target": True, "N": N, "batch": batch, "method": method, "dtype": args.dtype,
+                      "alt_calls": args.steps, "copy_bytes": 2 * a.numel() * 8}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -128,6 +235,10 @@ def main():
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("one GPU only: launch without torch.distributed", file=sys.stderr)
         sys.exit(2)
+
+    if args.profile_target:
+        profile_target(args)
+        return
 
     import numpy as np
     import torch
@@ -173,34 +284,19 @@ def main():
     ms_per_step = e0.elapsed_time(e1) / args.steps
     value = 2.0 * batch / (ms_per_step / 1e3)
 
-    # dominant kernel: the ALT (forward), timed alone with HIP events
+    # dominant kernel: timed alone, per launch, with HIP events that the
+    # library records on the stream the kernel runs on
     g = plan.empty_grid()
     t_alt_fwd = timer.time(lambda: plan.alt(0, 2 * N - 1, "fwd", beta, g), reps=max(3, args.steps))
     t_alt_inv = timer.time(lambda: plan.alt(0, 2 * N - 1, "inv", g, bout), reps=max(3, args.steps))
+    reps = max(3, args.steps)
+    plan.profile(True)
+    for _ in range(reps):
+        plan.alt(0, 2 * N - 1, "fwd", beta, g)
+    kern = plan.profile_report()
+    plan.profile(False)
     stats = plan.stats()
-    R = 4 * batch
-    if method == "dense":
-        flops = 2.0 * N * N * (2 * N + 1) * R  # 16 N^3 per field
-        roof = {"bound": "alu", "achieved": flops / t_alt_fwd / 1e12, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": flops / t_alt_fwd / 1e12 / PEAK_FP64_TFLOPS, "traffic": None,
-                "kernel": "k_alt_dense_fwd", "kernel_ms": t_alt_fwd * 1e3,
-                "algorithmic_flops_per_launch": flops}
-    else:
-        prog = stats.get("program", {})
-        nnz = float(prog.get("stored_entries", 0))
-        sbytes = 8 if args.dtype == "f64" else 4
-        fbytes = nnz * sbytes + float(prog.get("index_bytes", 0))
-        vbytes = batch * (4 * N * N + 2 * N * M) * 2 * sbytes
-        flops = 2.0 * nnz * R
-        if R * 2 / sbytes >= 78.6 / 8.0 * 1.0:  # above the FP64 ridge -> compute bound
-            roof = {"bound": "alu", "achieved": flops / t_alt_fwd / 1e12, "peak": PEAK_FP64_TFLOPS,
-                    "unit": "TFLOP/s", "frac": flops / t_alt_fwd / 1e12 / PEAK_FP64_TFLOPS}
-        else:
-            roof = {"bound": "hbm", "achieved": (fbytes + vbytes) / t_alt_fwd / 1e9, "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": (fbytes + vbytes) / t_alt_fwd / 1e9 / PEAK_HBM_GBS}
-        roof.update({"traffic": None, "kernel": "idbf ALT program (all stages)",
-                     "kernel_ms": t_alt_fwd * 1e3, "algorithmic_flops_per_launch": flops,
-                     "algorithmic_bytes_per_launch": fbytes + vbytes})
+    roof = roofline(method, N, batch, args.dtype, stats, kern, reps)
 
     out = {
         "metric": "SHT/s + ALT Gcoef/s at N=1024/4096, IDBF vs dense, FP64 & FP32, vs FP64 oracle",
@@ -222,6 +318,7 @@ def main():
         "alt_gcoef_per_s_inv": batch * 4 * N * N / t_alt_inv / 1e9,
         "plan_build_s": t_build,
         "roofline": roof,
+        "alt_kernels_fwd": kern,
     }
 
     if not args.no_check:

@@ -150,6 +150,17 @@ int sht_alt_apply(const sht_plan_t *plan, int m_lo, int m_hi, int dir,
  * the full length needed (>= 0) or a negative error. */
 int sht_plan_stats(const sht_plan_t *plan, char *json, size_t cap);
 
+/* Per-kernel timing.  sht_profile(plan, 1) clears earlier records and makes
+ * every later call on this plan bracket each kernel launch with HIP events
+ * recorded on the call's stream; sht_profile(plan, 0) stops recording.
+ * sht_profile_report waits for the recorded events and writes JSON
+ * {"<kernel>": {"launches": n, "total_ms": t, "avg_ms": t / n}, ...}
+ * (same size convention as sht_plan_stats).  Not for use while the stream
+ * is being captured into a graph; the recorder is not thread-safe, so a
+ * profiled plan is used from one host thread at a time. */
+int sht_profile(sht_plan_t *plan, int enable);
+int sht_profile_report(const sht_plan_t *plan, char *json, size_t cap);
+
 /* Sizes of the plan. */
 int sht_plan_info(const sht_plan_t *plan, int *N, int *batch, int *dtype, int *method);
 

@@ -17,6 +17,7 @@
 
 #include "idbf.h"
 #include "kernels.h"
+#include "prof.h"
 #include "sht_internal.h"
 
 namespace sht {
@@ -50,6 +51,10 @@ struct sht_plan {
     idbf::DeviceProgram prog;
     std::string stats;
     double build_seconds = 0.0;
+    // per-kernel timing (off unless sht_profile enables it)
+    bool profiling = false;
+    mutable prof::Recorder recorder;
+    prof::Recorder *rec() const { return profiling ? &recorder : nullptr; }
     ~sht_plan();
 };
 
@@ -304,8 +309,30 @@ int sht_plan_stats(const sht_plan_t *p, char *json, size_t cap) {
     return (int)s.size() + 1;
 }
 
+static int copy_json(const std::string &s, char *json, size_t cap) {
+    if (json && cap) {
+        size_t n = std::min(cap - 1, s.size());
+        std::memcpy(json, s.data(), n);
+        json[n] = 0;
+    }
+    return (int)s.size() + 1;
+}
+
+int sht_profile(sht_plan_t *p, int enable) {
+    if (!p) return SHT_ERR_INVALID_ARG;
+    p->recorder.clear();
+    p->profiling = enable != 0;
+    return SHT_OK;
+}
+
+int sht_profile_report(const sht_plan_t *p, char *json, size_t cap) {
+    if (!p) return SHT_ERR_INVALID_ARG;
+    return copy_json(p->recorder.report(), json, cap);
+}
+
 static int run_alt(const sht_plan_t *p, int a_lo, int a_hi, int dir, const void *in, void *out,
                    hipStream_t s) {
+    prof::Install inst(p->rec());
     hipError_t e;
     if (p->method == SHT_DENSE) {
         if (dir == SHT_FWD)
@@ -344,6 +371,7 @@ int sht_forward(const sht_plan_t *p, const void *beta, void *f, void *stream) {
     }
     hipStream_t s = (hipStream_t)stream;
     if ((rc = run_alt(p, 0, 2 * p->N - 1, SHT_FWD, beta, f, s))) return rc;
+    prof::Install inst(p->rec());
     hipError_t e = dev::dft_synthesis(p->dft, p->dtype, p->batch, f, s);
     if (e != hipSuccess) return hip_fail(e, "DFT synthesis");
     return SHT_OK;
@@ -355,6 +383,7 @@ static int transposed(const sht_plan_t *p, const void *f, void *beta, void *stre
     if ((rc = check_ptr(beta, elt_size(p->dtype)))) return rc;
     if ((rc = check_ptr(f, elt_size(p->dtype)))) return rc;
     hipStream_t s = (hipStream_t)stream;
+    prof::Install inst(p->rec());
     hipError_t e = dev::dft_analysis(p->dft, p->dtype, p->batch, inverse ? 1.0 / p->M : 1.0, f, p->d_g, s);
     if (e != hipSuccess) return hip_fail(e, "DFT analysis");
     return run_alt(p, 0, 2 * p->N - 1, inverse ? SHT_INV : SHT_ADJ, p->d_g, beta, s);

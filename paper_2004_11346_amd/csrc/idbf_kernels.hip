@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include "idbf_device.h"
+#include "prof.h"
 #include "kernels.h"
 
 namespace sht {
@@ -254,6 +255,7 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
             const Stage &sg = pd.stages[st];
             const int mo = std::max(1, (int)sg.max_out), mi = std::max(4, ((int)sg.max_in + 3) & ~3);
             const size_t lds = sizeof(T) * (size_t)(mo + mi) * RC;
+            prof::Scope ps(s, mfma ? "k_ops_mfma" : "k_ops");
             if (mfma) {
                 const double *vd = (const double *)vals;
                 const double *ind = (const double *)(in + c0);

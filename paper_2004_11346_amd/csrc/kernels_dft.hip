@@ -23,6 +23,7 @@
 #include <algorithm>
 
 #include "kernels.h"
+#include "prof.h"
 
 namespace sht {
 namespace dev {
@@ -194,6 +195,7 @@ hipError_t launch_rows(const DftPlan &p, int batch, int mode, double scale, cons
         attr_set = true;
     }
     const C *tw = sizeof(C) == 8 ? (const C *)p.tw2 : (const C *)p.tw2f;
+    prof::Scope sc(s, mode == 0 ? "k_dft_synthesis" : "k_dft_analysis");
     hipLaunchKernelGGL((k_dft_rows<C, T>), dim3(2 * p.N, batch), dim3(512), lds, s, p.N, p.M, ps, tw, p.src_pos,
                        mode, (C)scale, (const T *)in, (T *)out);
     return hipGetLastError();

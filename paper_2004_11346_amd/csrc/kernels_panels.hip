@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "prof.h"
 
 namespace sht {
 namespace dev {
@@ -112,6 +113,7 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 // (otherwise they have the element type of beta / g).
 hipError_t panel_pack(int dtype, bool panel64, int N, int batch, int a_lo, int a_hi, const int64_t *x_off,
                       int64_t max_cols, const void *beta, void *X, hipStream_t s) {
+    prof::Scope ps(s, "k_pack");
     const int R = 4 * batch, t_lo = 2 * a_lo, nt = 2 * (a_hi - a_lo + 1);
     dim3 grid(blocks_for(max_cols * R), nt);
     if (dtype == 0)
@@ -128,6 +130,7 @@ hipError_t panel_pack(int dtype, bool panel64, int N, int batch, int a_lo, int a
 
 hipError_t panel_scatter(int dtype, bool panel64, int N, int batch, int a_lo, int a_hi, const int64_t *x_off,
                          int64_t max_cols, const void *X, void *beta, hipStream_t s) {
+    prof::Scope ps(s, "k_scatter");
     const int R = 4 * batch, t_lo = 2 * a_lo, nt = 2 * (a_hi - a_lo + 1);
     dim3 grid(blocks_for(max_cols * R), nt);
     if (dtype == 0)
@@ -144,6 +147,7 @@ hipError_t panel_scatter(int dtype, bool panel64, int N, int batch, int a_lo, in
 
 hipError_t panel_combine(int dtype, bool panel64, int N, int batch, int a_lo, int a_hi, const void *Y, void *g,
                          hipStream_t s) {
+    prof::Scope ps(s, "k_combine");
     const int R = 4 * batch, M = 4 * N - 1;
     dim3 grid(blocks_for((int64_t)N * R), a_hi - a_lo + 1);
     if (dtype == 0)
@@ -160,6 +164,7 @@ hipError_t panel_combine(int dtype, bool panel64, int N, int batch, int a_lo, in
 
 hipError_t panel_fold(int dtype, bool panel64, int N, int batch, int a_lo, int a_hi, const double *wh,
                       const void *g, void *Y, hipStream_t s) {
+    prof::Scope ps(s, "k_fold");
     const int R = 4 * batch, M = 4 * N - 1;
     dim3 grid(blocks_for((int64_t)N * R), a_hi - a_lo + 1);
     if (dtype == 0)

@@ -25,7 +25,7 @@ SHT_SAMPLE_MOCK_CHEB, SHT_SAMPLE_RANDOM = 0, 1
 
 EXPORTED = [
     "sht_plan_opts_default", "sht_plan_create", "sht_plan_destroy", "sht_forward", "sht_inverse",
-    "sht_backward", "sht_alt_apply", "sht_plan_stats", "sht_plan_info", "sht_plan_nodes",
+    "sht_backward", "sht_alt_apply", "sht_plan_stats", "sht_profile", "sht_profile_report", "sht_plan_info", "sht_plan_nodes",
     "sht_strerror", "sht_last_error_detail", "sht_host_plan_create", "sht_host_plan_destroy",
     "sht_host_plan_apply", "sht_host_alt_matrix", "sht_host_plan_stats", "sht_host_gauss_legendre",
 ]
@@ -80,6 +80,8 @@ def load():
             getattr(lib, n).argtypes = [P, P, P, P]
         lib.sht_alt_apply.argtypes = [P, I, I, I, P, P, P]
         lib.sht_plan_stats.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
+        lib.sht_profile.argtypes = [P, I]
+        lib.sht_profile_report.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
         lib.sht_plan_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
                                       ctypes.POINTER(I)]
         lib.sht_plan_nodes.argtypes = [P, P, P]

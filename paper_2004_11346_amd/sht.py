@@ -134,6 +134,17 @@ class Plan:
         _l.check(self._lib.sht_plan_stats(self._h, buf, n), "sht_plan_stats")
         return json.loads(buf.value.decode())
 
+    def profile(self, enable: bool = True):
+        """Start (clearing earlier records) or stop per-kernel event timing."""
+        _l.check(self._lib.sht_profile(self._h, 1 if enable else 0), "sht_profile")
+
+    def profile_report(self) -> dict:
+        """{kernel: {"launches", "total_ms", "avg_ms"}} of the recorded calls."""
+        n = _l.check(self._lib.sht_profile_report(self._h, None, 0), "sht_profile_report")
+        buf = ctypes.create_string_buffer(n)
+        _l.check(self._lib.sht_profile_report(self._h, buf, n), "sht_profile_report")
+        return json.loads(buf.value.decode())
+
     def nodes(self):
         import numpy as np
         x = np.empty(2 * self.N)
