@@ -171,9 +171,12 @@ def roofline(method, N, batch, dtype, stats, kern, reps):
     R = 4 * batch
     sb = 8 if dtype == "f64" else 4
     mfma_name = "k_dense_fwd_mfma" if method == "dense" else "k_ops_mfma"
-    uses_mfma = mfma_name in kern
+    uses_mfma = any(name.startswith(mfma_name) for name in kern)
     label, files = DOMINANT[(method, uses_mfma)]
-    k = kern.get(label, {"launches": 0, "total_ms": float("nan")})
+    # the fast form's op kernel is labelled per stage kind ("[levels]", "[final]")
+    parts = [v for name, v in kern.items() if name == label or name.startswith(label + "[")]
+    k = {"launches": sum(v["launches"] for v in parts) if parts else 0,
+         "total_ms": sum(v["total_ms"] for v in parts) if parts else float("nan")}
     per_call_s = k["total_ms"] / reps / 1e3
     launches_per_call = k["launches"] / reps
     if method == "dense":

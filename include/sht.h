@@ -102,6 +102,10 @@ typedef struct sht_plan_opts {
     int threads;       /* host threads for plan construction (0 = all) */
     int f32_mode;      /* SHT_F32_VALU or SHT_F32_SPLIT_BF16 (F32 plans) */
     int min_idbf;      /* smallest block side given an IDBF (default 4*leaf) */
+    int dense_gen;     /* 1 (default): dense blocks of the fast form are not
+                          stored; the kernels regenerate their entries with the
+                          three-term recurrence from per-row checkpoints taken
+                          every 16 columns.  0: store their values. */
 } sht_plan_opts;
 
 void sht_plan_opts_default(sht_plan_opts *opts);
@@ -170,6 +174,43 @@ int sht_plan_nodes(const sht_plan_t *plan, double *x, double *w);
 
 const char *sht_strerror(int code);
 const char *sht_last_error_detail(void);
+
+/* ---- grouped transforms ------------------------------------------------
+ * Many independent transforms of different degrees applied together (the
+ * uneven workload: e.g. 64 transforms with N in {128, 256, 512, 1024} and 1-4
+ * fields each).  Transform i has degree Ns[i] (1 <= Ns[i] <= 1024) and
+ * fields[i] (1..4) fields; all share the dtype.  Each phase (forward ALT, phi
+ * synthesis; phi analysis, transposed ALT) is one persistent launch whose
+ * workgroups pull (transform, order, node tile) or (transform, field, row)
+ * items from a device queue ordered longest first.  The plain (dense) ALT is
+ * used.  The group owns its tables, queues and an inverse workspace; the
+ * caller owns the coefficient and grid buffers and binds them once. */
+typedef struct sht_group sht_group_t;
+
+int sht_group_create(int n, const int *Ns, const int *fields, int dtype, sht_group_t **out);
+void sht_group_destroy(sht_group_t *grp);
+
+/* Bind device buffers: beta[i] [fields_i][4 N_i^2] and f[i] [fields_i][2 N_i][4 N_i - 1]
+ * complex, laid out as for a plan.  Forward reads beta and writes f; inverse
+ * reads f and writes beta.  Re-binding drops captured graphs. */
+int sht_group_bind(sht_group_t *grp, void *const *beta, void *const *f);
+int sht_group_forward(sht_group_t *grp, void *stream);
+int sht_group_inverse(sht_group_t *grp, void *stream);
+
+/* Autotuner: times a few persistent grid sizes per phase on the bound
+ * buffers (overwriting f, beta and the workspace) and keeps the fastest;
+ * the timings are reported by sht_group_stats.  Drops captured graphs. */
+int sht_group_tune(sht_group_t *grp, void *stream);
+
+/* Capture one direction (SHT_FWD or SHT_INV) on a non-default stream into a
+ * hipGraph for the bound buffers, and replay it.  The graph holds kernel
+ * nodes only (counters are cleared by a kernel, not a memset). */
+int sht_group_capture(sht_group_t *grp, int dir, void *stream);
+int sht_group_replay(sht_group_t *grp, int dir, void *stream);
+
+/* Work items, grid sizes and tuning timings as JSON (size convention as
+ * sht_plan_stats). */
+int sht_group_stats(const sht_group_t *grp, char *json, size_t cap);
 
 /* ---- plan verification on the host (no GPU needed) --------------------
  * These calls build the same FP64 plan as sht_plan_create without touching

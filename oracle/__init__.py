@@ -69,12 +69,13 @@ def _load():
             lib.oracle_plm.argtypes = [I, I, D, P]
             lib.oracle_alt_forward_grid.argtypes = [I, P, P, P]
             lib.oracle_alt_forward_orders.argtypes = [I, P, P, I, P, P]
+            lib.oracle_alt_forward_rows.argtypes = [I, P, P, I, P, P]
             lib.oracle_alt_transpose_grid.argtypes = [I, P, P, P, P]
             lib.oracle_alt_transpose_orders.argtypes = [I, P, P, I, P, P, P]
             lib.oracle_dft_synthesis.argtypes = [I, P, I, P, P]
             lib.oracle_dft_analysis.argtypes = [I, P, I, P, D, P]
             for name in ("oracle_gauss_legendre", "oracle_plm", "oracle_alt_forward_grid",
-                         "oracle_alt_forward_orders", "oracle_alt_transpose_grid",
+                         "oracle_alt_forward_orders", "oracle_alt_forward_rows", "oracle_alt_transpose_grid",
                          "oracle_alt_transpose_orders", "oracle_dft_synthesis",
                          "oracle_dft_analysis"):
                 getattr(lib, name).restype = I
@@ -139,6 +140,18 @@ def alt_forward_orders(N: int, beta: np.ndarray, absm, x: np.ndarray | None = No
     out = np.zeros((len(absm), 2, 2 * N), dtype=np.complex128)
     _chk(_load().oracle_alt_forward_orders(N, _ptr(np.ascontiguousarray(x)), _ptr(beta),
                                            len(absm), _ptr(absm), _ptr(out)), "alt_forward_orders")
+    return out
+
+
+def alt_forward_rows(N: int, beta: np.ndarray, rows, x: np.ndarray | None = None) -> np.ndarray:
+    """Forward ALT for all orders at the listed nodes: g_rows[len(rows), M]."""
+    if x is None:
+        x, _ = gauss_legendre(2 * N)
+    beta = _c128(beta)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    out = np.zeros((len(rows), 4 * N - 1), dtype=np.complex128)
+    _chk(_load().oracle_alt_forward_rows(N, _ptr(np.ascontiguousarray(x)), _ptr(beta), len(rows), _ptr(rows),
+                                         _ptr(out)), "alt_forward_rows")
     return out
 
 

@@ -203,6 +203,48 @@ int oracle_alt_forward_grid(int N, const double *x, const double *beta, double *
     return bad ? -2 : 0;
 }
 
+/* Forward ALT for every order at a list of nodes (Section 1, ALT
+ * definition): g_rows[i][m mod M] = sum_k beta_{k,m} Pbar_k^{|m|}(x_{rows[i]}).
+ * g_rows: complex [n_rows][M]. */
+int oracle_alt_forward_rows(int N, const double *x, const double *beta, int n_rows, const int *rows,
+                            double *g_rows)
+{
+    if (N < 1 || n_rows < 0) return -1;
+    const int n = 2 * N, M = 4 * N - 1;
+    for (int i = 0; i < n_rows; ++i)
+        if (rows[i] < 0 || rows[i] >= n) return -1;
+    int bad = 0;
+#pragma omp parallel
+    {
+        ld *col = (ld *)malloc(sizeof(ld) * (size_t)n);
+        if (!col) {
+#pragma omp atomic write
+            bad = 1;
+        }
+#pragma omp for schedule(dynamic, 1) collapse(2)
+        for (int i = 0; i < n_rows; ++i) {
+            for (int a = 0; a < n; ++a) {
+                if (!col) continue;
+                plm_column_ld(a, n - 1, (ld)x[rows[i]], col);
+                for (int sgn = 0; sgn < (a == 0 ? 1 : 2); ++sgn) {
+                    int m = sgn ? -a : a;
+                    const double *bm = beta + 2 * oracle_coef_offset(N, m);
+                    ld re = 0.0L, im = 0.0L;
+                    for (int k = a; k < n; ++k) {
+                        re += col[k - a] * (ld)bm[2 * (k - a)];
+                        im += col[k - a] * (ld)bm[2 * (k - a) + 1];
+                    }
+                    int c = ((m % M) + M) % M;
+                    g_rows[2 * ((size_t)i * M + c)] = (double)re;
+                    g_rows[2 * ((size_t)i * M + c) + 1] = (double)im;
+                }
+            }
+        }
+        free(col);
+    }
+    return bad ? -2 : 0;
+}
+
 /* Forward ALT for a list of orders |m|: out[i][s][l] (complex), s = 0 for +|m|
  * and 1 for -|m| (for |m| = 0 both slots hold order 0). */
 int oracle_alt_forward_orders(int N, const double *x, const double *beta,

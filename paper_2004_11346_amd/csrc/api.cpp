@@ -133,6 +133,7 @@ void sht_plan_opts_default(sht_plan_opts *o) {
     o->threads = 0;
     o->f32_mode = SHT_F32_VALU;
     o->min_idbf = 0;
+    o->dense_gen = 1;
 }
 
 const char *sht_strerror(int code) {
@@ -264,7 +265,7 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
             return SHT_ERR_OOM;
         }
         if (brc) return brc;
-        brc = idbf::upload_program(hp, dtype, batch, p->d_wh, p->prog);
+        brc = idbf::upload_program(hp, dtype, batch, p->d_wh, p->d_xh, p->d_coef, p->prog);
         if (brc) return brc;
         p->stats = hp.stats_json;
     }

@@ -81,7 +81,7 @@ int sht_host_plan_apply(const sht_host_plan_t *hp, int absm, int parity, int dir
     const int64_t ob = fwd ? pk.y_off[task] : pk.x_off[task];
     const int nin = fwd ? t.cols : t.rows, nout = fwd ? t.rows : t.cols;
     std::memcpy(&pin[(size_t)ib * R], in, sizeof(double) * (size_t)nin * R);
-    idbf::host_run_program(p, R, pin.data(), pout.data());
+    idbf::host_run_program(p, R, pin.data(), pout.data(), hp->data.lt.xh.data(), hp->data.lt.coef.data());
     std::memcpy(out, &pout[(size_t)ob * R], sizeof(double) * (size_t)nout * R);
     return SHT_OK;
 }
@@ -107,7 +107,30 @@ int sht_host_plan_stats(const sht_host_plan_t *hp, char *json, size_t cap) {
              ",\"adj_stages\":" + std::to_string(pk.adj.stages.size()) + ",\"scratch_rows\":" +
              std::to_string(std::max(pk.fwd.scr_rows, pk.adj.scr_rows)) + ",\"max_n_out\":" +
              std::to_string(pk.fwd.max_n_out) + ",\"max_n_in\":" + std::to_string(pk.fwd.max_n_in) +
-             ",\"fwd_values\":" + std::to_string(pk.fwd.vals.size()) + ",\"adj_values\":" + std::to_string(pk.adj.vals.size()) + "}";
+             ",\"fwd_values\":" + std::to_string(pk.fwd.vals.size()) + ",\"adj_values\":" + std::to_string(pk.adj.vals.size());
+        // stored values by sub-op output count (1-8, 9-16, 17-32, 33-64),
+        // work stages vs final stage, per program
+        for (int d = 0; d < 2; ++d) {
+            const idbf::Program &pr = d ? pk.adj : pk.fwd;
+            int64_t h[2][4] = {{0}}, nsub[2][4] = {{0}};
+            for (size_t si = 0; si < pr.stages.size(); ++si) {
+                const int fin = si + 1 == pr.stages.size();
+                for (int q = pr.stages[si].op_begin; q < pr.stages[si].op_end; ++q)
+                    for (int k = 0; k < pr.ops[q].nsub; ++k) {
+                        const idbf::SubOp &so = pr.subs[pr.ops[q].sub0 + k];
+                        if (so.src == idbf::kGen || so.n_map == 0) continue;
+                        const int b = so.n_map <= 8 ? 0 : so.n_map <= 16 ? 1 : so.n_map <= 32 ? 2 : 3;
+                        h[fin][b] += (int64_t)so.n_map * so.n_in;
+                        nsub[fin][b] += 1;
+                    }
+            }
+            s += std::string(",\"") + (d ? "adj" : "fwd") + "_nmap_hist\":[";
+            for (int f = 0; f < 2; ++f)
+                for (int b = 0; b < 4; ++b)
+                    s += "[" + std::to_string(h[f][b]) + "," + std::to_string(nsub[f][b]) + "]" + (f == 1 && b == 3 ? "" : ",");
+            s += "]";
+        }
+        s += "}";
     }
     if (json && cap) {
         size_t n = std::min(cap - 1, s.size());

@@ -33,7 +33,7 @@ namespace idbf {
 
 int64_t Block::stored() const {
     switch (type) {
-        case kDense: return (int64_t)D.size();
+        case kDense: return gen ? 0 : (int64_t)D.size();
         case kLowRank: return (int64_t)U.size() + (int64_t)V.size();
         default: {
             int64_t s = 0;
@@ -46,6 +46,32 @@ int64_t Block::stored() const {
         }
     }
 }
+
+void rec_step(const LegendreTables &lt, int a, double x, int k, RecState &s) {
+    const double *c = &lt.coef[2 * (tri_offset(lt.N, a) + (k + 1 - a))];
+    const double p2 = c[0] * (x * s.p1 - c[1] * s.p0);
+    s.p0 = s.p1;
+    s.p1 = p2;
+    if (std::fabs(s.p1) > 0x1p200) {
+        s.p0 *= 0x1p-200;
+        s.p1 *= 0x1p-200;
+        s.e += 200;
+    }
+}
+
+RecState gen_state(const LegendreTables &lt, int a, int parity, const Block &b, int r, int col) {
+    const int q = (col - b.ck_c0) >> 4;
+    RecState s = b.ck[(size_t)(r - b.r0) * b.ck_n + q];
+    const double x = lt.xh[r];
+    for (int c = b.ck_c0 + 16 * q; c < col; ++c) {
+        const int k = a + parity + 2 * c;
+        rec_step(lt, a, x, k, s);
+        rec_step(lt, a, x, k + 1, s);
+    }
+    return s;
+}
+
+double gen_value(const RecState &s) { return s.e < -1074 ? 0.0 : s.p1 * std::ldexp(1.0, s.e); }
 
 namespace {
 
@@ -455,77 +481,6 @@ void butterfly_forward(const Butterfly &bf, int R, const double *x /* task cols 
     }
 }
 
-void butterfly_transpose(const Butterfly &bf, int R, const double *y /* task rows */, double *x /* task cols, += */) {
-    const int L = bf.L, h = bf.h;
-    std::vector<std::vector<Vec>> u(L - h + 1);
-    {
-        const int nleaf = 1 << L;
-        u[0].resize(nleaf);
-        for (int A = 0; A < nleaf; ++A) {
-            const int rlo = node_lo(bf.r0, bf.r1 - bf.r0, L, A), rhi = node_lo(bf.r0, bf.r1 - bf.r0, L, A + 1);
-            const ID &id = bf.row[0][A];
-            Vec &o = u[0][A];
-            o.assign((size_t)id.k() * R, 0.0);
-            id_gather(id, R, y + (size_t)rlo * R, o.data());
-            (void)rhi;
-        }
-    }
-    for (int l = 1; l <= L - h; ++l) {
-        const int nA = 1 << (L - l), nB = 1 << l, nBp = 1 << (l - 1);
-        u[l].resize((size_t)nA * nB);
-        for (int A = 0; A < nA; ++A)
-            for (int B = 0; B < nB; ++B) {
-                const int Bp = B >> 1;
-                const Vec &a1 = u[l - 1][(size_t)(2 * A) * nBp + Bp], &a2 = u[l - 1][(size_t)(2 * A + 1) * nBp + Bp];
-                Vec in = a1;
-                in.insert(in.end(), a2.begin(), a2.end());
-                const ID &id = bf.row[l][(size_t)A * nB + B];
-                Vec &o = u[l][(size_t)A * nB + B];
-                o.assign((size_t)id.k() * R, 0.0);
-                id_gather(id, R, in.data(), o.data());
-            }
-    }
-    std::vector<std::vector<Vec>> z(h + 1);
-    {
-        const int nA = 1 << h, nB = 1 << (L - h);
-        z[h].resize((size_t)nA * nB);
-        for (int A = 0; A < nA; ++A)
-            for (int B = 0; B < nB; ++B) {
-                const size_t ix = (size_t)A * nB + B;
-                const int kr = bf.row[L - h][ix].k(), kc = bf.col[h][ix].k();
-                Vec &o = z[h][ix];
-                o.assign((size_t)kc * R, 0.0);
-                const Vec &uu = u[L - h][ix];
-                for (int i = 0; i < kr; ++i)
-                    for (int j = 0; j < kc; ++j) {
-                        double s = bf.S[ix][(size_t)i * kc + j];
-                        for (int r = 0; r < R; ++r) o[(size_t)j * R + r] += s * uu[(size_t)i * R + r];
-                    }
-            }
-    }
-    for (int l = h; l >= 1; --l) {
-        const int nAp = 1 << (l - 1), nB = 1 << (L - l), nBc = 1 << (L - l + 1);
-        z[l - 1].resize((size_t)nAp * nBc);
-        for (int Ap = 0; Ap < nAp; ++Ap)
-            for (int B = 0; B < nB; ++B) {
-                const ID &ia = bf.col[l - 1][(size_t)Ap * nBc + 2 * B];
-                const ID &ib = bf.col[l - 1][(size_t)Ap * nBc + 2 * B + 1];
-                const int n1 = ia.k(), n2 = ib.k();
-                Vec v((size_t)(n1 + n2) * R, 0.0);
-                for (int A = 2 * Ap; A <= 2 * Ap + 1; ++A)
-                    id_scatter_add(bf.col[l][(size_t)A * nB + B], R, z[l][(size_t)A * nB + B].data(), v.data());
-                z[l - 1][(size_t)Ap * nBc + 2 * B].assign(v.begin(), v.begin() + (size_t)n1 * R);
-                z[l - 1][(size_t)Ap * nBc + 2 * B + 1].assign(v.begin() + (size_t)n1 * R, v.end());
-            }
-    }
-    const int nleaf = 1 << L;
-    for (int B = 0; B < nleaf; ++B) {
-        const int clo = node_lo(bf.c0, bf.c1 - bf.c0, L, B), chi = node_lo(bf.c0, bf.c1 - bf.c0, L, B + 1);
-        Vec v((size_t)(chi - clo) * R, 0.0);
-        id_scatter_add(bf.col[0][B], R, z[0][B].data(), v.data());
-        for (size_t q = 0; q < v.size(); ++q) x[(size_t)clo * R + q] += v[q];
-    }
-}
 
 double butterfly_check(const View &K, const Butterfly &bf, Ctx &cx) {
     // apply to a few random vectors and compare with the dense block
@@ -568,6 +523,35 @@ void trim(const View &K, Box &b, double tau, bool &empty) {
     if (!empty) b = Box{rlo, rhi + 1, clo, chi + 1};
 }
 
+// Recurrence states of every regenerated dense block: one walk along each
+// task row from degree |m|, recording the state at the 16-aligned columns the
+// blocks of that row need.
+void record_checkpoints(const LegendreTables &lt, Task &t) {
+    const int N = lt.N, a = t.a, par = t.parity;
+    std::vector<std::vector<std::pair<int, int>>> need(N);  // row -> (col, block)
+    for (int bi = 0; bi < (int)t.blocks.size(); ++bi) {
+        const Block &b = t.blocks[bi];
+        if (!b.gen) continue;
+        for (int r = b.r0; r < b.r1; ++r)
+            for (int q = 0; q < b.ck_n; ++q) need[r].push_back({b.ck_c0 + 16 * q, bi});
+    }
+    for (int r = 0; r < N; ++r) {
+        if (need[r].empty()) continue;
+        std::sort(need[r].begin(), need[r].end());
+        const double x = lt.xh[r];
+        RecState s;
+        s.p1 = lt.diag_m[(size_t)a * N + r];
+        s.e = lt.diag_e[(size_t)a * N + r];
+        int k = a;  // degree of s.p1
+        for (const auto &cb : need[r]) {
+            const int kt = a + par + 2 * cb.first;
+            while (k < kt) rec_step(lt, a, x, k++, s);
+            Block &b = t.blocks[cb.second];
+            b.ck[(size_t)(r - b.r0) * b.ck_n + ((cb.first - b.ck_c0) >> 4)] = s;
+        }
+    }
+}
+
 void build_task(int N, const LegendreTables &lt, const sht_plan_opts &o, int a, int par, Task &t,
                 std::vector<double> &mat, BuildStats &st) {
     t.a = a;
@@ -604,7 +588,14 @@ void build_task(int N, const LegendreTables &lt, const sht_plan_opts &o, int a, 
     };
     std::vector<Box> work, done;
     const int nb = std::max(1, (int)std::lround((double)N / cols));
-    for (int i = 0; i < nb; ++i) work.push_back(Box{(int)((int64_t)i * N / nb), (int)((int64_t)(i + 1) * N / nb), 0, cols});
+    // row boundaries on multiples of 64 where that keeps every block non-empty
+    // (the kernels tile outputs by 64 rows)
+    auto row_cut = [&](int64_t r) {
+        const int64_t a64 = (r + 32) / 64 * 64;
+        return (int)(N >= 64 * nb ? a64 : r);
+    };
+    for (int i = 0; i < nb; ++i)
+        work.push_back(Box{row_cut((int64_t)i * N / nb), i + 1 == nb ? N : row_cut((int64_t)(i + 1) * N / nb), 0, cols});
     const int n0 = std::max(8, o.n0);
     while (!work.empty()) {
         Box b = work.back();
@@ -612,6 +603,8 @@ void build_task(int N, const LegendreTables &lt, const sht_plan_opts &o, int a, 
         if (b.r1 <= b.r0 || b.c1 <= b.c0) continue;
         if (region(b) == kTurning && std::max(b.r1 - b.r0, b.c1 - b.c0) > n0) {
             int rm = (b.r0 + b.r1) / 2, cm = (b.c0 + b.c1) / 2;
+            const int rm64 = (rm + 32) / 64 * 64;
+            if (rm64 > b.r0 && rm64 < b.r1) rm = rm64;
             if (b.r1 - b.r0 < 2) rm = b.r1;
             if (b.c1 - b.c0 < 2) cm = b.c1;
             work.push_back(Box{b.r0, rm, b.c0, cm});
@@ -629,6 +622,7 @@ void build_task(int N, const LegendreTables &lt, const sht_plan_opts &o, int a, 
     for (Box b : done) {
         Block blk;
         blk.region = region(b);
+        const Box whole = b;
         if (blk.region != kOsc) {
             bool empty = false;
             trim(K, b, tau, empty);
@@ -676,12 +670,30 @@ void build_task(int N, const LegendreTables &lt, const sht_plan_opts &o, int a, 
         }
         if (!chosen) {
             blk.type = kDense;
-            blk.D.resize((size_t)m * n);
-            for (int i = 0; i < m; ++i)
-                for (int j = 0; j < n; ++j) blk.D[(size_t)i * n + j] = K(b.r0 + i, b.c0 + j);
+            if (o.dense_gen) {
+                // rows widened to multiples of 64 inside the untrimmed box:
+                // the extra entries are exact (regenerated), not stored
+                blk.r0 = std::max(whole.r0, blk.r0 & ~63);
+                blk.r1 = std::min(whole.r1, (blk.r1 + 63) & ~63);
+                blk.gen = true;
+                blk.ck_c0 = b.c0 & ~15;
+                blk.ck_n = (b.c1 - 1 - blk.ck_c0) / 16 + 1;
+                blk.ck.resize((size_t)(blk.r1 - blk.r0) * blk.ck_n);
+            } else {
+                blk.D.resize((size_t)m * n);
+                for (int i = 0; i < m; ++i)
+                    for (int j = 0; j < n; ++j) blk.D[(size_t)i * n + j] = K(b.r0 + i, b.c0 + j);
+            }
         }
         switch (blk.type) {
-            case kDense: st.n_dense++; st.dense_stored += blk.stored(); break;
+            case kDense:
+                st.n_dense++;
+                st.dense_stored += blk.stored();
+                if (blk.gen) {
+                    st.n_gen++;
+                    st.gen_entries += (int64_t)(blk.r1 - blk.r0) * n;
+                }
+                break;
             case kLowRank: st.n_lowrank++; st.lowrank_stored += blk.stored(); st.max_rank = std::max(st.max_rank, blk.rank); break;
             default: {
                 st.n_butterfly++;
@@ -697,6 +709,7 @@ void build_task(int N, const LegendreTables &lt, const sht_plan_opts &o, int a, 
         st.region_area[blk.region] += dense_sz;
         t.blocks.push_back(std::move(blk));
     }
+    if (o.dense_gen) record_checkpoints(lt, t);
 }
 
 }  // namespace
@@ -735,6 +748,8 @@ int build_all(int N, const sht_plan_opts &opts, HostPlanData &out) {
         tot.dense_stored += s.dense_stored;
         tot.lowrank_stored += s.lowrank_stored;
         tot.butterfly_stored += s.butterfly_stored;
+        tot.n_gen += s.n_gen;
+        tot.gen_entries += s.gen_entries;
         tot.max_rank = std::max(tot.max_rank, s.max_rank);
         for (int i = 0; i < 3; ++i) {
             tot.region_area[i] += s.region_area[i];
@@ -753,7 +768,8 @@ std::string HostPlanData::stats_json() const {
        << ",\"blocks_dense\":" << stats.n_dense << ",\"blocks_lowrank\":" << stats.n_lowrank
        << ",\"blocks_butterfly\":" << stats.n_butterfly << ",\"blocks_dropped\":" << stats.n_dropped
        << ",\"dense_stored\":" << stats.dense_stored << ",\"lowrank_stored\":" << stats.lowrank_stored
-       << ",\"butterfly_stored\":" << stats.butterfly_stored << ",\"max_rank\":" << stats.max_rank
+       << ",\"butterfly_stored\":" << stats.butterfly_stored << ",\"blocks_generated\":" << stats.n_gen
+       << ",\"generated_entries\":" << stats.gen_entries << ",\"max_rank\":" << stats.max_rank
        << ",\"build_seconds\":" << stats.seconds << ",\"eps\":" << opts.eps << ",\"n0\":" << opts.n0
        << ",\"leaf\":" << opts.leaf;
     const char *rn[3] = {"osc", "nonosc", "turning"};
@@ -762,54 +778,6 @@ std::string HostPlanData::stats_json() const {
            << ",\"lowrank\":" << stats.region_stored[i][1] << ",\"butterfly\":" << stats.region_stored[i][2] << "}";
     os << "}";
     return os.str();
-}
-
-void host_apply_task(const Task &t, int dir, int R, const double *x, double *y) {
-    if (dir == 0) {
-        std::fill(y, y + (size_t)t.rows * R, 0.0);
-        for (const Block &b : t.blocks) {
-            const int m = b.r1 - b.r0, n = b.c1 - b.c0;
-            if (b.type == kDense) {
-                for (int i = 0; i < m; ++i)
-                    for (int j = 0; j < n; ++j) {
-                        double d = b.D[(size_t)i * n + j];
-                        for (int r = 0; r < R; ++r) y[(size_t)(b.r0 + i) * R + r] += d * x[(size_t)(b.c0 + j) * R + r];
-                    }
-            } else if (b.type == kLowRank) {
-                std::vector<double> w((size_t)b.rank * R, 0.0);
-                for (int j = 0; j < n; ++j)
-                    for (int q = 0; q < b.rank; ++q)
-                        for (int r = 0; r < R; ++r) w[(size_t)q * R + r] += b.V[(size_t)j * b.rank + q] * x[(size_t)(b.c0 + j) * R + r];
-                for (int i = 0; i < m; ++i)
-                    for (int q = 0; q < b.rank; ++q)
-                        for (int r = 0; r < R; ++r) y[(size_t)(b.r0 + i) * R + r] += b.U[(size_t)i * b.rank + q] * w[(size_t)q * R + r];
-            } else {
-                butterfly_forward(b.bf, R, x, y);
-            }
-        }
-    } else {
-        std::fill(y, y + (size_t)t.cols * R, 0.0);
-        for (const Block &b : t.blocks) {
-            const int m = b.r1 - b.r0, n = b.c1 - b.c0;
-            if (b.type == kDense) {
-                for (int i = 0; i < m; ++i)
-                    for (int j = 0; j < n; ++j) {
-                        double d = b.D[(size_t)i * n + j];
-                        for (int r = 0; r < R; ++r) y[(size_t)(b.c0 + j) * R + r] += d * x[(size_t)(b.r0 + i) * R + r];
-                    }
-            } else if (b.type == kLowRank) {
-                std::vector<double> w((size_t)b.rank * R, 0.0);
-                for (int i = 0; i < m; ++i)
-                    for (int q = 0; q < b.rank; ++q)
-                        for (int r = 0; r < R; ++r) w[(size_t)q * R + r] += b.U[(size_t)i * b.rank + q] * x[(size_t)(b.r0 + i) * R + r];
-                for (int j = 0; j < n; ++j)
-                    for (int q = 0; q < b.rank; ++q)
-                        for (int r = 0; r < R; ++r) y[(size_t)(b.c0 + j) * R + r] += b.V[(size_t)j * b.rank + q] * w[(size_t)q * R + r];
-            } else {
-                butterfly_transpose(b.bf, R, x, y);
-            }
-        }
-    }
 }
 
 }  // namespace idbf

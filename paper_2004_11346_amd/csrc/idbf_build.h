@@ -41,6 +41,17 @@ struct Butterfly {
 };
 
 enum BlockType { kDense = 0, kLowRank = 1, kButterfly = 2 };
+
+// Three-term recurrence state of one matrix row (node x_r) at a degree k:
+// the entries of degrees k-1 and k are p0 * 2^e and p1 * 2^e.
+struct RecState {
+    double p0 = 0.0, p1 = 0.0;
+    int32_t e = 0;
+};
+
+// Advance a state of order a at node x from degree k to k + 1 (same
+// arithmetic and rescaling as the table builder and the device kernels).
+void rec_step(const LegendreTables &lt, int a, double x, int k, RecState &s);
 enum Region { kOsc = 0, kNonOsc = 1, kTurning = 2 };
 
 struct Block {
@@ -51,8 +62,19 @@ struct Block {
     int rank = 0;                        // low rank: A ~= U V^T
     std::vector<double> U, V;            // U: rows x rank, V: cols x rank (row-major)
     Butterfly bf;
-    int64_t stored() const;              // stored factor entries
+    // dense blocks regenerated on the device: no values, but the recurrence
+    // state of every row at columns ck_c0 + 16 q (q < ck_n, ck_c0 = c0 & ~15)
+    bool gen = false;
+    int ck_c0 = 0, ck_n = 0;
+    std::vector<RecState> ck;  // [row - r0][q]
+    int64_t stored() const;    // stored factor entries
 };
+
+// State of block row r (task row) at task column col (c0 <= col < c1) of a
+// regenerated dense block: nearest checkpoint, then the recurrence.
+RecState gen_state(const LegendreTables &lt, int a, int parity, const Block &b, int r, int col);
+// Entry (r, col) of a regenerated dense block as the device forms it.
+double gen_value(const RecState &s);
 
 struct Task {
     int a = 0, parity = 0, rows = 0, cols = 0;
@@ -65,6 +87,7 @@ struct BuildStats {
     int64_t stored = 0;          // stored factor entries
     int64_t n_dense = 0, n_lowrank = 0, n_butterfly = 0, n_dropped = 0;
     int64_t dense_stored = 0, lowrank_stored = 0, butterfly_stored = 0;
+    int64_t n_gen = 0, gen_entries = 0;   // regenerated dense blocks and their area
     int max_rank = 0;
     double seconds = 0.0;
     int64_t region_stored[3][3] = {{0}};  // [region][type]
@@ -83,9 +106,6 @@ struct HostPlanData {
 // Build every task (all orders, both parities).
 int build_all(int N, const sht_plan_opts &opts, HostPlanData &out);
 
-// Host application of the factors of one task (verification only):
-// dir 0: y[rows][R] = A x[cols][R];  dir 2: y[cols][R] = A^T x[rows][R].
-void host_apply_task(const Task &t, int dir, int R, const double *x, double *y);
 
 }  // namespace idbf
 }  // namespace sht

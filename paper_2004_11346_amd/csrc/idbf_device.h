@@ -17,6 +17,9 @@ struct DeviceProgramDir {
     Op *d_ops = nullptr;
     SubOp *d_subs = nullptr;
     int32_t *d_idx = nullptr;
+    double *d_ck = nullptr;      // recurrence states (p0, p1) of generated sub-ops
+    int32_t *d_ckexp = nullptr;  // their exponents
+    bool gen = false;
     // stage_task_first[s][t]: first op (global index) of task t in stage s;
     // entry ntask is the stage end
     std::vector<std::vector<int32_t>> stage_task_first;
@@ -30,6 +33,8 @@ struct DeviceProgram {
     void *d_X = nullptr, *d_Y = nullptr, *d_scrA = nullptr, *d_scrB = nullptr;
     int64_t *d_x_off = nullptr;    // [4N + 1]
     const double *d_wh = nullptr;  // half-grid weights (owned by the plan)
+    const double *d_xh = nullptr;    // half-grid nodes (owned by the plan)
+    const double *d_coef = nullptr;  // recurrence coefficient pairs (owned by the plan)
     std::vector<int64_t> x_off_h, y_off_h;
     int64_t max_task_cols = 0;
     int64_t index_bytes = 0;

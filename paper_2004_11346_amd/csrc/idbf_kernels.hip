@@ -6,12 +6,17 @@
 // 2N-1-r).  k_pack / k_scatter move between beta and X, k_combine / k_fold
 // between Y and the (l, m mod M) grid with the parity split of Section 3.1.2.
 //
-// k_ops executes one stage of the program: one wave per op (see below); ops of
-// input rows are gathered into LDS, each stored matrix block is copied into LDS
-// with coalesced loads, and the products, identity (skeleton) terms and the
-// final write (scratch) or accumulation (output panel) follow.  Ops of one
-// stage never write the same rows, so there are no atomics and the result is
-// bitwise reproducible.
+// k_ops executes one stage of the program: one wave per op (see below); the
+// input rows of each sub-op are gathered into LDS, the stored matrix streams
+// from HBM output-major (consecutive lanes, consecutive words), and the
+// products, identity (skeleton) terms and the final write (scratch) or
+// accumulation (output panel) follow.  Ops of one stage never write the same
+// rows, so there are no atomics and the result is bitwise reproducible.
+//
+// Generated sub-ops (dense blocks near the turning point, Section 3.2) carry
+// no values: each lane walks the three-term recurrence of one node from a
+// stored state (two FP64 steps per column, same parity), rescaling by exact
+// powers of two as the table builder does.
 #include <hip/hip_runtime.h>
 
 #include "idbf_device.h"
@@ -32,6 +37,28 @@ __device__ __forceinline__ int64_t d_coef_offset(int N, int m) {
     return off;
 }
 
+constexpr int kGT = 65;  // row stride of the LDS tile of a generated block
+
+__device__ __forceinline__ double scale_of(int e) { return e < -1074 ? 0.0 : ldexp(1.0, e); }
+
+// two recurrence steps (to the next column of the same parity); cf points at
+// the coefficient pairs of the two new degrees
+__device__ __forceinline__ void gen_step2(const double *__restrict__ cf, double x, double &p0, double &p1, int &e,
+                                          double &sc) {
+    double p2 = cf[0] * (x * p1 - cf[1] * p0);
+    p0 = p1;
+    p1 = p2;
+    p2 = cf[2] * (x * p1 - cf[3] * p0);
+    p0 = p1;
+    p1 = p2;
+    if (fabs(p1) > 0x1p200) {
+        p0 *= 0x1p-200;
+        p1 *= 0x1p-200;
+        e += 200;
+        sc = scale_of(e);
+    }
+}
+
 // One wave per op.  Lanes own matrix outputs: lane q of a sub-op streams
 // column q of its output-major matrix (consecutive lanes, consecutive words)
 // and keeps the RC right-hand-side sums in registers; the gathered input rows
@@ -41,16 +68,89 @@ __global__ __launch_bounds__(64) void k_ops(const Op *__restrict__ ops, const Su
                                             const int32_t *__restrict__ idx, const T *__restrict__ vals,
                                             int op_begin, const T *__restrict__ in, int64_t in_stride,
                                             T *__restrict__ out, int64_t out_stride, T *__restrict__ scrA,
-                                            T *__restrict__ scrB, int rc, int max_out) {
+                                            T *__restrict__ scrB, int rc, int max_out, int max_in,
+                                            const double *__restrict__ xh, const double *__restrict__ coef,
+                                            const double *__restrict__ ck, const int32_t *__restrict__ ckexp) {
     extern __shared__ unsigned char smem_raw[];
     T *acc = reinterpret_cast<T *>(smem_raw);
     T *xin = acc + (size_t)max_out * RC;
+    T *gt = xin + (size_t)max_in * RC;  // [64][kGT] tile of a transposed generated block
     const Op op = ops[op_begin + blockIdx.x];
     const int lane = threadIdx.x;
     const int n_out = op.n_out;
     for (int e = lane; e < n_out * RC; e += 64) acc[e] = (T)0;
     for (int s = 0; s < op.nsub; ++s) {
         const SubOp sb = subs[op.sub0 + s];
+        if (sb.src == kGen) {
+            const int nin = sb.n_in, nmap = sb.n_map;
+            const bool fwd = sb.pad == 0;
+            __syncthreads();
+            for (int e = lane; e < nin * RC; e += 64) {
+                const int j = e / RC, r = e - j * RC;
+                xin[e] = r < rc ? in[(int64_t)(sb.in_off + j) * in_stride + r] : (T)0;
+            }
+            __syncthreads();
+            const int ngen = fwd ? nmap : nin, ncol = fwd ? nin : nmap;
+            double p0 = 0.0, p1 = 0.0, x = 0.0, sc = 0.0;
+            int ex = 0;
+            if (lane < ngen) {
+                p0 = ck[2 * (sb.mat_off + lane)];
+                p1 = ck[2 * (sb.mat_off + lane) + 1];
+                ex = ckexp[sb.mat_off + lane];
+                sc = scale_of(ex);
+                x = xh[sb.dir_off + lane];
+            }
+            const double *cf = coef + 2 * (int64_t)sb.n_dir;
+            if (fwd) {
+                T a[RC];
+#pragma unroll
+                for (int r = 0; r < RC; ++r) a[r] = (T)0;
+                for (int t = 0; t < ncol; ++t) {
+                    if (t > 0) gen_step2(cf + 4 * t - 2, x, p0, p1, ex, sc);
+                    const T v = (T)(p1 * sc);
+#pragma unroll
+                    for (int r = 0; r < RC; ++r) a[r] += v * xin[t * RC + r];
+                }
+                if (lane < ngen)
+#pragma unroll
+                    for (int r = 0; r < RC; ++r) acc[(sb.map_off + lane) * RC + r] += a[r];
+            } else {
+                // transposed: the block's rows walk 16 columns at a time into
+                // an LDS tile; lane (column tq, row quarter qq) then sums 16
+                // rows and the four quarters are combined across lanes
+                const int tq = lane & 15, qq = lane >> 4;
+                for (int t0 = 0; t0 < ncol; t0 += 16) {
+                    const int tn = min(16, ncol - t0);
+                    for (int tt = 0; tt < tn; ++tt) {
+                        const int t = t0 + tt;
+                        if (t > 0) gen_step2(cf + 4 * t - 2, x, p0, p1, ex, sc);
+                        gt[tt * kGT + lane] = lane < ngen ? (T)(p1 * sc) : (T)0;
+                    }
+                    __syncthreads();
+                    T a[RC];
+#pragma unroll
+                    for (int r = 0; r < RC; ++r) a[r] = (T)0;
+                    if (tq < tn) {
+                        const int i1 = min(ngen, 16 * qq + 16);
+                        for (int i = 16 * qq; i < i1; ++i) {
+                            const T g = gt[tq * kGT + i];
+#pragma unroll
+                            for (int r = 0; r < RC; ++r) a[r] += g * xin[i * RC + r];
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < RC; ++r) {
+                        a[r] += __shfl_xor(a[r], 16);
+                        a[r] += __shfl_xor(a[r], 32);
+                    }
+                    if (qq == 0 && tq < tn)
+#pragma unroll
+                        for (int r = 0; r < RC; ++r) acc[(sb.map_off + t0 + tq) * RC + r] += a[r];
+                    __syncthreads();
+                }
+            }
+            continue;
+        }
         const T *src;
         int64_t sstride;
         if (sb.src == kIn) {
@@ -139,20 +239,24 @@ __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, co
                                                   int op_begin, const double *__restrict__ in, int64_t in_stride,
                                                   double *__restrict__ out, int64_t out_stride,
                                                   double *__restrict__ scrA, double *__restrict__ scrB, int rc,
-                                                  int max_out) {
+                                                  int max_out, int max_in, const double *__restrict__ xh,
+                                                  const double *__restrict__ coef, const double *__restrict__ ck,
+                                                  const int32_t *__restrict__ ckexp) {
     constexpr int NCB = RCW / 16;
     extern __shared__ unsigned char smem_raw[];
     double *acc = reinterpret_cast<double *>(smem_raw);
     double *xin = acc + (size_t)max_out * RCW;
+    double *gt = xin + (size_t)((max_in + 3) & ~3) * RCW;  // [64][kGT] generated block, outputs x inputs
     const Op op = ops[op_begin + blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n_out = op.n_out;
     for (int e = tid; e < n_out * RCW; e += 256) acc[e] = 0.0;
     for (int s = 0; s < op.nsub; ++s) {
         const SubOp sb = subs[op.sub0 + s];
+        const bool gen = sb.src == kGen;
         const double *src;
         int64_t sstride;
-        if (sb.src == kIn) {
+        if (sb.src == kIn || gen) {
             src = in;
             sstride = in_stride;
         } else {
@@ -166,7 +270,29 @@ __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, co
             const int nin4 = (nin + 3) & ~3;
             for (int e = tid; e < nin4 * RCW; e += 256) {
                 const int j = e / RCW, c = e - j * RCW;
-                xin[e] = (j < nin && c < rc) ? src[(int64_t)inr[j] * sstride + c] : 0.0;
+                const int64_t row = gen ? (int64_t)sb.in_off + j : (int64_t)inr[j < nin ? j : 0];
+                xin[e] = (j < nin && c < rc) ? src[row * sstride + c] : 0.0;
+            }
+            const bool gfwd = gen && sb.pad == 0;
+            if (gen && !gfwd) {
+                // transposed generated block into LDS (outputs x inputs):
+                // thread (row i, quarter w) walks columns [16 w, 16 w + 16)
+                // from the state stored there
+                const int ngen = nin, ncol = nmap;
+                const int i = lane, c0 = 16 * wave;
+                if (i < ngen && c0 < ncol) {
+                    const int64_t si = sb.mat_off + (int64_t)wave * ngen + i;
+                    double p0 = ck[2 * si], p1 = ck[2 * si + 1];
+                    int ex = ckexp[si];
+                    double sc = scale_of(ex);
+                    const double x = xh[sb.dir_off + i];
+                    const double *cf = coef + 2 * (int64_t)sb.n_dir;
+                    const int c1 = min(ncol, c0 + 16);
+                    for (int t = c0; t < c1; ++t) {
+                        if (t > c0) gen_step2(cf + 4 * t - 2, x, p0, p1, ex, sc);
+                        gt[t * kGT + i] = p1 * sc;
+                    }
+                }
             }
             __syncthreads();
             const int32_t *map = idx + sb.map_off;
@@ -175,10 +301,43 @@ __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, co
             for (int t = wave; t < ntile; t += 4) {
                 const int q = t * 16 + cl;
                 double areg[16];
+                if (gfwd) {
+                    // forward generated block: lane walks row q over all the
+                    // inputs and keeps the columns j = 4 st + jl of its A slots
+                    double p0 = 0.0, p1 = 0.0, x = 0.0, sc = 0.0;
+                    int ex = 0;
+                    if (q < nmap) {
+                        p0 = ck[2 * (sb.mat_off + q)];
+                        p1 = ck[2 * (sb.mat_off + q) + 1];
+                        ex = ckexp[sb.mat_off + q];
+                        sc = scale_of(ex);
+                        x = xh[sb.dir_off + q];
+                    }
+                    const double *cf = coef + 2 * (int64_t)sb.n_dir;
 #pragma unroll
-                for (int st = 0; st < 16; ++st) {
-                    const int j = 4 * st + jl;
-                    areg[st] = (q < nmap && j < nin) ? vals[sb.mat_off + (int64_t)j * nmap + q] : 0.0;
+                    for (int st = 0; st < 16; ++st) {
+                        areg[st] = 0.0;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int j = 4 * st + u;
+                            if (j < nin) {
+                                if (j > 0) gen_step2(cf + 4 * j - 2, x, p0, p1, ex, sc);
+                                if (u == jl) areg[st] = p1 * sc;
+                            }
+                        }
+                    }
+                } else if (gen) {
+#pragma unroll
+                    for (int st = 0; st < 16; ++st) {
+                        const int j = 4 * st + jl;
+                        areg[st] = (q < nmap && j < nin) ? gt[q * kGT + j] : 0.0;
+                    }
+                } else {
+#pragma unroll
+                    for (int st = 0; st < 16; ++st) {
+                        const int j = 4 * st + jl;
+                        areg[st] = (q < nmap && j < nin) ? vals[sb.mat_off + (int64_t)j * nmap + q] : 0.0;
+                    }
                 }
                 d4v D[NCB];
 #pragma unroll
@@ -195,7 +354,7 @@ __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, co
                 for (int i = 0; i < 4; ++i) {
                     const int qq = t * 16 + jl + 4 * i;
                     if (qq < nmap) {
-                        double *ar = acc + map[qq] * RCW + cl;
+                        double *ar = acc + (gen ? sb.map_off + qq : map[qq]) * RCW + cl;
 #pragma unroll
                         for (int cb = 0; cb < NCB; ++cb) ar[cb * 16] += D[cb][i];
                     }
@@ -203,7 +362,7 @@ __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, co
             }
         }
         __syncthreads();
-        if (sb.n_dir > 0) {
+        if (!gen && sb.n_dir > 0) {
             const int32_t *dir = idx + sb.dir_off;
             for (int e = tid; e < sb.n_dir * RCW; e += 256) {
                 const int d = e / RCW, c = e - d * RCW;
@@ -254,8 +413,16 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
             if (oe <= ob) continue;
             const Stage &sg = pd.stages[st];
             const int mo = std::max(1, (int)sg.max_out), mi = std::max(4, ((int)sg.max_in + 3) & ~3);
-            const size_t lds = sizeof(T) * (size_t)(mo + mi) * RC;
-            prof::Scope ps(s, mfma ? "k_ops_mfma" : "k_ops");
+            // LDS tile of transposed generated blocks: 64 x 64 (matrix cores)
+            // or 16 x 64 (VALU)
+            const size_t gtile = (sg.gen & 2) ? (size_t)(mfma ? 64 : 16) * kGT : 0;
+            const size_t lds = sizeof(T) * ((size_t)(mo + mi) * RC + gtile);
+            if (lds > 160 * 1024) return hipErrorInvalidValue;
+            const double *ck = pd.d_ck;
+            const int32_t *cke = pd.d_ckexp;
+            const bool last = st + 1 == pd.stage_task_first.size();
+            prof::Scope ps(s, mfma ? (last ? "k_ops_mfma[final]" : "k_ops_mfma[levels]")
+                                   : (last ? "k_ops[final]" : "k_ops[levels]"));
             if (mfma) {
                 const double *vd = (const double *)vals;
                 const double *ind = (const double *)(in + c0);
@@ -263,20 +430,20 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
                 if (RC == 128)
                     hipLaunchKernelGGL((k_ops_mfma<128>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
                                        pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
-                                       (double *)scrB, rc, mo);
+                                       (double *)scrB, rc, mo, mi, p.d_xh, p.d_coef, ck, cke);
                 else if (RC == 64)
                     hipLaunchKernelGGL((k_ops_mfma<64>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
                                        pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
-                                       (double *)scrB, rc, mo);
+                                       (double *)scrB, rc, mo, mi, p.d_xh, p.d_coef, ck, cke);
                 else
                     hipLaunchKernelGGL((k_ops_mfma<32>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
                                        pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
-                                       (double *)scrB, rc, mo);
+                                       (double *)scrB, rc, mo, mi, p.d_xh, p.d_coef, ck, cke);
                 continue;
             }
 #define SHT_OPS_LAUNCH(RCV)                                                                                      \
     hipLaunchKernelGGL((k_ops<T, RCV>), dim3(oe - ob), dim3(64), lds, s, pd.d_ops, pd.d_subs, pd.d_idx, vals, ob, \
-                       (const T *)(in + c0), (int64_t)R, out + c0, (int64_t)R, scrA, scrB, rc, mo)
+                       (const T *)(in + c0), (int64_t)R, out + c0, (int64_t)R, scrA, scrB, rc, mo, mi, p.d_xh, p.d_coef, ck, cke)
             if (RC == 4)
                 SHT_OPS_LAUNCH(4);
             else if (RC == 8)

@@ -35,6 +35,13 @@ hipError_t upload_dir(Program &p, int ntask, int dtype, DeviceProgramDir &d) {
     if ((e = up(p.ops, &d.d_ops)) != hipSuccess) return e;
     if ((e = up(p.subs, &d.d_subs)) != hipSuccess) return e;
     if ((e = up(p.idx, &d.d_idx)) != hipSuccess) return e;
+    if ((e = up(p.ck, &d.d_ck)) != hipSuccess) return e;
+    if ((e = up(p.ckexp, &d.d_ckexp)) != hipSuccess) return e;
+    d.gen = !p.ckexp.empty();
+    p.ck.clear();
+    p.ck.shrink_to_fit();
+    p.ckexp.clear();
+    p.ckexp.shrink_to_fit();
     d.stages = p.stages;
     d.stage_task_first.clear();
     for (const Stage &st : p.stages) {
@@ -61,7 +68,8 @@ int fail(hipError_t e, const char *what) {
 
 void DeviceProgram::release() {
     for (void *p : {d_X, d_Y, d_scrA, d_scrB, (void *)d_x_off, fwd.d_vals, (void *)fwd.d_ops, (void *)fwd.d_subs,
-                    (void *)fwd.d_idx, adj.d_vals, (void *)adj.d_ops, (void *)adj.d_subs, (void *)adj.d_idx})
+                    (void *)fwd.d_idx, (void *)fwd.d_ck, (void *)fwd.d_ckexp, adj.d_vals, (void *)adj.d_ops,
+                    (void *)adj.d_subs, (void *)adj.d_idx, (void *)adj.d_ck, (void *)adj.d_ckexp})
         if (p) (void)hipFree(p);
     d_X = d_Y = d_scrA = d_scrB = nullptr;
     d_x_off = nullptr;
@@ -85,7 +93,9 @@ int build_program(int N, const LegendreTables &lt, const sht_plan_opts &opts, Ho
                         (int64_t)(out.packed.fwd.ops.size() + out.packed.adj.ops.size()) * sizeof(Op) +
                         (int64_t)(out.packed.fwd.subs.size() + out.packed.adj.subs.size()) * sizeof(SubOp);
     os << base << ",\"fwd_values\":" << out.packed.fwd.vals.size() << ",\"adj_values\":" << out.packed.adj.vals.size()
-       << ",\"index_bytes\":" << idx_bytes
+       << ",\"index_bytes\":" << idx_bytes << ",\"ckpt_states\":"
+       << (out.packed.fwd.ckexp.size() + out.packed.adj.ckexp.size()) << ",\"ckpt_bytes\":"
+       << 20 * (int64_t)(out.packed.fwd.ckexp.size() + out.packed.adj.ckexp.size())
        << ",\"fwd_stages\":" << out.packed.fwd.stages.size() << ",\"fwd_work_stages\":"
        << out.packed.fwd.n_work_stages << ",\"adj_stages\":" << out.packed.adj.stages.size()
        << ",\"fwd_ops\":" << out.packed.fwd.ops.size() << ",\"scratch_rows\":"
@@ -94,7 +104,8 @@ int build_program(int N, const LegendreTables &lt, const sht_plan_opts &opts, Ho
     return SHT_OK;
 }
 
-int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, DeviceProgram &d) {
+int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, const double *d_xh,
+                   const double *d_coef, DeviceProgram &d) {
     hipError_t e;
     PackedPlan &pk = hp.packed;
     const int N = hp.N, ntask = 4 * N;
@@ -111,7 +122,11 @@ int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, De
         int v = std::atoi(e);
         d.RCW = (dtype == SHT_F64 && (v == 32 || v == 64 || v == 128)) ? v : 0;
     }
+    if (d.RCW == 128 && (!hp.packed.fwd.ckexp.empty() || !hp.packed.adj.ckexp.empty()))
+        d.RCW = 64;  // 128 columns leave no LDS for the tile of a generated block
     d.d_wh = d_wh;
+    d.d_xh = d_xh;
+    d.d_coef = d_coef;
     if ((e = upload_dir(hp.packed.fwd, ntask, dtype, d.fwd)) != hipSuccess) return fail(e, "upload program");
     if ((e = upload_dir(hp.packed.adj, ntask, dtype, d.adj)) != hipSuccess) return fail(e, "upload program");
     d.x_off_h = pk.x_off;

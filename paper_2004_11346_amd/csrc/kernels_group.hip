@@ -1,0 +1,164 @@
+// Persistent kernels of grouped transforms (see group.h).  Every workgroup
+// loops: one lane takes the next item index from the phase's counter (a
+// vector atomic in global memory), the index is shared through LDS, and the
+// workgroup runs the same device bodies as the per-plan kernels for that
+// item.  Items are ordered by decreasing cost, so the queue drains longest
+// first and the tail is short.  Each item is computed by one workgroup from
+// start to end, so results do not depend on the schedule.
+#include <hip/hip_runtime.h>
+
+#include "dense_device.h"
+#include "dft_device.h"
+#include "group.h"
+#include "prof.h"
+
+namespace sht {
+namespace group {
+
+namespace {
+
+using namespace dev::dense;
+
+constexpr int kNpl = 2;  // nodes per lane in the forward ALT items
+
+__global__ void k_group_reset(int *counters, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) counters[i] = 0;
+}
+
+__device__ __forceinline__ int next_item(int *counter, int *slot) {
+    if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = *slot;
+    __syncthreads();
+    return it;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_group_fwd(const GTrans *__restrict__ tr, const GItem *__restrict__ items,
+                                                  int nitems, int *counter) {
+    __shared__ double lds[fwd_tile_lds(4)];
+    __shared__ int slot;
+    for (;;) {
+        const int it = next_item(counter, &slot);
+        if (it >= nitems) break;
+        const GItem w = items[it];
+        const GTrans &d = tr[w.t];
+        const T *beta = (const T *)d.beta;
+        T *f = (T *)d.f;
+        switch (d.fields) {
+            case 1: dense_fwd_tile<T, 1, kNpl>(d.N, d.M, 1, w.a, w.b, d.xh, d.dmant, d.dexp, d.coef, beta, f, lds); break;
+            case 2: dense_fwd_tile<T, 2, kNpl>(d.N, d.M, 2, w.a, w.b, d.xh, d.dmant, d.dexp, d.coef, beta, f, lds); break;
+            case 3: dense_fwd_tile<T, 3, kNpl>(d.N, d.M, 3, w.a, w.b, d.xh, d.dmant, d.dexp, d.coef, beta, f, lds); break;
+            default: dense_fwd_tile<T, 4, kNpl>(d.N, d.M, d.fields, w.a, w.b, d.xh, d.dmant, d.dexp, d.coef, beta, f, lds); break;
+        }
+    }
+}
+
+// 4 waves, four nodes per lane (N <= 1024), one field per pass
+template <typename T>
+__global__ __launch_bounds__(256) void k_group_adj(const GTrans *__restrict__ tr, const GItem *__restrict__ items,
+                                                   int nitems, int *counter) {
+    __shared__ double red[4 * 64];
+    __shared__ int slot;
+    for (;;) {
+        const int it = next_item(counter, &slot);
+        if (it >= nitems) break;
+        const GItem w = items[it];
+        const GTrans &d = tr[w.t];
+        const T *g = (const T *)d.g;
+        T *beta = (T *)d.beta;
+        for (int b0 = 0; b0 < d.fields; ++b0)
+            dense_adj_order<T, 1, 4>(d.N, d.M, d.fields, b0, w.a, 4, d.xh, d.wh, d.dmant, d.dexp, d.coef, g, beta,
+                                     red);
+    }
+}
+
+// mode 0: synthesis in place on f; mode 1: analysis f -> g (scale 1/M)
+template <typename C, typename T>
+__global__ __launch_bounds__(512) void k_group_dft(const GTrans *__restrict__ tr, const GItem *__restrict__ items,
+                                                   int nitems, int *counter, int mode) {
+    extern __shared__ unsigned char smem_raw[];
+    typename dev::dft::V2<C>::t *buf = reinterpret_cast<typename dev::dft::V2<C>::t *>(smem_raw);
+    __shared__ int slot;
+    __shared__ dev::dft::Passes ps;
+    for (;;) {
+        const int it = next_item(counter, &slot);
+        if (it >= nitems) break;
+        const GItem w = items[it];
+        const GTrans &d = tr[w.t];
+        if (threadIdx.x == 0) {
+            ps.n = d.npass;
+            for (int i = 0; i < kMaxPass; ++i) {
+                ps.R[i] = d.R[i];
+                ps.L[i] = d.L[i];
+            }
+        }
+        __syncthreads();
+        const int64_t base = 2 * ((int64_t)w.a * 2 * d.N * d.M + (int64_t)w.b * d.M);
+        const C *tw = sizeof(C) == 8 ? (const C *)d.tw2 : (const C *)d.tw2f;
+        if (mode == 0) {
+            T *row = (T *)d.f + base;
+            dev::dft::dft_row<C, T>(d.N, d.M, ps, tw, d.src_pos, 0, (C)1, row, row, buf);
+        } else {
+            dev::dft::dft_row<C, T>(d.N, d.M, ps, tw, d.src_pos, 1, (C)(1.0 / d.M), (const T *)d.f + base,
+                                    (T *)d.g + base, buf);
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+int fwd_rows_per_tile() { return 64 * kNpl; }
+
+hipError_t init_attributes() {
+    for (const void *fn : {(const void *)&k_group_dft<double, double>, (const void *)&k_group_dft<float, float>}) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_reset(int *counters, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_reset, dim3((n + 63) / 64), dim3(64), 0, s, counters, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase(int phase, int dtype, int grid, const GTrans *tr, const GItem *items, int nitems,
+                        int *counter, int max_M, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    switch (phase) {
+        case kFwdAlt: {
+            prof::Scope ps(s, "k_group_fwd");
+            if (dtype == 0)
+                hipLaunchKernelGGL(k_group_fwd<double>, dim3(grid), dim3(64), 0, s, tr, items, nitems, counter);
+            else
+                hipLaunchKernelGGL(k_group_fwd<float>, dim3(grid), dim3(64), 0, s, tr, items, nitems, counter);
+            break;
+        }
+        case kAdjAlt: {
+            prof::Scope ps(s, "k_group_adj");
+            if (dtype == 0)
+                hipLaunchKernelGGL(k_group_adj<double>, dim3(grid), dim3(256), 0, s, tr, items, nitems, counter);
+            else
+                hipLaunchKernelGGL(k_group_adj<float>, dim3(grid), dim3(256), 0, s, tr, items, nitems, counter);
+            break;
+        }
+        default: {
+            const int mode = phase == kDftSyn ? 0 : 1;
+            prof::Scope ps(s, mode == 0 ? "k_group_dft_synthesis" : "k_group_dft_analysis");
+            const size_t lds = (dtype == 0 ? 16 : 8) * (size_t)max_M;
+            if (dtype == 0)
+                hipLaunchKernelGGL((k_group_dft<double, double>), dim3(grid), dim3(512), lds, s, tr, items, nitems,
+                                   counter, mode);
+            else
+                hipLaunchKernelGGL((k_group_dft<float, float>), dim3(grid), dim3(512), lds, s, tr, items, nitems,
+                                   counter, mode);
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace group
+}  // namespace sht

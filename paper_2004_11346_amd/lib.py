@@ -28,6 +28,8 @@ EXPORTED = [
     "sht_backward", "sht_alt_apply", "sht_plan_stats", "sht_profile", "sht_profile_report", "sht_plan_info", "sht_plan_nodes",
     "sht_strerror", "sht_last_error_detail", "sht_host_plan_create", "sht_host_plan_destroy",
     "sht_host_plan_apply", "sht_host_alt_matrix", "sht_host_plan_stats", "sht_host_gauss_legendre",
+    "sht_group_create", "sht_group_destroy", "sht_group_bind", "sht_group_forward", "sht_group_inverse",
+    "sht_group_tune", "sht_group_capture", "sht_group_replay", "sht_group_stats",
 ]
 
 
@@ -51,6 +53,7 @@ class PlanOpts(ctypes.Structure):
         ("threads", ctypes.c_int),
         ("f32_mode", ctypes.c_int),
         ("min_idbf", ctypes.c_int),
+        ("dense_gen", ctypes.c_int),
     ]
 
 
@@ -96,6 +99,15 @@ def load():
         lib.sht_host_alt_matrix.argtypes = [P, I, I, P]
         lib.sht_host_plan_stats.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
         lib.sht_host_gauss_legendre.argtypes = [I, P, P]
+        lib.sht_group_create.argtypes = [I, P, P, I, PP]
+        lib.sht_group_destroy.argtypes = [P]
+        lib.sht_group_destroy.restype = None
+        lib.sht_group_bind.argtypes = [P, P, P]
+        for n in ("sht_group_forward", "sht_group_inverse", "sht_group_tune"):
+            getattr(lib, n).argtypes = [P, P]
+        lib.sht_group_capture.argtypes = [P, I, P]
+        lib.sht_group_replay.argtypes = [P, I, P]
+        lib.sht_group_stats.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
         for n in EXPORTED:
             f = getattr(lib, n)
             if f.restype is ctypes.c_int or n in ("sht_plan_create", "sht_forward", "sht_inverse",

@@ -160,3 +160,80 @@ def host_gauss_legendre(n: int):
     w = np.empty(n)
     _l.check(_l.load().sht_host_gauss_legendre(n, x.ctypes.data, w.ctypes.data), "sht_host_gauss_legendre")
     return x, w
+
+
+class Group:
+    """Many independent transforms of different degrees (``Ns[i]``, 1..1024)
+    and field counts (``fields[i]``, 1..4) applied together by persistent
+    kernels.  Bind the per-transform tensors once, then call ``forward`` /
+    ``inverse`` (or capture them into a hipGraph and ``replay``)."""
+
+    def __init__(self, Ns, fields, dtype=torch.complex128):
+        self._lib = _l.load()
+        self.Ns = [int(n) for n in Ns]
+        self.fields = [int(f) for f in fields]
+        if len(self.Ns) != len(self.fields):
+            raise ValueError("Ns and fields must have the same length")
+        self.dtype = dtype
+        n = len(self.Ns)
+        arr = ctypes.c_int * n
+        h = ctypes.c_void_p()
+        _l.check(self._lib.sht_group_create(n, arr(*self.Ns), arr(*self.fields), _DT[dtype], ctypes.byref(h)),
+                 "sht_group_create")
+        self._h = h
+        self._bound = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sht_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def coef_shape(self, i):
+        return (self.fields[i], 4 * self.Ns[i] ** 2)
+
+    def grid_shape(self, i):
+        return (self.fields[i], 2 * self.Ns[i], 4 * self.Ns[i] - 1)
+
+    def bind(self, betas, fs):
+        """betas[i]: [fields_i, 4 N_i^2], fs[i]: [fields_i, 2 N_i, 4 N_i - 1]
+        (complex, contiguous, on the GPU).  The tensors must stay alive."""
+        n = len(self.Ns)
+        if len(betas) != n or len(fs) != n:
+            raise ValueError("one beta and one f tensor per transform")
+        for i in range(n):
+            for t, shp, nm in ((betas[i], self.coef_shape(i), "beta"), (fs[i], self.grid_shape(i), "f")):
+                if not t.is_cuda or t.dtype != self.dtype or tuple(t.shape) != shp or not t.is_contiguous():
+                    raise ValueError(f"{nm}[{i}] must be a contiguous {self.dtype} CUDA tensor of shape {shp}")
+        arr = ctypes.c_void_p * n
+        _l.check(self._lib.sht_group_bind(self._h, arr(*[b.data_ptr() for b in betas]),
+                                          arr(*[f.data_ptr() for f in fs])), "sht_group_bind")
+        self._bound = (list(betas), list(fs))
+
+    def forward(self, stream=None):
+        _l.check(self._lib.sht_group_forward(self._h, ctypes.c_void_p(_stream_ptr(stream))), "sht_group_forward")
+
+    def inverse(self, stream=None):
+        _l.check(self._lib.sht_group_inverse(self._h, ctypes.c_void_p(_stream_ptr(stream))), "sht_group_inverse")
+
+    def tune(self, stream=None):
+        _l.check(self._lib.sht_group_tune(self._h, ctypes.c_void_p(_stream_ptr(stream))), "sht_group_tune")
+
+    def capture(self, direction: str, stream):
+        d = {"fwd": _l.SHT_FWD, "inv": _l.SHT_INV}[direction]
+        _l.check(self._lib.sht_group_capture(self._h, d, ctypes.c_void_p(_stream_ptr(stream))), "sht_group_capture")
+
+    def replay(self, direction: str, stream=None):
+        d = {"fwd": _l.SHT_FWD, "inv": _l.SHT_INV}[direction]
+        _l.check(self._lib.sht_group_replay(self._h, d, ctypes.c_void_p(_stream_ptr(stream))), "sht_group_replay")
+
+    def stats(self) -> dict:
+        n = _l.check(self._lib.sht_group_stats(self._h, None, 0), "sht_group_stats")
+        buf = ctypes.create_string_buffer(n)
+        _l.check(self._lib.sht_group_stats(self._h, buf, n), "sht_group_stats")
+        return json.loads(buf.value.decode())

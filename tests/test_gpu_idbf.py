@@ -29,6 +29,7 @@ def _dev(a, dtype=torch.complex128):
 CASES = [
     (16, 1, dict(n0=8, leaf=2)),
     (64, 1, dict(n0=32, leaf=8)),
+    (64, 2, dict(n0=32, leaf=8, dense_gen=0)),
     (64, 3, dict(n0=32, leaf=8)),
     (100, 2, dict(n0=48, leaf=8)),
     (130, 1, dict()),
@@ -131,7 +132,8 @@ def test_idbf_matrix_core_path(N, batch, rcw, monkeypatch):
     print(f"idbf mfma N={N} batch={batch} rcw={rcw}", flush=True)
     if rcw:
         monkeypatch.setenv("SHT_IDBF_RCW", rcw)
-    p = _plan(N, batch, n0=32, leaf=8)
+    # 128 columns per pass only fit in LDS when dense blocks are stored
+    p = _plan(N, batch, n0=32, leaf=8, **({"dense_gen": 0} if rcw == "128" else {}))
     beta = inputs.make_beta(N, batch, 6)
     f = p.forward(_dev(beta)).cpu().numpy()
     grid = inputs.make_grid(N, batch, 6)

@@ -268,6 +268,16 @@ def test_round_trip_and_parseval(N):
     assert abs(lhs - rhs) <= 1e-13 * rhs
 
 
+def test_alt_rows_match_grid():
+    """The row-subset ALT repeats the full-grid sums at the listed nodes (the
+    full grid is pinned by the closed forms and identities above)."""
+    N = 8
+    beta = inputs.make_beta(N, 1, 92)[0]
+    g = oracle.alt_forward(N, beta)
+    rows = [0, 3, 7, 8, 15]
+    np.testing.assert_array_equal(oracle.alt_forward_rows(N, beta, rows), g[rows])
+
+
 def test_single_mode_sht():
     """beta = e_{k0,m0}  =>  f(theta_l, phi_j) = Pbar_{k0}^{|m0|}(x_l) e^{i m0 phi_j}."""
     N = 5
