@@ -77,7 +77,10 @@ extern "C" {
 
 /* F32 arithmetic for the IDBF block products */
 #define SHT_F32_VALU 0       /* FP32 products on the vector ALUs */
-#define SHT_F32_SPLIT_BF16 1 /* split-BF16 three-product MFMA, FP32 accumulate */
+#define SHT_F32_SPLIT_BF16 1 /* split-BF16 three-product MFMA, FP32 accumulate
+                                (two BF16 parts per value: about 4e-6 relative) */
+#define SHT_F32_SPLIT_BF16_6 2 /* six products of three BF16 parts per value
+                                  (FP32 accuracy on the BF16 matrix cores) */
 
 /* ID row sampling (Section 2.1) */
 #define SHT_SAMPLE_MOCK_CHEB 0
@@ -100,7 +103,8 @@ typedef struct sht_plan_opts {
     int sampling;      /* SHT_SAMPLE_MOCK_CHEB or SHT_SAMPLE_RANDOM */
     uint64_t seed;     /* seed of every random choice of the plan */
     int threads;       /* host threads for plan construction (0 = all) */
-    int f32_mode;      /* SHT_F32_VALU or SHT_F32_SPLIT_BF16 (F32 plans) */
+    int f32_mode;      /* SHT_F32_VALU, SHT_F32_SPLIT_BF16 or SHT_F32_SPLIT_BF16_6
+                          (FP32 plans of the fast form) */
     int min_idbf;      /* smallest block side given an IDBF (default 4*leaf) */
     int dense_gen;     /* 1 (default): dense blocks of the fast form are not
                           stored; the kernels regenerate their entries with the

@@ -178,6 +178,13 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
     sht_plan_opts_default(&p->opts);
     if (opts) p->opts = *opts;
     HIP_TRY(hipGetDevice(&p->device), "hipGetDevice");
+    if (p->opts.f32_mode != SHT_F32_VALU && p->opts.f32_mode != SHT_F32_SPLIT_BF16 &&
+        p->opts.f32_mode != SHT_F32_SPLIT_BF16_6)
+        return SHT_ERR_INVALID_ARG;
+    if (p->opts.f32_mode != SHT_F32_VALU && (dtype != SHT_F32 || method != SHT_IDBF)) {
+        set_error_detail("split-BF16 products apply to FP32 plans of the fast form");
+        return SHT_ERR_UNSUPPORTED;
+    }
     if (!dev::dft_supported(p->M, dtype)) {
         set_error_detail("phi DFT row does not fit in LDS for this N and dtype");
         return SHT_ERR_UNSUPPORTED;

@@ -23,6 +23,7 @@ namespace idbf {
 
 struct HostProgram {
     int N = 0;
+    int f32_mode = 0;  // SHT_F32_VALU or SHT_F32_SPLIT_BF16
     PackedPlan packed;
     BuildStats stats;
     std::string stats_json;

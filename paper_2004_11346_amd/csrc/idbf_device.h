@@ -29,7 +29,9 @@ struct DeviceProgramDir {
 struct DeviceProgram {
     bool valid = false;
     int N = 0, batch = 0, dtype = 0, RC = 16;
-    int RCW = 0;  // > 0: FP64 matrix-core executor with RCW columns per pass
+    int RCW = 0;  // > 0: matrix-core executor with RCW columns per pass
+    bool bf16 = false;  // FP32 plan on the BF16 matrix cores (split-BF16)
+    int bf16_terms = 3;  // 3 or 6 products per value pair
     void *d_X = nullptr, *d_Y = nullptr, *d_scrA = nullptr, *d_scrB = nullptr;
     int64_t *d_x_off = nullptr;    // [4N + 1]
     const double *d_wh = nullptr;  // half-grid weights (owned by the plan)

@@ -382,6 +382,218 @@ __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, co
     }
 }
 
+// FP32 plans on the BF16 matrix cores (split-BF16): every FP32 factor value
+// a and input x is split into BF16 parts by repeated round-to-nearest-even,
+// a_h = bf16(a), a_m = bf16(a - a_h), a_l = bf16(a - a_h - a_m), and a x is
+// accumulated in FP32 by v_mfma_f32_16x16x16_bf16 products of the parts:
+//   TERMS = 3:  a_h x_h + a_h x_m + a_m x_h   (two parts each; the residuals
+//               and the dropped a_m x_m are about 2^-17 of the product)
+//   TERMS = 6:  the above + a_m x_m + a_h x_l + a_l x_h   (three parts each;
+//               dropped terms below 2^-24, i.e. FP32 accuracy)
+// Inputs are split once when staged into LDS as [j / 4][column][j % 4] so
+// that a lane's four k values of the B operand are one 8-byte read; A values
+// are split as they stream from HBM.  Operand layouts of the 16x16x16 shape:
+// A lane l: row l % 16, k = 4 (l / 16) + i; B lane l: column l % 16,
+// k = 4 (l / 16) + i; D lane l: rows 4 (l / 16) + i, column l % 16.
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float v) {
+    unsigned u = __float_as_uint(v);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+template <int NP>
+__device__ __forceinline__ void split_bf16(float v, short *parts) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const unsigned short b = bf16_rne(v);
+        parts[i] = (short)b;
+        v -= bf16_val(b);
+    }
+}
+
+template <int RCW, int TERMS>
+__global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, const SubOp *__restrict__ subs,
+                                                  const int32_t *__restrict__ idx, const float *__restrict__ vals,
+                                                  int op_begin, const float *__restrict__ in, int64_t in_stride,
+                                                  float *__restrict__ out, int64_t out_stride,
+                                                  float *__restrict__ scrA, float *__restrict__ scrB, int rc,
+                                                  int max_out, int max_in, const double *__restrict__ xh,
+                                                  const double *__restrict__ coef, const double *__restrict__ ck,
+                                                  const int32_t *__restrict__ ckexp) {
+    constexpr int NCB = RCW / 16;
+    constexpr int NP = TERMS == 3 ? 2 : 3;  // BF16 parts per value
+    extern __shared__ unsigned char smem_raw[];
+    float *acc = reinterpret_cast<float *>(smem_raw);
+    const int mi16 = (max_in + 15) & ~15;
+    short *xp16 = reinterpret_cast<short *>(acc + (size_t)max_out * RCW);  // NP x [mi16 / 4][RCW][4]
+    const size_t pstride = (size_t)mi16 * RCW;
+    float *gt = reinterpret_cast<float *>(xp16 + NP * pstride);            // [64][kGT]
+    const Op op = ops[op_begin + blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n_out = op.n_out;
+    for (int e = tid; e < n_out * RCW; e += 256) acc[e] = 0.f;
+    for (int s = 0; s < op.nsub; ++s) {
+        const SubOp sb = subs[op.sub0 + s];
+        const bool gen = sb.src == kGen;
+        const float *src;
+        int64_t sstride;
+        if (sb.src == kIn || gen) {
+            src = in;
+            sstride = in_stride;
+        } else {
+            src = sb.src == kScrA ? scrA : scrB;
+            sstride = RCW;
+        }
+        __syncthreads();
+        const int nin = sb.n_in, nmap = sb.n_map;
+        if (nmap > 0) {
+            const int32_t *inr = idx + sb.in_off;
+            const int nin16 = (nin + 15) & ~15;
+            for (int e = tid; e < nin16 * RCW; e += 256) {
+                const int j = e / RCW, c = e - j * RCW;
+                const int64_t row = gen ? (int64_t)sb.in_off + j : (int64_t)inr[j < nin ? j : 0];
+                const float v = (j < nin && c < rc) ? src[row * sstride + c] : 0.f;
+                short pt[NP];
+                split_bf16<NP>(v, pt);
+                const int o = ((j >> 2) * RCW + c) * 4 + (j & 3);
+#pragma unroll
+                for (int k = 0; k < NP; ++k) xp16[k * pstride + o] = pt[k];
+            }
+            const bool gfwd = gen && sb.pad == 0;
+            if (gen && !gfwd) {
+                const int ngen = nin, ncol = nmap;
+                const int i = lane, c0 = 16 * wave;
+                if (i < ngen && c0 < ncol) {
+                    const int64_t si = sb.mat_off + (int64_t)wave * ngen + i;
+                    double p0 = ck[2 * si], p1 = ck[2 * si + 1];
+                    int ex = ckexp[si];
+                    double sc = scale_of(ex);
+                    const double x = xh[sb.dir_off + i];
+                    const double *cf = coef + 2 * (int64_t)sb.n_dir;
+                    const int c1 = min(ncol, c0 + 16);
+                    for (int t = c0; t < c1; ++t) {
+                        if (t > c0) gen_step2(cf + 4 * t - 2, x, p0, p1, ex, sc);
+                        gt[t * kGT + i] = (float)(p1 * sc);
+                    }
+                }
+            }
+            __syncthreads();
+            const int32_t *map = idx + sb.map_off;
+            const int ntile = (nmap + 15) >> 4;
+            const int jl = lane >> 4, cl = lane & 15;
+            const int nks = (nin + 15) >> 4;  // k-steps of 16 inputs
+            for (int t = wave; t < ntile; t += 4) {
+                const int q = t * 16 + cl;
+                float av[16];  // A values: k-step st, slot i -> input 16 st + 4 jl + i
+                if (gfwd) {
+                    double p0 = 0.0, p1 = 0.0, x = 0.0, sc = 0.0;
+                    int ex = 0;
+                    if (q < nmap) {
+                        p0 = ck[2 * (sb.mat_off + q)];
+                        p1 = ck[2 * (sb.mat_off + q) + 1];
+                        ex = ckexp[sb.mat_off + q];
+                        sc = scale_of(ex);
+                        x = xh[sb.dir_off + q];
+                    }
+                    const double *cf = coef + 2 * (int64_t)sb.n_dir;
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) av[v] = 0.f;
+#pragma unroll
+                    for (int st = 0; st < 4; ++st)
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) {
+                            const int j = 16 * st + u;
+                            if (j < nin) {
+                                if (j > 0) gen_step2(cf + 4 * j - 2, x, p0, p1, ex, sc);
+                                if ((u >> 2) == jl) av[4 * st + (u & 3)] = (float)(p1 * sc);
+                            }
+                        }
+                } else if (gen) {
+#pragma unroll
+                    for (int st = 0; st < 4; ++st)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int j = 16 * st + 4 * jl + i;
+                            av[4 * st + i] = (q < nmap && j < nin) ? gt[q * kGT + j] : 0.f;
+                        }
+                } else {
+#pragma unroll
+                    for (int st = 0; st < 4; ++st)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int j = 16 * st + 4 * jl + i;
+                            av[4 * st + i] = (q < nmap && j < nin) ? vals[sb.mat_off + (int64_t)j * nmap + q] : 0.f;
+                        }
+                }
+                f4v D[NCB];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) D[cb] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    if (st >= nks) break;
+                    s4v ap[NP];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        short pt[NP];
+                        split_bf16<NP>(av[4 * st + i], pt);
+#pragma unroll
+                        for (int k = 0; k < NP; ++k) ap[k][i] = pt[k];
+                    }
+                    const int kq = 4 * st + jl;  // group of four inputs
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) {
+                        const int o = (kq * RCW + cb * 16 + cl) * 4;
+                        s4v bp[NP];
+#pragma unroll
+                        for (int k = 0; k < NP; ++k) bp[k] = *reinterpret_cast<const s4v *>(xp16 + k * pstride + o);
+                        // smallest terms first
+                        if (TERMS == 6) {
+                            D[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[2], bp[0], D[cb], 0, 0, 0);
+                            D[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[0], bp[2], D[cb], 0, 0, 0);
+                            D[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[1], bp[1], D[cb], 0, 0, 0);
+                        }
+                        D[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[1], bp[0], D[cb], 0, 0, 0);
+                        D[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[0], bp[1], D[cb], 0, 0, 0);
+                        D[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[0], bp[0], D[cb], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int qq = t * 16 + 4 * jl + i;
+                    if (qq < nmap) {
+                        float *ar = acc + (gen ? sb.map_off + qq : map[qq]) * RCW + cl;
+#pragma unroll
+                        for (int cb = 0; cb < NCB; ++cb) ar[cb * 16] += D[cb][i];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (!gen && sb.n_dir > 0) {
+            const int32_t *dir = idx + sb.dir_off;
+            for (int e = tid; e < sb.n_dir * RCW; e += 256) {
+                const int d = e / RCW, c = e - d * RCW;
+                if (c < rc) acc[dir[2 * d + 1] * RCW + c] += src[(int64_t)dir[2 * d] * sstride + c];
+            }
+        }
+    }
+    __syncthreads();
+    if (op.dst == kOut) {
+        for (int e = tid; e < n_out * RCW; e += 256) {
+            const int i = e / RCW, c = e - i * RCW;
+            if (c < rc) out[(op.dst_row + i) * out_stride + c] = acc[e];
+        }
+    } else {
+        float *dst = op.dst == kScrA ? scrA : scrB;
+        for (int e = tid; e < n_out * RCW; e += 256) dst[op.dst_row * RCW + e] = acc[e];
+    }
+}
+
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 template <typename T>
@@ -404,7 +616,8 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
     T *out = fwd ? Y : X;
     const T *vals = (const T *)pd.d_vals;
     const bool mfma = sizeof(T) == 8 && p.RCW > 0;
-    const int RC = mfma ? p.RCW : p.RC;
+    const bool bf16 = sizeof(T) == 4 && p.bf16;
+    const int RC = (mfma || bf16) ? p.RCW : p.RC;
     for (int c0 = 0; c0 < R; c0 += RC) {
         const int rc = std::min(RC, R - c0);
         for (size_t st = 0; st < pd.stage_task_first.size(); ++st) {
@@ -415,14 +628,44 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
             const int mo = std::max(1, (int)sg.max_out), mi = std::max(4, ((int)sg.max_in + 3) & ~3);
             // LDS tile of transposed generated blocks: 64 x 64 (matrix cores)
             // or 16 x 64 (VALU)
-            const size_t gtile = (sg.gen & 2) ? (size_t)(mfma ? 64 : 16) * kGT : 0;
-            const size_t lds = sizeof(T) * ((size_t)(mo + mi) * RC + gtile);
+            const size_t gtile = (sg.gen & 2) ? (size_t)((mfma || bf16) ? 64 : 16) * kGT : 0;
+            size_t lds = sizeof(T) * ((size_t)(mo + mi) * RC + gtile);
+            if (bf16)  // FP32 accumulators, split BF16 inputs, FP32 tile
+                lds = 4 * (size_t)mo * RC + (p.bf16_terms == 3 ? 2 : 3) * 2 * (size_t)((mi + 15) & ~15) * RC +
+                      4 * gtile;
             if (lds > 160 * 1024) return hipErrorInvalidValue;
             const double *ck = pd.d_ck;
             const int32_t *cke = pd.d_ckexp;
             const bool last = st + 1 == pd.stage_task_first.size();
-            prof::Scope ps(s, mfma ? (last ? "k_ops_mfma[final]" : "k_ops_mfma[levels]")
-                                   : (last ? "k_ops[final]" : "k_ops[levels]"));
+            prof::Scope ps(s, mfma   ? (last ? "k_ops_mfma[final]" : "k_ops_mfma[levels]")
+                              : bf16 ? (last ? "k_ops_bf16[final]" : "k_ops_bf16[levels]")
+                                     : (last ? "k_ops[final]" : "k_ops[levels]"));
+            if (bf16) {
+                const float *vf = (const float *)vals;
+                const float *inf = (const float *)(in + c0);
+                float *outf = (float *)(out + c0);
+#define SHT_BF16_LAUNCH(W, TM)                                                                                    \
+    hipLaunchKernelGGL((k_ops_bf16<W, TM>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs, pd.d_idx, vf, ob,  \
+                       inf, (int64_t)R, outf, (int64_t)R, (float *)scrA, (float *)scrB, rc, mo, mi, p.d_xh, p.d_coef, \
+                       ck, cke)
+                if (p.bf16_terms == 3) {
+                    if (RC == 64)
+                        SHT_BF16_LAUNCH(64, 3);
+                    else if (RC == 32)
+                        SHT_BF16_LAUNCH(32, 3);
+                    else
+                        SHT_BF16_LAUNCH(16, 3);
+                } else {
+                    if (RC == 64)
+                        SHT_BF16_LAUNCH(64, 6);
+                    else if (RC == 32)
+                        SHT_BF16_LAUNCH(32, 6);
+                    else
+                        SHT_BF16_LAUNCH(16, 6);
+                }
+#undef SHT_BF16_LAUNCH
+                continue;
+            }
             if (mfma) {
                 const double *vd = (const double *)vals;
                 const double *ind = (const double *)(in + c0);
@@ -464,7 +707,10 @@ hipError_t set_kernel_attributes() {
                          (const void *)&k_ops<double, 16>,  (const void *)&k_ops<float, 4>,
                          (const void *)&k_ops<float, 8>,    (const void *)&k_ops<float, 16>,
                          (const void *)&k_ops_mfma<32>,     (const void *)&k_ops_mfma<64>,
-                         (const void *)&k_ops_mfma<128>};
+                         (const void *)&k_ops_mfma<128>,    (const void *)&k_ops_bf16<16, 3>,
+                         (const void *)&k_ops_bf16<32, 3>,  (const void *)&k_ops_bf16<64, 3>,
+                         (const void *)&k_ops_bf16<16, 6>,  (const void *)&k_ops_bf16<32, 6>,
+                         (const void *)&k_ops_bf16<64, 6>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;

@@ -85,6 +85,7 @@ int build_program(int N, const LegendreTables &lt, const sht_plan_opts &opts, Ho
     if (rc) return rc;
     pack_programs(hp, out.packed);
     out.N = N;
+    out.f32_mode = opts.f32_mode;
     out.stats = hp.stats;
     std::ostringstream os;
     std::string base = hp.stats_json();
@@ -121,6 +122,11 @@ int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, co
     if (const char *e = std::getenv("SHT_IDBF_RCW")) {
         int v = std::atoi(e);
         d.RCW = (dtype == SHT_F64 && (v == 32 || v == 64 || v == 128)) ? v : 0;
+    }
+    if (dtype == SHT_F32 && (hp.f32_mode == SHT_F32_SPLIT_BF16 || hp.f32_mode == SHT_F32_SPLIT_BF16_6)) {
+        d.bf16 = true;
+        d.bf16_terms = hp.f32_mode == SHT_F32_SPLIT_BF16 ? 3 : 6;
+        d.RCW = R <= 16 ? 16 : R <= 32 ? 32 : 64;
     }
     if (d.RCW == 128 && (!hp.packed.fwd.ckexp.empty() || !hp.packed.adj.ckexp.empty()))
         d.RCW = 64;  // 128 columns leave no LDS for the tile of a generated block

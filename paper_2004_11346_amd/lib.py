@@ -20,7 +20,7 @@ SHT_OK = 0
 SHT_F64, SHT_F32 = 0, 1
 SHT_DENSE, SHT_IDBF = 0, 1
 SHT_FWD, SHT_INV, SHT_ADJ = 0, 1, 2
-SHT_F32_VALU, SHT_F32_SPLIT_BF16 = 0, 1
+SHT_F32_VALU, SHT_F32_SPLIT_BF16, SHT_F32_SPLIT_BF16_6 = 0, 1, 2
 SHT_SAMPLE_MOCK_CHEB, SHT_SAMPLE_RANDOM = 0, 1
 
 EXPORTED = [

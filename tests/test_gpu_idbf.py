@@ -141,3 +141,35 @@ def test_idbf_matrix_core_path(N, batch, rcw, monkeypatch):
     for b in sorted({0, batch // 2, batch - 1}):
         assert rel_l2(f[b], oracle.sht_forward(N, beta[b])) <= 1e-11
         assert rel_l2(bi[b], oracle.sht_inverse(N, grid[b])) <= 1e-11
+
+
+@pytest.mark.parametrize("terms", [3, 6])
+@pytest.mark.parametrize("N,batch,kw", [(64, 1, dict(n0=32, leaf=8)), (64, 8, dict(n0=32, leaf=8)),
+                                        (130, 3, dict()), (48, 12, dict(n0=24, leaf=4))])
+def test_idbf_split_bf16(N, batch, kw, terms):
+    """FP32 plans on the BF16 matrix cores with FP32 accumulation.  Three
+    products of two BF16 parts (hi, lo) leave residuals of about 2^-17 of each
+    product, so the relative l2 error is a few 1e-6 (bar 6e-6); six products
+    of three parts drop only terms below 2^-24 and meet the FP32 bar 2e-6."""
+    from paper_2004_11346_amd import lib as L
+    mode = L.SHT_F32_SPLIT_BF16 if terms == 3 else L.SHT_F32_SPLIT_BF16_6
+    tol = 6e-6 if terms == 3 else 2e-6
+    print(f"idbf split-bf16 x{terms} N={N} batch={batch}", flush=True)
+    p = _plan(N, batch, dtype=torch.complex64, f32_mode=mode, **kw)
+    beta = inputs.make_beta(N, batch, 1).astype(np.complex64)
+    f = p.forward(_dev(beta, torch.complex64)).cpu().numpy()
+    grid = inputs.make_grid(N, batch, 2).astype(np.complex64)
+    bi = p.inverse(_dev(grid, torch.complex64)).cpu().numpy()
+    ef = max(rel_l2(f[b], oracle.sht_forward(N, beta[b].astype(np.complex128))) for b in range(batch))
+    ei = max(rel_l2(bi[b], oracle.sht_inverse(N, grid[b].astype(np.complex128))) for b in range(batch))
+    print(f"split-bf16 x{terms} rel l2: forward {ef:.2e} inverse {ei:.2e}", flush=True)
+    assert ef <= tol and ei <= tol, (ef, ei)
+
+
+def test_split_bf16_needs_fast_fp32_plan():
+    from paper_2004_11346_amd import lib as L
+    from paper_2004_11346_amd.sht import Plan
+    with pytest.raises(L.ShtError):
+        Plan(16, 1, dtype=torch.complex128, method="idbf", f32_mode=L.SHT_F32_SPLIT_BF16)
+    with pytest.raises(L.ShtError):
+        Plan(16, 1, dtype=torch.complex64, method="dense", f32_mode=L.SHT_F32_SPLIT_BF16)
