@@ -110,6 +110,10 @@ typedef struct sht_plan_opts {
                           stored; the kernels regenerate their entries with the
                           three-term recurrence from per-row checkpoints taken
                           every 16 columns.  0: store their values. */
+    int m_lo, m_hi;    /* orders |m| in [m_lo, m_hi] covered by the fast form's
+                          factors (default 0 and -1 = all).  A plan restricted
+                          to a range serves sht_alt_apply inside it (one GPU's
+                          share of the orders); the full transforms need all. */
 } sht_plan_opts;
 
 void sht_plan_opts_default(sht_plan_opts *opts);

@@ -31,6 +31,7 @@ using namespace sht;
 
 struct sht_plan {
     int N = 0, M = 0, batch = 0, dtype = 0, method = 0, device = 0;
+    bool dft_ok = true;
     sht_plan_opts opts{};
     std::vector<double> x, w;  // full rule, ascending
     // device tables
@@ -134,6 +135,8 @@ void sht_plan_opts_default(sht_plan_opts *o) {
     o->f32_mode = SHT_F32_VALU;
     o->min_idbf = 0;
     o->dense_gen = 1;
+    o->m_lo = 0;
+    o->m_hi = -1;
 }
 
 const char *sht_strerror(int code) {
@@ -185,10 +188,17 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
         set_error_detail("split-BF16 products apply to FP32 plans of the fast form");
         return SHT_ERR_UNSUPPORTED;
     }
-    if (!dev::dft_supported(p->M, dtype)) {
-        set_error_detail("phi DFT row does not fit in LDS for this N and dtype");
+    if (p->opts.m_hi < 0) p->opts.m_hi = 2 * N - 1;
+    if (p->opts.m_lo < 0 || p->opts.m_lo > p->opts.m_hi || p->opts.m_hi > 2 * N - 1) {
+        set_error_detail("order range of the plan out of bounds");
+        return SHT_ERR_INVALID_ARG;
+    }
+    if (method == SHT_DENSE && (p->opts.m_lo != 0 || p->opts.m_hi != 2 * N - 1)) {
+        set_error_detail("order ranges apply to the fast form (the plain form stores no per-order data)");
         return SHT_ERR_UNSUPPORTED;
     }
+    // the phi DFT holds a row in LDS; without it the plan serves sht_alt_apply only
+    p->dft_ok = dev::dft_supported(p->M, dtype);
 
     LegendreTables lt;
     try {
@@ -317,6 +327,18 @@ int sht_plan_stats(const sht_plan_t *p, char *json, size_t cap) {
     return (int)s.size() + 1;
 }
 
+static int full_transform_ok(const sht_plan_t *p) {
+    if (!p->dft_ok) {
+        set_error_detail("the phi DFT row does not fit in LDS for this N and dtype; use sht_alt_apply");
+        return SHT_ERR_UNSUPPORTED;
+    }
+    if (p->opts.m_lo != 0 || p->opts.m_hi != 2 * p->N - 1) {
+        set_error_detail("the plan covers a range of orders only; use sht_alt_apply");
+        return SHT_ERR_UNSUPPORTED;
+    }
+    return SHT_OK;
+}
+
 static int copy_json(const std::string &s, char *json, size_t cap) {
     if (json && cap) {
         size_t n = std::min(cap - 1, s.size());
@@ -362,6 +384,10 @@ int sht_alt_apply(const sht_plan_t *p, int m_lo, int m_hi, int dir, const void *
         set_error_detail("order range or direction out of bounds");
         return SHT_ERR_INVALID_ARG;
     }
+    if (m_lo < p->opts.m_lo || m_hi > p->opts.m_hi) {
+        set_error_detail("orders outside the range the plan was built for");
+        return SHT_ERR_INVALID_ARG;
+    }
     int rc;
     if ((rc = check_ptr(in, elt_size(p->dtype)))) return rc;
     if ((rc = check_ptr(out, elt_size(p->dtype)))) return rc;
@@ -377,6 +403,7 @@ int sht_forward(const sht_plan_t *p, const void *beta, void *f, void *stream) {
         set_error_detail("f may not alias beta");
         return SHT_ERR_INVALID_ARG;
     }
+    if ((rc = full_transform_ok(p))) return rc;
     hipStream_t s = (hipStream_t)stream;
     if ((rc = run_alt(p, 0, 2 * p->N - 1, SHT_FWD, beta, f, s))) return rc;
     prof::Install inst(p->rec());
@@ -388,6 +415,7 @@ int sht_forward(const sht_plan_t *p, const void *beta, void *f, void *stream) {
 static int transposed(const sht_plan_t *p, const void *f, void *beta, void *stream, bool inverse) {
     if (!p) return SHT_ERR_INVALID_ARG;
     int rc;
+    if ((rc = full_transform_ok(p))) return rc;
     if ((rc = check_ptr(beta, elt_size(p->dtype)))) return rc;
     if ((rc = check_ptr(f, elt_size(p->dtype)))) return rc;
     hipStream_t s = (hipStream_t)stream;

@@ -723,7 +723,8 @@ int build_all(int N, const sht_plan_opts &opts, HostPlanData &out) {
     out.tasks.assign(ntask, Task());
     int nth = opts.threads > 0 ? opts.threads : (int)std::thread::hardware_concurrency();
     nth = std::max(1, std::min(nth, 64));
-    std::atomic<int> next(0);
+    const int m_lo = std::max(0, opts.m_lo), m_hi = opts.m_hi < 0 ? 2 * N - 1 : std::min(opts.m_hi, 2 * N - 1);
+    std::atomic<int> next(2 * m_lo);
     std::vector<BuildStats> st(nth);
     std::vector<std::thread> th;
     for (int w = 0; w < nth; ++w)
@@ -731,7 +732,7 @@ int build_all(int N, const sht_plan_opts &opts, HostPlanData &out) {
             std::vector<double> mat;
             for (;;) {
                 int i = next.fetch_add(1);
-                if (i >= ntask) break;
+                if (i >= ntask || i > 2 * m_hi + 1) break;
                 // heaviest (small |m|) first
                 build_task(N, out.lt, opts, i / 2, i % 2, out.tasks[i], mat, st[w]);
             }

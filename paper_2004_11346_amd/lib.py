@@ -54,6 +54,8 @@ class PlanOpts(ctypes.Structure):
         ("f32_mode", ctypes.c_int),
         ("min_idbf", ctypes.c_int),
         ("dense_gen", ctypes.c_int),
+        ("m_lo", ctypes.c_int),
+        ("m_hi", ctypes.c_int),
     ]
 
 
