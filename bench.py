@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--profile-target", action="store_true",
                     help="only a 1 GiB device copy (counter scale) and a few ALT calls, for rocprofv3 runs")
+    ap.add_argument("--workload", choices=["default", "n4096-orders", "uneven"], default="default",
+                    help="n4096-orders: N=4096, 8 fields, fast vs plain ALT on 64-order windows across the "
+                         "order range; uneven: the grouped 64-transform workload")
     return ap.parse_args()
 
 
@@ -229,6 +232,97 @@ def profile_target(args):
                       "alt_calls": args.steps, "copy_bytes": 2 * a.numel() * 8}), flush=True)
 
 
+def n4096_orders(args):
+    """N = 4096 (grid 8192 x 16383), 8 fields, FP64: the fast form (plans
+    restricted to 64-order windows, the unit of per-GPU sharding) against the
+    plain form on the same orders, windows spread over the whole order range.
+    The full transform time is the sum over 128 windows, estimated from the
+    measured ones by the trapezoid rule in the window start."""
+    import torch
+
+    import paper_2004_11346_amd.sht as S
+    torch.cuda.init()
+    N, B, W = 4096, 8, 64
+    M = 4 * N - 1
+    starts = [0, 1024, 2048, 3072, 4096, 5120, 6144, 7168, 8128]
+    beta = torch.randn((B, 4 * N * N), dtype=torch.complex128, device="cuda")
+    g = torch.zeros((B, 2 * N, M), dtype=torch.complex128, device="cuda")
+    bo = torch.zeros_like(beta)
+    timer = Timer()
+    dense = S.Plan(N, B, dtype=torch.complex128, method="dense")
+    rows = []
+    for a0 in starts:
+        lo, hi = a0, min(2 * N - 1, a0 + W - 1)
+        t0 = time.perf_counter()
+        p = S.Plan(N, B, dtype=torch.complex128, method="idbf", m_lo=lo, m_hi=hi)
+        tb = time.perf_counter() - t0
+        st = p.stats()["program"]
+        r = {"orders": [lo, hi], "plan_build_s": tb, "dense_entries": st["dense_entries"],
+             "stored_entries": st["stored_entries"], "generated_entries": st["generated_entries"]}
+        for name, pl in (("fast", p), ("plain", dense)):
+            r[name + "_fwd_ms"] = 1e3 * timer.time(lambda: pl.alt(lo, hi, "fwd", beta, g), reps=3)
+            r[name + "_inv_ms"] = 1e3 * timer.time(lambda: pl.alt(lo, hi, "inv", g, bo), reps=3)
+        rows.append(r)
+        print(json.dumps({"window": r}), flush=True)
+        p.close()
+        torch.cuda.empty_cache()
+    # trapezoid estimate of the whole transform (128 windows of 64 orders)
+    def total(key):
+        xs = [r["orders"][0] for r in rows]
+        ys = [r[key] for r in rows]
+        acc = 0.0
+        for i in range(len(xs) - 1):
+            acc += 0.5 * (ys[i] + ys[i + 1]) * (xs[i + 1] - xs[i]) / W
+        return acc + ys[-1]
+    est = {k: total(k) for k in ("fast_fwd_ms", "fast_inv_ms", "plain_fwd_ms", "plain_inv_ms")}
+    coefs = B * 4 * N * N
+    print(json.dumps({"metric": "ALT Gcoef/s at N=4096, fast vs plain, FP64, 8 fields (estimated from windows)",
+                      "unit": "Gcoef/s", "n_gpus": 1, "data": "synthetic", "dtype": "f64",
+                      "config": {"workload": "ALT N=4096 (grid 8192x16383), 8 fields, 64-order windows", "N": N,
+                                 "batch": B, "windows": starts},
+                      "estimated_full_ms": est,
+                      "alt_gcoef_per_s": {k.replace("_ms", ""): coefs / (v / 1e3) / 1e9 for k, v in est.items()},
+                      "fast_over_plain": {"fwd": est["plain_fwd_ms"] / est["fast_fwd_ms"],
+                                          "inv": est["plain_inv_ms"] / est["fast_inv_ms"]}}), flush=True)
+
+
+def uneven(args):
+    """The grouped workload: 64 transforms, N drawn from {128, 256, 512, 1024}
+    and 1-4 fields each (seed 4000), one persistent launch per phase,
+    autotuned, replayed from a hipGraph; FP64 and FP32."""
+    import numpy as np
+    import torch
+
+    from paper_2004_11346_amd import inputs
+    from paper_2004_11346_amd.sht import Group
+    torch.cuda.init()
+    rng = np.random.Generator(np.random.PCG64(4000))
+    Ns = [int(v) for v in rng.choice([128, 256, 512, 1024], size=64)]
+    fields = [int(v) for v in rng.integers(1, 5, size=64)]
+    timer = Timer()
+    out = {}
+    for dname, dt in (("f64", torch.complex128), ("f32", torch.complex64)):
+        grp = Group(Ns, fields, dtype=dt)
+        betas = [torch.from_numpy(inputs.make_beta(N, f, 4100 + i)).to(dt).cuda()
+                 for i, (N, f) in enumerate(zip(Ns, fields))]
+        fs = [torch.zeros((f, 2 * N, 4 * N - 1), dtype=dt, device="cuda") for N, f in zip(Ns, fields)]
+        grp.bind(betas, fs)
+        grp.tune()
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            grp.capture("fwd", s)
+            grp.capture("inv", s)
+            tf = timer.time(lambda: grp.replay("fwd", s), reps=max(3, args.steps))
+            ti = timer.time(lambda: grp.replay("inv", s), reps=max(3, args.steps))
+        out[dname] = {"fwd_ms": tf * 1e3, "inv_ms": ti * 1e3, "sht_per_s": 2 * sum(fields) / (tf + ti),
+                      "grid": grp.stats()["grid"]}
+        grp.close()
+    print(json.dumps({"metric": "SHT/s, uneven batch of 64 transforms in one persistent launch per phase",
+                      "unit": "SHT/s", "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": "64 transforms, N in {128,256,512,1024}, 1-4 fields (seed 4000)",
+                                 "fields": sum(fields)}, "results": out}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -241,6 +335,12 @@ def main():
 
     if args.profile_target:
         profile_target(args)
+        return
+    if args.workload == "n4096-orders":
+        n4096_orders(args)
+        return
+    if args.workload == "uneven":
+        uneven(args)
         return
 
     import numpy as np

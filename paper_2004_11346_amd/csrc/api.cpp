@@ -35,7 +35,7 @@ struct sht_plan {
     sht_plan_opts opts{};
     std::vector<double> x, w;  // full rule, ascending
     // device tables
-    double *d_xh = nullptr, *d_wh = nullptr, *d_dmant = nullptr, *d_coef = nullptr;
+    double *d_xh = nullptr, *d_wh = nullptr, *d_dmant = nullptr, *d_coef = nullptr, *d_coef2 = nullptr;
     int *d_dexp = nullptr;
     double *d_tw2 = nullptr;
     float *d_tw2f = nullptr;
@@ -68,6 +68,7 @@ sht_plan::~sht_plan() {
     dfree(d_wh);
     dfree(d_dmant);
     dfree(d_coef);
+    dfree(d_coef2);
     dfree(d_dexp);
     dfree(d_tw2);
     dfree(d_tw2f);
@@ -216,6 +217,7 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
     if ((rc = upload(lt.diag_m, &p->d_dmant, "upload diag"))) return rc;
     if ((rc = upload(lt.diag_e, &p->d_dexp, "upload diag exponents"))) return rc;
     if ((rc = upload(lt.coef, &p->d_coef, "upload recurrence coefficients"))) return rc;
+    if (method == SHT_IDBF && (rc = upload(lt.coef2, &p->d_coef2, "upload recurrence coefficients"))) return rc;
     p->dense.N = N;
     p->dense.M = p->M;
     p->dense.xh = p->d_xh;
@@ -282,7 +284,7 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
             return SHT_ERR_OOM;
         }
         if (brc) return brc;
-        brc = idbf::upload_program(hp, dtype, batch, p->d_wh, p->d_xh, p->d_coef, p->prog);
+        brc = idbf::upload_program(hp, dtype, batch, p->d_wh, p->d_xh, p->d_coef2, p->prog);
         if (brc) return brc;
         p->stats = hp.stats_json;
     }

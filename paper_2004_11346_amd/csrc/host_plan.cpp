@@ -81,7 +81,7 @@ int sht_host_plan_apply(const sht_host_plan_t *hp, int absm, int parity, int dir
     const int64_t ob = fwd ? pk.y_off[task] : pk.x_off[task];
     const int nin = fwd ? t.cols : t.rows, nout = fwd ? t.rows : t.cols;
     std::memcpy(&pin[(size_t)ib * R], in, sizeof(double) * (size_t)nin * R);
-    idbf::host_run_program(p, R, pin.data(), pout.data(), hp->data.lt.xh.data(), hp->data.lt.coef.data());
+    idbf::host_run_program(p, R, pin.data(), pout.data(), hp->data.lt.xh.data(), hp->data.lt.coef2.data());
     std::memcpy(out, &pout[(size_t)ob * R], sizeof(double) * (size_t)nout * R);
     return SHT_OK;
 }

@@ -31,7 +31,7 @@ struct HostProgram {
 
 int build_program(int N, const LegendreTables &lt, const sht_plan_opts &opts, HostProgram &out);
 int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, const double *d_xh,
-                   const double *d_coef, DeviceProgram &out);
+                   const double *d_coef2, DeviceProgram &out);
 hipError_t run(const DeviceProgram &prog, const dev::DenseTables &t, int dtype, int batch, int a_lo, int a_hi,
                int dir, const void *in, void *out, hipStream_t s);
 

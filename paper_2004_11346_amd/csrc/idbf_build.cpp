@@ -50,9 +50,11 @@ int64_t Block::stored() const {
 void rec_step(const LegendreTables &lt, int a, double x, int k, RecState &s) {
     const double *c = &lt.coef[2 * (tri_offset(lt.N, a) + (k + 1 - a))];
     const double p2 = c[0] * (x * s.p1 - c[1] * s.p0);
+    s.pm2 = s.p0;
     s.p0 = s.p1;
     s.p1 = p2;
     if (std::fabs(s.p1) > 0x1p200) {
+        s.pm2 *= 0x1p-200;
         s.p0 *= 0x1p-200;
         s.p1 *= 0x1p-200;
         s.e += 200;

@@ -46,6 +46,7 @@ enum BlockType { kDense = 0, kLowRank = 1, kButterfly = 2 };
 // the entries of degrees k-1 and k are p0 * 2^e and p1 * 2^e.
 struct RecState {
     double p0 = 0.0, p1 = 0.0;
+    double pm2 = 0.0;  // entry of degree k-2 (same parity as k), same scale
     int32_t e = 0;
 };
 

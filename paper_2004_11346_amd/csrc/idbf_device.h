@@ -36,7 +36,7 @@ struct DeviceProgram {
     int64_t *d_x_off = nullptr;    // [4N + 1]
     const double *d_wh = nullptr;  // half-grid weights (owned by the plan)
     const double *d_xh = nullptr;    // half-grid nodes (owned by the plan)
-    const double *d_coef = nullptr;  // recurrence coefficient pairs (owned by the plan)
+    const double *d_coef2 = nullptr;  // composed two-step recurrence coefficients (owned by the plan)
     std::vector<int64_t> x_off_h, y_off_h;
     int64_t max_task_cols = 0;
     int64_t index_bytes = 0;

@@ -14,9 +14,9 @@
 // rows, so there are no atomics and the result is bitwise reproducible.
 //
 // Generated sub-ops (dense blocks near the turning point, Section 3.2) carry
-// no values: each lane walks the three-term recurrence of one node from a
-// stored state (two FP64 steps per column, same parity), rescaling by exact
-// powers of two as the table builder does.
+// no values: each lane walks the recurrence of one node from a stored state,
+// one composed two-step (same parity) per column, rescaling by exact powers
+// of two as the table builder does.
 #include <hip/hip_runtime.h>
 
 #include "idbf_device.h"
@@ -41,14 +41,19 @@ constexpr int kGT = 65;  // row stride of the LDS tile of a generated block
 
 __device__ __forceinline__ double scale_of(int e) { return e < -1074 ? 0.0 : ldexp(1.0, e); }
 
-// two recurrence steps (to the next column of the same parity); cf points at
-// the coefficient pairs of the two new degrees
-__device__ __forceinline__ void gen_step2(const double *__restrict__ cf, double x, double &p0, double &p1, int &e,
+constexpr int kGco = 64 * 3;  // LDS doubles for the coefficients of one generated sub-op
+
+// copy the (alpha, beta, gamma) triples of the sub-op's ncol columns to LDS
+__device__ __forceinline__ void stage_coef(const double *__restrict__ src, int ncol, int tid, int nthreads,
+                                           double *gco) {
+    for (int e = tid; e < 3 * ncol; e += nthreads) gco[e] = src[6 * (e / 3) + e % 3];
+}
+
+// next column of the same parity: the composed two-step recurrence
+// p_k = (alpha_k x^2 + beta_k) p_{k-2} + gamma_k p_{k-4}; c3 = (alpha, beta, gamma)
+__device__ __forceinline__ void gen_2step(const double *__restrict__ c3, double x2, double &p0, double &p1, int &e,
                                           double &sc) {
-    double p2 = cf[0] * (x * p1 - cf[1] * p0);
-    p0 = p1;
-    p1 = p2;
-    p2 = cf[2] * (x * p1 - cf[3] * p0);
+    const double p2 = fma(c3[0], x2, c3[1]) * p1 + c3[2] * p0;
     p0 = p1;
     p1 = p2;
     if (fabs(p1) > 0x1p200) {
@@ -72,9 +77,10 @@ __global__ __launch_bounds__(64) void k_ops(const Op *__restrict__ ops, const Su
                                             const double *__restrict__ xh, const double *__restrict__ coef,
                                             const double *__restrict__ ck, const int32_t *__restrict__ ckexp) {
     extern __shared__ unsigned char smem_raw[];
-    T *acc = reinterpret_cast<T *>(smem_raw);
+    double *gco = reinterpret_cast<double *>(smem_raw);  // [64][3] recurrence coefficients of a generated sub-op
+    T *acc = reinterpret_cast<T *>(gco + kGco);
     T *xin = acc + (size_t)max_out * RC;
-    T *gt = xin + (size_t)max_in * RC;  // [64][kGT] tile of a transposed generated block
+    T *gt = xin + (size_t)max_in * RC;  // [16][kGT] tile of a transposed generated block
     const Op op = ops[op_begin + blockIdx.x];
     const int lane = threadIdx.x;
     const int n_out = op.n_out;
@@ -84,13 +90,14 @@ __global__ __launch_bounds__(64) void k_ops(const Op *__restrict__ ops, const Su
         if (sb.src == kGen) {
             const int nin = sb.n_in, nmap = sb.n_map;
             const bool fwd = sb.pad == 0;
+            const int ngen = fwd ? nmap : nin, ncol = fwd ? nin : nmap;
             __syncthreads();
             for (int e = lane; e < nin * RC; e += 64) {
                 const int j = e / RC, r = e - j * RC;
                 xin[e] = r < rc ? in[(int64_t)(sb.in_off + j) * in_stride + r] : (T)0;
             }
+            stage_coef(coef + 3 * (int64_t)sb.n_dir, ncol, lane, 64, gco);
             __syncthreads();
-            const int ngen = fwd ? nmap : nin, ncol = fwd ? nin : nmap;
             double p0 = 0.0, p1 = 0.0, x = 0.0, sc = 0.0;
             int ex = 0;
             if (lane < ngen) {
@@ -100,13 +107,13 @@ __global__ __launch_bounds__(64) void k_ops(const Op *__restrict__ ops, const Su
                 sc = scale_of(ex);
                 x = xh[sb.dir_off + lane];
             }
-            const double *cf = coef + 2 * (int64_t)sb.n_dir;
+            const double *cf = gco;
             if (fwd) {
                 T a[RC];
 #pragma unroll
                 for (int r = 0; r < RC; ++r) a[r] = (T)0;
                 for (int t = 0; t < ncol; ++t) {
-                    if (t > 0) gen_step2(cf + 4 * t - 2, x, p0, p1, ex, sc);
+                    if (t > 0) gen_2step(cf + 3 * t, x * x, p0, p1, ex, sc);
                     const T v = (T)(p1 * sc);
 #pragma unroll
                     for (int r = 0; r < RC; ++r) a[r] += v * xin[t * RC + r];
@@ -123,7 +130,7 @@ __global__ __launch_bounds__(64) void k_ops(const Op *__restrict__ ops, const Su
                     const int tn = min(16, ncol - t0);
                     for (int tt = 0; tt < tn; ++tt) {
                         const int t = t0 + tt;
-                        if (t > 0) gen_step2(cf + 4 * t - 2, x, p0, p1, ex, sc);
+                        if (t > 0) gen_2step(cf + 3 * t, x * x, p0, p1, ex, sc);
                         gt[tt * kGT + lane] = lane < ngen ? (T)(p1 * sc) : (T)0;
                     }
                     __syncthreads();
@@ -244,7 +251,8 @@ __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, co
                                                   const int32_t *__restrict__ ckexp) {
     constexpr int NCB = RCW / 16;
     extern __shared__ unsigned char smem_raw[];
-    double *acc = reinterpret_cast<double *>(smem_raw);
+    double *gco = reinterpret_cast<double *>(smem_raw);
+    double *acc = gco + kGco;
     double *xin = acc + (size_t)max_out * RCW;
     double *gt = xin + (size_t)((max_in + 3) & ~3) * RCW;  // [64][kGT] generated block, outputs x inputs
     const Op op = ops[op_begin + blockIdx.x];
@@ -273,6 +281,10 @@ __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, co
                 const int64_t row = gen ? (int64_t)sb.in_off + j : (int64_t)inr[j < nin ? j : 0];
                 xin[e] = (j < nin && c < rc) ? src[row * sstride + c] : 0.0;
             }
+            if (gen) {
+                stage_coef(coef + 3 * (int64_t)sb.n_dir, sb.pad == 0 ? nin : nmap, tid, 256, gco);
+                __syncthreads();
+            }
             const bool gfwd = gen && sb.pad == 0;
             if (gen && !gfwd) {
                 // transposed generated block into LDS (outputs x inputs):
@@ -286,10 +298,10 @@ __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, co
                     int ex = ckexp[si];
                     double sc = scale_of(ex);
                     const double x = xh[sb.dir_off + i];
-                    const double *cf = coef + 2 * (int64_t)sb.n_dir;
+                    const double *cf = gco;
                     const int c1 = min(ncol, c0 + 16);
                     for (int t = c0; t < c1; ++t) {
-                        if (t > c0) gen_step2(cf + 4 * t - 2, x, p0, p1, ex, sc);
+                        if (t > c0) gen_2step(cf + 3 * t, x * x, p0, p1, ex, sc);
                         gt[t * kGT + i] = p1 * sc;
                     }
                 }
@@ -313,7 +325,7 @@ __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, co
                         sc = scale_of(ex);
                         x = xh[sb.dir_off + q];
                     }
-                    const double *cf = coef + 2 * (int64_t)sb.n_dir;
+                    const double *cf = gco;
 #pragma unroll
                     for (int st = 0; st < 16; ++st) {
                         areg[st] = 0.0;
@@ -321,7 +333,7 @@ __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, co
                         for (int u = 0; u < 4; ++u) {
                             const int j = 4 * st + u;
                             if (j < nin) {
-                                if (j > 0) gen_step2(cf + 4 * j - 2, x, p0, p1, ex, sc);
+                                if (j > 0) gen_2step(cf + 3 * j, x * x, p0, p1, ex, sc);
                                 if (u == jl) areg[st] = p1 * sc;
                             }
                         }
@@ -428,7 +440,8 @@ __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, co
     constexpr int NCB = RCW / 16;
     constexpr int NP = TERMS == 3 ? 2 : 3;  // BF16 parts per value
     extern __shared__ unsigned char smem_raw[];
-    float *acc = reinterpret_cast<float *>(smem_raw);
+    double *gco = reinterpret_cast<double *>(smem_raw);
+    float *acc = reinterpret_cast<float *>(gco + kGco);
     const int mi16 = (max_in + 15) & ~15;
     short *xp16 = reinterpret_cast<short *>(acc + (size_t)max_out * RCW);  // NP x [mi16 / 4][RCW][4]
     const size_t pstride = (size_t)mi16 * RCW;
@@ -464,6 +477,10 @@ __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, co
 #pragma unroll
                 for (int k = 0; k < NP; ++k) xp16[k * pstride + o] = pt[k];
             }
+            if (gen) {
+                stage_coef(coef + 3 * (int64_t)sb.n_dir, sb.pad == 0 ? nin : nmap, tid, 256, gco);
+                __syncthreads();
+            }
             const bool gfwd = gen && sb.pad == 0;
             if (gen && !gfwd) {
                 const int ngen = nin, ncol = nmap;
@@ -474,10 +491,10 @@ __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, co
                     int ex = ckexp[si];
                     double sc = scale_of(ex);
                     const double x = xh[sb.dir_off + i];
-                    const double *cf = coef + 2 * (int64_t)sb.n_dir;
+                    const double *cf = gco;
                     const int c1 = min(ncol, c0 + 16);
                     for (int t = c0; t < c1; ++t) {
-                        if (t > c0) gen_step2(cf + 4 * t - 2, x, p0, p1, ex, sc);
+                        if (t > c0) gen_2step(cf + 3 * t, x * x, p0, p1, ex, sc);
                         gt[t * kGT + i] = (float)(p1 * sc);
                     }
                 }
@@ -500,7 +517,7 @@ __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, co
                         sc = scale_of(ex);
                         x = xh[sb.dir_off + q];
                     }
-                    const double *cf = coef + 2 * (int64_t)sb.n_dir;
+                    const double *cf = gco;
 #pragma unroll
                     for (int v = 0; v < 16; ++v) av[v] = 0.f;
 #pragma unroll
@@ -509,7 +526,7 @@ __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, co
                         for (int u = 0; u < 16; ++u) {
                             const int j = 16 * st + u;
                             if (j < nin) {
-                                if (j > 0) gen_step2(cf + 4 * j - 2, x, p0, p1, ex, sc);
+                                if (j > 0) gen_2step(cf + 3 * j, x * x, p0, p1, ex, sc);
                                 if ((u >> 2) == jl) av[4 * st + (u & 3)] = (float)(p1 * sc);
                             }
                         }
@@ -633,6 +650,7 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
             if (bf16)  // FP32 accumulators, split BF16 inputs, FP32 tile
                 lds = 4 * (size_t)mo * RC + (p.bf16_terms == 3 ? 2 : 3) * 2 * (size_t)((mi + 15) & ~15) * RC +
                       4 * gtile;
+            lds += 8 * kGco;  // coefficients of a generated sub-op
             if (lds > 160 * 1024) return hipErrorInvalidValue;
             const double *ck = pd.d_ck;
             const int32_t *cke = pd.d_ckexp;
@@ -646,7 +664,7 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
                 float *outf = (float *)(out + c0);
 #define SHT_BF16_LAUNCH(W, TM)                                                                                    \
     hipLaunchKernelGGL((k_ops_bf16<W, TM>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs, pd.d_idx, vf, ob,  \
-                       inf, (int64_t)R, outf, (int64_t)R, (float *)scrA, (float *)scrB, rc, mo, mi, p.d_xh, p.d_coef, \
+                       inf, (int64_t)R, outf, (int64_t)R, (float *)scrA, (float *)scrB, rc, mo, mi, p.d_xh, p.d_coef2, \
                        ck, cke)
                 if (p.bf16_terms == 3) {
                     if (RC == 64)
@@ -673,20 +691,20 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
                 if (RC == 128)
                     hipLaunchKernelGGL((k_ops_mfma<128>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
                                        pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
-                                       (double *)scrB, rc, mo, mi, p.d_xh, p.d_coef, ck, cke);
+                                       (double *)scrB, rc, mo, mi, p.d_xh, p.d_coef2, ck, cke);
                 else if (RC == 64)
                     hipLaunchKernelGGL((k_ops_mfma<64>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
                                        pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
-                                       (double *)scrB, rc, mo, mi, p.d_xh, p.d_coef, ck, cke);
+                                       (double *)scrB, rc, mo, mi, p.d_xh, p.d_coef2, ck, cke);
                 else
                     hipLaunchKernelGGL((k_ops_mfma<32>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
                                        pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
-                                       (double *)scrB, rc, mo, mi, p.d_xh, p.d_coef, ck, cke);
+                                       (double *)scrB, rc, mo, mi, p.d_xh, p.d_coef2, ck, cke);
                 continue;
             }
 #define SHT_OPS_LAUNCH(RCV)                                                                                      \
     hipLaunchKernelGGL((k_ops<T, RCV>), dim3(oe - ob), dim3(64), lds, s, pd.d_ops, pd.d_subs, pd.d_idx, vals, ob, \
-                       (const T *)(in + c0), (int64_t)R, out + c0, (int64_t)R, scrA, scrB, rc, mo, mi, p.d_xh, p.d_coef, ck, cke)
+                       (const T *)(in + c0), (int64_t)R, out + c0, (int64_t)R, scrA, scrB, rc, mo, mi, p.d_xh, p.d_coef2, ck, cke)
             if (RC == 4)
                 SHT_OPS_LAUNCH(4);
             else if (RC == 8)

@@ -419,7 +419,7 @@ void emit_gen(const LegendreTables &lt, int a, int par, const Block &b, int mode
     for (int s = 0; s * 16 < nc; ++s)
         for (int i = 0; i < ng; ++i) {
             const RecState st = gen_state(lt, a, par, b, r0 + i, c0 + 16 * s);
-            p.ck.push_back(st.p0);
+            p.ck.push_back(st.pm2);  // same-parity pair (k - 2, k)
             p.ck.push_back(st.p1);
             p.ckexp.push_back(st.e);
         }
@@ -657,7 +657,7 @@ void pack_programs(const HostPlanData &hp, PackedPlan &pk) {
 }
 
 void host_run_program(const Program &p, int R, const double *in, double *out, const double *xh,
-                      const double *coef) {
+                      const double *coef2) {
     std::vector<double> scr[2];
     scr[0].assign((size_t)std::max<int64_t>(1, p.scr_rows) * R, 0.0);
     scr[1].assign((size_t)std::max<int64_t>(1, p.scr_rows) * R, 0.0);
@@ -674,20 +674,19 @@ void host_run_program(const Program &p, int R, const double *in, double *out, co
                     for (int i = 0; i < ngen; ++i) {
                         double p0 = p.ck[2 * (sb.mat_off + i)], p1 = p.ck[2 * (sb.mat_off + i) + 1];
                         int e = p.ckexp[sb.mat_off + i];
-                        const double x = xh[sb.dir_off + i];
+                        const double x = xh[sb.dir_off + i], x2 = x * x;
                         for (int t = 0; t < ncol; ++t) {
-                            if (t > 0)
-                                for (int h = 0; h < 2; ++h) {
-                                    const double *c = coef + 2 * ((int64_t)sb.n_dir + 2 * t - 1 + h);
-                                    const double p2 = c[0] * (x * p1 - c[1] * p0);
-                                    p0 = p1;
-                                    p1 = p2;
-                                    if (std::fabs(p1) > 0x1p200) {
-                                        p0 *= 0x1p-200;
-                                        p1 *= 0x1p-200;
-                                        e += 200;
-                                    }
+                            if (t > 0) {
+                                const double *c = coef2 + 3 * ((int64_t)sb.n_dir + 2 * t);
+                                const double p2 = (c[0] * x2 + c[1]) * p1 + c[2] * p0;
+                                p0 = p1;
+                                p1 = p2;
+                                if (std::fabs(p1) > 0x1p200) {
+                                    p0 *= 0x1p-200;
+                                    p1 *= 0x1p-200;
+                                    e += 200;
                                 }
+                            }
                             const double v = e < -1074 ? 0.0 : p1 * std::ldexp(1.0, e);
                             const int jin = sb.pad == 0 ? t : i, qout = sb.pad == 0 ? i : t;
                             const double *xr = in + (size_t)(sb.in_off + jin) * R;

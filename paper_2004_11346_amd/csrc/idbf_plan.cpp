@@ -106,7 +106,7 @@ int build_program(int N, const LegendreTables &lt, const sht_plan_opts &opts, Ho
 }
 
 int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, const double *d_xh,
-                   const double *d_coef, DeviceProgram &d) {
+                   const double *d_coef2, DeviceProgram &d) {
     hipError_t e;
     PackedPlan &pk = hp.packed;
     const int N = hp.N, ntask = 4 * N;
@@ -132,7 +132,7 @@ int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, co
         d.RCW = 64;  // 128 columns leave no LDS for the tile of a generated block
     d.d_wh = d_wh;
     d.d_xh = d_xh;
-    d.d_coef = d_coef;
+    d.d_coef2 = d_coef2;
     if ((e = upload_dir(hp.packed.fwd, ntask, dtype, d.fwd)) != hipSuccess) return fail(e, "upload program");
     if ((e = upload_dir(hp.packed.adj, ntask, dtype, d.adj)) != hipSuccess) return fail(e, "upload program");
     d.x_off_h = pk.x_off;

@@ -113,6 +113,33 @@ void build_legendre_tables(int N, LegendreTables &t) {
             c[2 * (k - m) + 1] = (double)b;
         }
     }
+    // composed two-step coefficients: from P_{k-1} = a_{k-1} (x P_{k-2} - b_{k-1} P_{k-3})
+    // and x P_{k-3} = P_{k-2} / a_{k-2} + b_{k-2} P_{k-4},
+    //   alpha_k = a_k a_{k-1},  beta_k = -a_k (b_k + a_{k-1} b_{k-1} / a_{k-2}),
+    //   gamma_k = -a_k a_{k-1} b_{k-1} b_{k-2};
+    // b_{m+1} = 0 removes the terms that would need a_m or b_m
+    t.coef2.assign((size_t)3 * tri_offset(N, n), 0.0);
+    for (int m = 0; m < n; ++m) {
+        double *c2 = &t.coef2[3 * tri_offset(N, m)];
+        auto A = [&](int k) -> ld {
+            if (k == m + 1) return sqrtl((ld)(2 * m + 3));
+            ld kk = k, mm = m;
+            return sqrtl((4.0L * kk * kk - 1.0L) / ((kk - mm) * (kk + mm)));
+        };
+        auto B = [&](int k) -> ld {
+            if (k <= m + 1) return 0.0L;
+            ld kk = k, mm = m;
+            return sqrtl(((kk - 1 - mm) * (kk - 1 + mm)) / (4.0L * (kk - 1) * (kk - 1) - 1.0L));
+        };
+        for (int k = m + 2; k < n; ++k) {
+            const ld ak = A(k), ak1 = A(k - 1), bk = B(k), bk1 = B(k - 1);
+            const ld mid = bk1 == 0.0L ? 0.0L : ak1 * bk1 / A(k - 2);
+            const ld gam = (bk1 == 0.0L || k - 2 <= m) ? 0.0L : -ak * ak1 * bk1 * B(k - 2);
+            c2[3 * (k - m)] = (double)(ak * ak1);
+            c2[3 * (k - m) + 1] = (double)(-ak * (bk + mid));
+            c2[3 * (k - m) + 2] = (double)gam;
+        }
+    }
 }
 
 void alt_half_matrix(const LegendreTables &t, int a, int parity, double *out) {

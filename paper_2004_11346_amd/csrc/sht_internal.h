@@ -55,6 +55,9 @@ struct LegendreTables {
     std::vector<double> diag_m;   // [2N][N] mantissa of Pbar_m^m(xh[r]) in [0.5, 1)
     std::vector<int32_t> diag_e;  // [2N][N] binary exponent
     std::vector<double> coef;     // [tri][2]: (a_k, b_k) of order m at k = m + j
+    // [tri][3]: two steps of the recurrence composed, same parity:
+    // P_k = (alpha_k x^2 + beta_k) P_{k-2} + gamma_k P_{k-4}, k = m + j, j >= 2
+    std::vector<double> coef2;
 };
 
 void build_legendre_tables(int N, LegendreTables &t);
