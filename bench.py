@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--profile-target", action="store_true",
                     help="only a 1 GiB device copy (counter scale) and a few ALT calls, for rocprofv3 runs")
+    ap.add_argument("--profile-dirs", default="fwd",
+                    help="ALT directions run by --profile-target (comma separated: fwd, inv)")
     ap.add_argument("--workload", choices=["default", "n4096-orders", "uneven"], default="default",
                     help="n4096-orders: N=4096, 8 fields, fast vs plain ALT on 64-order windows across the "
                          "order range; uneven: the grouped 64-transform workload")
@@ -225,8 +227,13 @@ def profile_target(args):
     beta = torch.from_numpy(inputs.make_beta(N, batch, 2, dist="decay")).to(cdt).cuda()
     plan = S.Plan(N, batch, dtype=cdt, method=method)
     g = plan.empty_grid()
-    for _ in range(args.steps):
-        plan.alt(0, 2 * N - 1, "fwd", beta, g)
+    bo = plan.empty_coefs()
+    for d in args.profile_dirs.split(","):
+        for _ in range(args.steps):
+            if d == "fwd":
+                plan.alt(0, 2 * N - 1, "fwd", beta, g)
+            else:
+                plan.alt(0, 2 * N - 1, "inv", g, bo)
     torch.cuda.synchronize()
     print(json.dumps({"profile_target": True, "N": N, "batch": batch, "method": method, "dtype": args.dtype,
                       "alt_calls": args.steps, "copy_bytes": 2 * a.numel() * 8}), flush=True)

@@ -279,7 +279,7 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
         idbf::HostProgram hp;
         int brc;
         try {
-            brc = idbf::build_program(N, lt, p->opts, hp);
+            brc = idbf::build_program(N, batch, lt, p->opts, hp);
         } catch (const std::bad_alloc &) {
             return SHT_ERR_OOM;
         }

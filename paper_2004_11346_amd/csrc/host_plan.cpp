@@ -82,6 +82,12 @@ int sht_host_plan_apply(const sht_host_plan_t *hp, int absm, int parity, int dir
     const int nin = fwd ? t.cols : t.rows, nout = fwd ? t.rows : t.cols;
     std::memcpy(&pin[(size_t)ib * R], in, sizeof(double) * (size_t)nin * R);
     idbf::host_run_program(p, R, pin.data(), pout.data(), hp->data.lt.xh.data(), hp->data.lt.coef2.data());
+    if (fwd && pk.gen_kernels)
+        idbf::host_run_gen_forward(pk.gen_fwd, N, task, task, R, pk.x_off, pk.y_off, pin.data(), pout.data(),
+                                   hp->data.lt.xh.data(), hp->data.lt.coef2.data());
+    if (!fwd && pk.adj_gen_kernel)
+        idbf::host_run_gen_adjoint(pk.gen_adj, N, task, task, R, pk.x_off, pk.y_off, pin.data(), pout.data(),
+                                   hp->data.lt.xh.data(), hp->data.lt.coef2.data());
     std::memcpy(out, &pout[(size_t)ob * R], sizeof(double) * (size_t)nout * R);
     return SHT_OK;
 }
@@ -129,6 +135,17 @@ int sht_host_plan_stats(const sht_host_plan_t *hp, char *json, size_t cap) {
                 for (int b = 0; b < 4; ++b)
                     s += "[" + std::to_string(h[f][b]) + "," + std::to_string(nsub[f][b]) + "]" + (f == 1 && b == 3 ? "" : ",");
             s += "]";
+        }
+        s += ",\"gen_fwd_items\":" + std::to_string(pk.gen_fwd.items.size()) + ",\"gen_fwd_segs\":" +
+             std::to_string(pk.gen_fwd.segs.size()) + ",\"gen_adj_items\":" + std::to_string(pk.gen_adj.items.size()) +
+             ",\"gen_adj_segs\":" + std::to_string(pk.gen_adj.segs.size());
+        {
+            int64_t cols = 0;
+            for (auto &sg : pk.gen_adj.segs) cols += sg.ncol;
+            s += ",\"gen_adj_seg_cols\":" + std::to_string(cols);
+            cols = 0;
+            for (auto &sg : pk.gen_fwd.segs) cols += sg.ncol;
+            s += ",\"gen_fwd_seg_cols\":" + std::to_string(cols);
         }
         s += "}";
     }

@@ -29,7 +29,7 @@ struct HostProgram {
     std::string stats_json;
 };
 
-int build_program(int N, const LegendreTables &lt, const sht_plan_opts &opts, HostProgram &out);
+int build_program(int N, int batch, const LegendreTables &lt, const sht_plan_opts &opts, HostProgram &out);
 int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, const double *d_xh,
                    const double *d_coef2, DeviceProgram &out);
 hipError_t run(const DeviceProgram &prog, const dev::DenseTables &t, int dtype, int batch, int a_lo, int a_hi,

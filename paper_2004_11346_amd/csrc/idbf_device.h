@@ -41,6 +41,14 @@ struct DeviceProgram {
     int64_t max_task_cols = 0;
     int64_t index_bytes = 0;
     DeviceProgramDir fwd, adj;
+    // regenerated forward blocks applied by their own kernel
+    struct Gen {
+        int n_items = 0;
+        void *d_items = nullptr, *d_segs = nullptr;
+        double *d_ck = nullptr;
+        int32_t *d_ckexp = nullptr;
+        std::vector<int32_t> task_first_h;
+    } gen, gena;  // forward, transposed
     void release();
 };
 

@@ -64,6 +64,10 @@ __device__ __forceinline__ void gen_2step(const double *__restrict__ c3, double 
     }
 }
 
+__device__ __forceinline__ int64_t d_tri_offset2(int N, int a) {
+    return 2 * (int64_t)N * a - (int64_t)a * (a - 1) / 2;
+}
+
 // One wave per op.  Lanes own matrix outputs: lane q of a sub-op streams
 // column q of its output-major matrix (consecutive lanes, consecutive words)
 // and keeps the RC right-hand-side sums in registers; the gathered input rows
@@ -611,6 +615,250 @@ __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, co
     }
 }
 
+// ---------------------------------------------------------------------------
+// Regenerated forward blocks (after the op program).  One wave per (task,
+// 64-row tile): lane = row, the block's columns walked from the row's stored
+// state with the two-step recurrence; coefficients and input rows staged in
+// LDS by 64-column chunks.  The tile's sums are added to Y once at the end
+// (items of one tile are one workgroup, so no two workgroups add to a row).
+struct GenItem {
+    int32_t task, row0, seg_begin, seg_end;
+};
+struct GenSeg {
+    int32_t c0, ncol, ck, pad;
+};
+
+template <typename T, int RC>
+__global__ __launch_bounds__(64) void k_gen_fwd(const GenItem *__restrict__ items, int item0,
+                                                const GenSeg *__restrict__ segs, const double *__restrict__ ck,
+                                                const int32_t *__restrict__ ckexp, const double *__restrict__ xh,
+                                                const double *__restrict__ coef2, int N,
+                                                const int64_t *__restrict__ x_off, const T *__restrict__ X,
+                                                int64_t R, int rc, T *__restrict__ Y) {
+    __shared__ double s_c[64 * 3];
+    __shared__ T s_x[64 * RC];
+    const GenItem it = items[item0 + blockIdx.x];
+    const int lane = threadIdx.x;
+    const int r = it.row0 + lane;
+    const int a = it.task >> 1, par = it.task & 1;
+    const double x = xh[r < N ? r : N - 1], x2 = x * x;
+    const double *cfo = coef2 + 3 * (d_tri_offset2(N, a) + par);
+    const T *Xt = X + x_off[it.task] * R;
+    T acc[RC];
+#pragma unroll
+    for (int q = 0; q < RC; ++q) acc[q] = (T)0;
+    for (int s = it.seg_begin; s < it.seg_end; ++s) {
+        const GenSeg sg = segs[s];
+        double p0 = ck[2 * ((int64_t)sg.ck + lane)], p1 = ck[2 * ((int64_t)sg.ck + lane) + 1];
+        int ex = ckexp[sg.ck + lane];
+        double sc = scale_of(ex);
+        for (int t0 = 0; t0 < sg.ncol; t0 += 64) {
+            const int n = min(64, sg.ncol - t0);
+            __syncthreads();
+            if (lane < n) {
+                const int c = sg.c0 + t0 + lane;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) s_c[3 * lane + k] = cfo[3 * (2 * (int64_t)c) + k];
+#pragma unroll
+                for (int q = 0; q < RC; ++q) s_x[lane * RC + q] = q < rc ? Xt[(int64_t)c * R + q] : (T)0;
+            }
+            __syncthreads();
+            for (int t = 0; t < n; ++t) {
+                if (t0 + t > 0) gen_2step(s_c + 3 * t, x2, p0, p1, ex, sc);
+                const T v = (T)(p1 * sc);
+#pragma unroll
+                for (int q = 0; q < RC; ++q) acc[q] += v * s_x[t * RC + q];
+            }
+        }
+    }
+    if (r < N) {
+        T *y = Y + ((int64_t)it.task * N + r) * R;
+#pragma unroll
+        for (int q = 0; q < RC; ++q)
+            if (q < rc) y[q] += acc[q];
+    }
+}
+
+// FP64 matrix cores: 64 rows x 16 CBP columns per wave; per 8-column tile the
+// lanes write their rows' values to LDS and v_mfma_f64_16x16x4f64 takes
+// A = values[16 rows][4 columns], B = X[4 columns][16 columns].
+template <int CBP>
+__global__ __launch_bounds__(64) void k_gen_fwd_mfma(const GenItem *__restrict__ items, int item0,
+                                                     const GenSeg *__restrict__ segs, const double *__restrict__ ck,
+                                                     const int32_t *__restrict__ ckexp,
+                                                     const double *__restrict__ xh, const double *__restrict__ coef2,
+                                                     int N, const int64_t *__restrict__ x_off,
+                                                     const double *__restrict__ X, int64_t R, int col0,
+                                                     double *__restrict__ Y) {
+    constexpr int PAD = 9;
+    __shared__ double tile[64 * PAD];
+    __shared__ double s_c[8 * 3];
+    const GenItem it = items[item0 + blockIdx.x];
+    const int lane = threadIdx.x, jl = lane >> 4, cl = lane & 15;
+    const int r = it.row0 + lane;
+    const int a = it.task >> 1, par = it.task & 1;
+    const double x = xh[r < N ? r : N - 1], x2 = x * x;
+    const double *cfo = coef2 + 3 * (d_tri_offset2(N, a) + par);
+    const double *Xt = X + x_off[it.task] * R;
+    d4v D[4][CBP];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int cb = 0; cb < CBP; ++cb) D[t][cb] = d4v{0.0, 0.0, 0.0, 0.0};
+    for (int s = it.seg_begin; s < it.seg_end; ++s) {
+        const GenSeg sg = segs[s];
+        double p0 = ck[2 * ((int64_t)sg.ck + lane)], p1 = ck[2 * ((int64_t)sg.ck + lane) + 1];
+        int ex = ckexp[sg.ck + lane];
+        double sc = scale_of(ex);
+        for (int t0 = 0; t0 < sg.ncol; t0 += 8) {
+            // B fragments: columns t0 + 4 h + jl (h = 0, 1), RHS col0 + 16 cb + cl
+            double B[2][CBP];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int cb = 0; cb < CBP; ++cb) {
+                    const int t = t0 + 4 * h + jl, col = col0 + 16 * cb + cl;
+                    B[h][cb] = (t < sg.ncol && col < R) ? Xt[(int64_t)(sg.c0 + t) * R + col] : 0.0;
+                }
+            if (lane < 24) {
+                const int t = t0 + lane / 3;
+                s_c[lane] = t < sg.ncol ? cfo[3 * (2 * (int64_t)(sg.c0 + t)) + lane % 3] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int t = t0 + j;
+                double v = 0.0;
+                if (t < sg.ncol) {
+                    if (t > 0) gen_2step(s_c + 3 * j, x2, p0, p1, ex, sc);
+                    v = p1 * sc;
+                }
+                tile[lane * PAD + j] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const double A = tile[(16 * t + cl) * PAD + 4 * h + jl];
+#pragma unroll
+                    for (int cb = 0; cb < CBP; ++cb)
+                        D[t][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(A, B[h][cb], D[t][cb], 0, 0, 0);
+                }
+        }
+    }
+    // element i of lane l: row l/16 + 4 i of row block t, column l % 16
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int cb = 0; cb < CBP; ++cb) {
+            const int col = col0 + 16 * cb + cl;
+            if (col >= R) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = it.row0 + 16 * t + jl + 4 * i;
+                if (row < N) Y[((int64_t)it.task * N + row) * R + col] += D[t][cb][i];
+            }
+        }
+}
+
+// Regenerated transposed blocks (after the op program): one wave per (task,
+// 64-column output tile).  For each segment (a block's 64-row chunk), the
+// lanes (rows) walk the tile's columns 16 at a time into an LDS tile and
+// v_mfma_f64_16x16x4f64 sums over the rows: A = values[16 columns][4 rows],
+// B = H[4 rows][16 right-hand sides] (H rows staged in LDS per segment).
+struct GenItemA {
+    int32_t task, col0, seg_begin, seg_end;
+};
+struct GenSegA {
+    int32_t row0, c0, ncol, ck;
+};
+
+template <typename T, int CBP>
+__global__ __launch_bounds__(64) void k_gen_adj(const GenItemA *__restrict__ items, int item0,
+                                                const GenSegA *__restrict__ segs, const double *__restrict__ ck,
+                                                const int32_t *__restrict__ ckexp, const double *__restrict__ xh,
+                                                const double *__restrict__ coef2, int N,
+                                                const int64_t *__restrict__ x_off, const T *__restrict__ H,
+                                                int64_t R, int rhs0, T *__restrict__ X) {
+    constexpr int PAD = 65, RW = 16 * CBP;
+    constexpr int NCH = 4 / CBP;  // independent accumulation chains per output block
+    __shared__ double tile[16 * PAD];
+    __shared__ double hs[64 * RW];
+    __shared__ double s_c[64 * 3];
+    const GenItemA it = items[item0 + blockIdx.x];
+    const int lane = threadIdx.x, jl = lane >> 4, cl = lane & 15;
+    const int a = it.task >> 1, par = it.task & 1;
+    const double *cfo = coef2 + 3 * (d_tri_offset2(N, a) + par);
+    const int cols_task = (int)(x_off[it.task + 1] - x_off[it.task]);
+    d4v D[4][CBP][NCH];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int cb = 0; cb < CBP; ++cb)
+#pragma unroll
+            for (int h = 0; h < NCH; ++h) D[g][cb][h] = d4v{0.0, 0.0, 0.0, 0.0};
+    for (int s = it.seg_begin; s < it.seg_end; ++s) {
+        const GenSegA sg = segs[s];
+        const int r = sg.row0 + lane;
+        const double x = xh[r < N ? r : N - 1], x2 = x * x;
+        double p0 = ck[2 * ((int64_t)sg.ck + lane)], p1 = ck[2 * ((int64_t)sg.ck + lane) + 1];
+        int ex = ckexp[sg.ck + lane];
+        double sc = scale_of(ex);
+        __syncthreads();
+        for (int e = lane; e < 64 * RW; e += 64) {
+            const int row = e / RW, cc = e - row * RW;
+            const int rr = sg.row0 + row, col = rhs0 + cc;
+            hs[e] = (rr < N && col < R) ? (double)H[((int64_t)it.task * N + rr) * R + col] : 0.0;
+        }
+        for (int e = lane; e < 3 * sg.ncol; e += 64) s_c[e] = cfo[3 * (2 * (int64_t)(sg.c0 + e / 3)) + e % 3];
+        __syncthreads();
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int gc0 = it.col0 + 16 * g;  // first output column of the group
+            if (gc0 + 16 <= sg.c0 || gc0 >= sg.c0 + sg.ncol) continue;
+            for (int j = 0; j < 16; ++j) {
+                const int t = gc0 + j - sg.c0;  // column index in the segment
+                double v = 0.0;
+                if (t >= 0 && t < sg.ncol) {
+                    if (t > 0) gen_2step(s_c + 3 * t, x2, p0, p1, ex, sc);
+                    v = p1 * sc;
+                }
+                tile[j * PAD + lane] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) {
+                const double A = tile[cl * PAD + 4 * ks + jl];
+#pragma unroll
+                for (int cb = 0; cb < CBP; ++cb)
+                    D[g][cb][ks % NCH] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                        A, hs[(4 * ks + jl) * RW + 16 * cb + cl], D[g][cb][ks % NCH], 0, 0, 0);
+            }
+            __syncthreads();
+        }
+    }
+    // element i of lane l: output column l/16 + 4 i of group g, right-hand side l % 16
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int cb = 0; cb < CBP; ++cb) {
+            const int col = rhs0 + 16 * cb + cl;
+            if (col >= R) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int oc = it.col0 + 16 * g + jl + 4 * i;
+                if (oc < cols_task) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int h = 0; h < NCH; ++h) v += D[g][cb][h][i];
+                    T *xo = X + (x_off[it.task] + oc) * R + col;
+                    *xo = (T)((double)*xo + v);
+                }
+            }
+        }
+}
+
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 template <typename T>
@@ -712,6 +960,53 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
             else
                 SHT_OPS_LAUNCH(16);
 #undef SHT_OPS_LAUNCH
+        }
+    }
+    if (fwd && p.gen.n_items > 0) {
+        const int i0 = p.gen.task_first_h[t_lo], i1 = p.gen.task_first_h[t_hi + 1];
+        if (i1 > i0) {
+            prof::Scope ps(s, mfma ? "k_gen_fwd_mfma" : "k_gen_fwd");
+            const GenItem *gi = (const GenItem *)p.gen.d_items;
+            const GenSeg *gs = (const GenSeg *)p.gen.d_segs;
+            if (mfma) {
+                for (int c0 = 0; c0 < R; c0 += 32)
+                    hipLaunchKernelGGL((k_gen_fwd_mfma<2>), dim3(i1 - i0), dim3(64), 0, s, gi, i0, gs, p.gen.d_ck,
+                                       p.gen.d_ckexp, p.d_xh, p.d_coef2, N, p.d_x_off, (const double *)X,
+                                       (int64_t)R, c0, (double *)Y);
+            } else {
+#define SHT_GEN_LAUNCH(RCV)                                                                                      \
+    for (int c0 = 0; c0 < R; c0 += RCV)                                                                          \
+        hipLaunchKernelGGL((k_gen_fwd<T, RCV>), dim3(i1 - i0), dim3(64), 0, s, gi, i0, gs, p.gen.d_ck, p.gen.d_ckexp, \
+                           p.d_xh, p.d_coef2, N, p.d_x_off, (const T *)X + c0, (int64_t)R, std::min(RCV, R - c0), \
+                           Y + c0)
+                if (p.RC == 4)
+                    SHT_GEN_LAUNCH(4);
+                else if (p.RC == 8)
+                    SHT_GEN_LAUNCH(8);
+                else
+                    SHT_GEN_LAUNCH(16);
+#undef SHT_GEN_LAUNCH
+            }
+            hipError_t ge = hipGetLastError();
+            if (ge != hipSuccess) return ge;
+        }
+    }
+    if (!fwd && p.gena.n_items > 0) {
+        const int i0 = p.gena.task_first_h[t_lo], i1 = p.gena.task_first_h[t_hi + 1];
+        if (i1 > i0) {
+            prof::Scope ps(s, "k_gen_adj");
+            const GenItemA *gi = (const GenItemA *)p.gena.d_items;
+            const GenSegA *gs = (const GenSegA *)p.gena.d_segs;
+            if (R <= 16)
+                hipLaunchKernelGGL((k_gen_adj<T, 1>), dim3(i1 - i0), dim3(64), 0, s, gi, i0, gs, p.gena.d_ck,
+                                   p.gena.d_ckexp, p.d_xh, p.d_coef2, N, p.d_x_off, (const T *)Y, (int64_t)R, 0, X);
+            else
+                for (int c0 = 0; c0 < R; c0 += 32)
+                    hipLaunchKernelGGL((k_gen_adj<T, 2>), dim3(i1 - i0), dim3(64), 0, s, gi, i0, gs, p.gena.d_ck,
+                                       p.gena.d_ckexp, p.d_xh, p.d_coef2, N, p.d_x_off, (const T *)Y, (int64_t)R,
+                                       c0, X);
+            hipError_t ge = hipGetLastError();
+            if (ge != hipSuccess) return ge;
         }
     }
     if (fwd) return dev::panel_combine(dt, false, N, batch, a_lo, a_hi, Y, outp, s);

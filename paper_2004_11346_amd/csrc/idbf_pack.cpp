@@ -428,8 +428,8 @@ void emit_gen(const LegendreTables &lt, int a, int par, const Block &b, int mode
 }
 
 void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t> &out_off,
-              const std::vector<int64_t> &in_off, bool fwd, const LegendreTables &lt, int64_t value_hint,
-              Program &p) {
+              const std::vector<int64_t> &in_off, bool fwd, bool gen_kernel, const LegendreTables &lt,
+              int64_t value_hint, Program &p) {
     const int64_t in_rows = in_off[ntask];
     int D = 0;  // number of work stages
     for (auto &b : bps) D = std::max(D, (int)b.levels.size());
@@ -572,7 +572,7 @@ void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t>
                     srcinfo(bi, ls.src_level, buf, base);
                     em.emit(ls, sel, dsel, buf, base, T0, subs);
                 }
-                if (b.gen) {
+                if (b.gen && !gen_kernel) {
                     const Block &g = *b.gen;
                     const int a = t / 2, par = t % 2;
                     const int64_t lo = T0 - r0, hi = T1 - r0;  // tile in task-local rows / columns
@@ -609,7 +609,93 @@ void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t>
 
 }  // namespace
 
-void pack_programs(const HostPlanData &hp, PackedPlan &pk) {
+namespace {
+
+void build_gen_forward(const HostPlanData &hp, GenForward &gf) {
+    const int N = hp.N, ntask = 4 * N;
+    gf = GenForward();
+    gf.task_first.assign(ntask + 1, 0);
+    for (int t = 0; t < ntask; ++t) {
+        gf.task_first[t] = (int32_t)gf.items.size();
+        const Task &tk = hp.tasks[t];
+        if (tk.cols <= 0) continue;
+        std::vector<const Block *> gb;
+        for (const Block &b : tk.blocks)
+            if (b.type == kDense && b.gen) gb.push_back(&b);
+        if (gb.empty()) continue;
+        for (int r0 = 0; r0 < N; r0 += kTile) {
+            GenForward::Item it{t, r0, (int32_t)gf.segs.size(), 0};
+            for (const Block *b : gb) {
+                if (b->r1 <= r0 || b->r0 >= r0 + kTile) continue;
+                GenForward::Seg sg{b->c0, b->c1 - b->c0, (int32_t)gf.ckexp.size(), 0};
+                gf.segs.push_back(sg);
+                for (int q = 0; q < kTile; ++q) {
+                    const int r = r0 + q;
+                    RecState st;
+                    if (r >= b->r0 && r < b->r1 && r < N) {
+                        st = gen_state(hp.lt, tk.a, tk.parity, *b, r, b->c0);
+                        gf.entries += sg.ncol;
+                    } else {
+                        st.pm2 = st.p1 = 0.0;
+                        st.e = 0;
+                    }
+                    gf.ck.push_back(st.pm2);
+                    gf.ck.push_back(st.p1);
+                    gf.ckexp.push_back(st.e);
+                }
+            }
+            it.seg_end = (int32_t)gf.segs.size();
+            if (it.seg_end > it.seg_begin) gf.items.push_back(it);
+        }
+    }
+    gf.task_first[ntask] = (int32_t)gf.items.size();
+}
+
+void build_gen_adjoint(const HostPlanData &hp, GenAdjoint &ga) {
+    const int N = hp.N, ntask = 4 * N;
+    ga = GenAdjoint();
+    ga.task_first.assign(ntask + 1, 0);
+    for (int t = 0; t < ntask; ++t) {
+        ga.task_first[t] = (int32_t)ga.items.size();
+        const Task &tk = hp.tasks[t];
+        if (tk.cols <= 0) continue;
+        std::vector<const Block *> gb;
+        for (const Block &b : tk.blocks)
+            if (b.type == kDense && b.gen) gb.push_back(&b);
+        if (gb.empty()) continue;
+        for (int C0 = 0; C0 < tk.cols; C0 += kTile) {
+            GenAdjoint::Item it{t, C0, (int32_t)ga.segs.size(), 0};
+            for (const Block *b : gb) {
+                const int c0 = std::max(b->c0, C0), c1 = std::min(b->c1, C0 + kTile);
+                if (c1 <= c0) continue;
+                for (int R0 = b->r0 & ~63; R0 < b->r1; R0 += kTile) {
+                    GenAdjoint::Seg sg{R0, c0, c1 - c0, (int32_t)ga.ckexp.size()};
+                    ga.segs.push_back(sg);
+                    for (int q = 0; q < kTile; ++q) {
+                        const int r = R0 + q;
+                        RecState st;
+                        if (r >= b->r0 && r < b->r1 && r < N) {
+                            st = gen_state(hp.lt, tk.a, tk.parity, *b, r, c0);
+                        } else {
+                            st.pm2 = st.p1 = 0.0;
+                            st.e = 0;
+                        }
+                        ga.ck.push_back(st.pm2);
+                        ga.ck.push_back(st.p1);
+                        ga.ckexp.push_back(st.e);
+                    }
+                }
+            }
+            it.seg_end = (int32_t)ga.segs.size();
+            if (it.seg_end > it.seg_begin) ga.items.push_back(it);
+        }
+    }
+    ga.task_first[ntask] = (int32_t)ga.items.size();
+}
+
+}  // namespace
+
+void pack_programs(const HostPlanData &hp, PackedPlan &pk, bool adj_gen_kernel) {
     const int N = hp.N;
     const int ntask = 4 * N;
     Offsets of;
@@ -645,15 +731,96 @@ void pack_programs(const HostPlanData &hp, PackedPlan &pk) {
             }
         auto t1 = T();
         if (fwd)
-            schedule(bps, ntask, of.y, of.x, true, hp.lt, hint, pk.fwd);
+            schedule(bps, ntask, of.y, of.x, true, pk.gen_kernels, hp.lt, hint, pk.fwd);
         else
-            schedule(bps, ntask, of.x, of.y, false, hp.lt, hint, pk.adj);
+            schedule(bps, ntask, of.x, of.y, false, pk.adj_gen_kernel, hp.lt, hint, pk.adj);
         if (verbose)
             std::fprintf(stderr, "[sht] %s chains %.2fs schedule %.2fs\n", fwd ? "fwd" : "adj", D(t0, t1), D(t1, T()));
     };
+    pk.gen_kernels = true;
+    pk.adj_gen_kernel = adj_gen_kernel;
     std::thread th([&] { pack_dir(false); });
     pack_dir(true);
     th.join();
+    std::thread tg([&] {
+        if (adj_gen_kernel) build_gen_adjoint(hp, pk.gen_adj);
+    });
+    build_gen_forward(hp, pk.gen_fwd);
+    tg.join();
+}
+
+void host_run_gen_forward(const GenForward &gf, int N, int t_lo, int t_hi, int R, const std::vector<int64_t> &x_off,
+                          const std::vector<int64_t> &y_off, const double *in, double *out, const double *xh,
+                          const double *coef2) {
+    for (int i = gf.task_first[t_lo]; i < gf.task_first[t_hi + 1]; ++i) {
+        const GenForward::Item &it = gf.items[i];
+        const int a = it.task / 2, par = it.task % 2;
+        const double *cf = coef2 + 3 * (tri_offset(N, a) + par);
+        for (int q = 0; q < 64 && it.row0 + q < N; ++q) {
+            const int r = it.row0 + q;
+            const double x = xh[r], x2 = x * x;
+            double *y = out + (size_t)(y_off[it.task] + r) * R;
+            for (int s = it.seg_begin; s < it.seg_end; ++s) {
+                const GenForward::Seg &sg = gf.segs[s];
+                double p0 = gf.ck[2 * ((int64_t)sg.ck + q)], p1 = gf.ck[2 * ((int64_t)sg.ck + q) + 1];
+                int e = gf.ckexp[sg.ck + q];
+                for (int t = 0; t < sg.ncol; ++t) {
+                    const int c = sg.c0 + t;
+                    if (t > 0) {
+                        const double *c3 = cf + 3 * (2 * (int64_t)c);
+                        const double p2 = (c3[0] * x2 + c3[1]) * p1 + c3[2] * p0;
+                        p0 = p1;
+                        p1 = p2;
+                        if (std::fabs(p1) > 0x1p200) {
+                            p0 *= 0x1p-200;
+                            p1 *= 0x1p-200;
+                            e += 200;
+                        }
+                    }
+                    const double v = e < -1074 ? 0.0 : p1 * std::ldexp(1.0, e);
+                    const double *xr = in + (size_t)(x_off[it.task] + c) * R;
+                    for (int k = 0; k < R; ++k) y[k] += v * xr[k];
+                }
+            }
+        }
+    }
+}
+
+void host_run_gen_adjoint(const GenAdjoint &ga, int N, int t_lo, int t_hi, int R, const std::vector<int64_t> &x_off,
+                          const std::vector<int64_t> &y_off, const double *in, double *out, const double *xh,
+                          const double *coef2) {
+    for (int i = ga.task_first[t_lo]; i < ga.task_first[t_hi + 1]; ++i) {
+        const GenAdjoint::Item &it = ga.items[i];
+        const int a = it.task / 2, par = it.task % 2;
+        const double *cf = coef2 + 3 * (tri_offset(N, a) + par);
+        for (int s = it.seg_begin; s < it.seg_end; ++s) {
+            const GenAdjoint::Seg &sg = ga.segs[s];
+            for (int q = 0; q < 64 && sg.row0 + q < N; ++q) {
+                const int r = sg.row0 + q;
+                const double x = xh[r], x2 = x * x;
+                double p0 = ga.ck[2 * ((int64_t)sg.ck + q)], p1 = ga.ck[2 * ((int64_t)sg.ck + q) + 1];
+                int e = ga.ckexp[sg.ck + q];
+                const double *h = in + (size_t)(y_off[it.task] + r) * R;
+                for (int t = 0; t < sg.ncol; ++t) {
+                    const int c = sg.c0 + t;
+                    if (t > 0) {
+                        const double *c3 = cf + 3 * (2 * (int64_t)c);
+                        const double p2 = (c3[0] * x2 + c3[1]) * p1 + c3[2] * p0;
+                        p0 = p1;
+                        p1 = p2;
+                        if (std::fabs(p1) > 0x1p200) {
+                            p0 *= 0x1p-200;
+                            p1 *= 0x1p-200;
+                            e += 200;
+                        }
+                    }
+                    const double v = e < -1074 ? 0.0 : p1 * std::ldexp(1.0, e);
+                    double *xo = out + (size_t)(x_off[it.task] + c) * R;
+                    for (int k = 0; k < R; ++k) xo[k] += v * h[k];
+                }
+            }
+        }
+    }
 }
 
 void host_run_program(const Program &p, int R, const double *in, double *out, const double *xh,

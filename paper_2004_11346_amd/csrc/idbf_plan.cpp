@@ -71,6 +71,11 @@ void DeviceProgram::release() {
                     (void *)fwd.d_idx, (void *)fwd.d_ck, (void *)fwd.d_ckexp, adj.d_vals, (void *)adj.d_ops,
                     (void *)adj.d_subs, (void *)adj.d_idx, (void *)adj.d_ck, (void *)adj.d_ckexp})
         if (p) (void)hipFree(p);
+    for (Gen *g : {&gen, &gena}) {
+        for (void *q : {g->d_items, g->d_segs, (void *)g->d_ck, (void *)g->d_ckexp})
+            if (q) (void)hipFree(q);
+        *g = Gen();
+    }
     d_X = d_Y = d_scrA = d_scrB = nullptr;
     d_x_off = nullptr;
     fwd = DeviceProgramDir();
@@ -78,12 +83,13 @@ void DeviceProgram::release() {
     valid = false;
 }
 
-int build_program(int N, const LegendreTables &lt, const sht_plan_opts &opts, HostProgram &out) {
+int build_program(int N, int batch, const LegendreTables &lt, const sht_plan_opts &opts, HostProgram &out) {
     (void)lt;
     HostPlanData hp;
     int rc = build_all(N, opts, hp);
     if (rc) return rc;
-    pack_programs(hp, out.packed);
+    // transposed regenerated blocks: matrix-core kernel from 16 right-hand sides
+    pack_programs(hp, out.packed, 4 * batch >= 16);
     out.N = N;
     out.f32_mode = opts.f32_mode;
     out.stats = hp.stats;
@@ -135,6 +141,24 @@ int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, co
     d.d_coef2 = d_coef2;
     if ((e = upload_dir(hp.packed.fwd, ntask, dtype, d.fwd)) != hipSuccess) return fail(e, "upload program");
     if ((e = upload_dir(hp.packed.adj, ntask, dtype, d.adj)) != hipSuccess) return fail(e, "upload program");
+    if (pk.gen_kernels) {
+        GenForward &gf = pk.gen_fwd;
+        d.gen.n_items = (int)gf.items.size();
+        d.gen.task_first_h = gf.task_first;
+        if ((e = up(gf.items, (GenForward::Item **)&d.gen.d_items)) != hipSuccess ||
+            (e = up(gf.segs, (GenForward::Seg **)&d.gen.d_segs)) != hipSuccess ||
+            (e = up(gf.ck, &d.gen.d_ck)) != hipSuccess || (e = up(gf.ckexp, &d.gen.d_ckexp)) != hipSuccess)
+            return fail(e, "upload regenerated blocks");
+        gf = GenForward();
+        GenAdjoint &ga = pk.gen_adj;
+        d.gena.n_items = (int)ga.items.size();
+        d.gena.task_first_h = ga.task_first;
+        if ((e = up(ga.items, (GenAdjoint::Item **)&d.gena.d_items)) != hipSuccess ||
+            (e = up(ga.segs, (GenAdjoint::Seg **)&d.gena.d_segs)) != hipSuccess ||
+            (e = up(ga.ck, &d.gena.d_ck)) != hipSuccess || (e = up(ga.ckexp, &d.gena.d_ckexp)) != hipSuccess)
+            return fail(e, "upload regenerated blocks");
+        ga = GenAdjoint();
+    }
     d.x_off_h = pk.x_off;
     d.y_off_h = pk.y_off;
     if ((e = up(pk.x_off, &d.d_x_off)) != hipSuccess) return fail(e, "upload offsets");
