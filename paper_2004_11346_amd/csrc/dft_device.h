@@ -109,8 +109,10 @@ __device__ __forceinline__ void pass_sum(typename V2<C>::t *buf, int M, int R, i
 // mode 0: synthesis (pre-twiddle e^{+i pi m/M}, sign +1)
 // mode 1: analysis  (sign -1, post-twiddle scale * e^{-i pi m/M})
 // One row by one workgroup: src and dst point at the row (may alias), buf is
-// M complex values of LDS.
-template <typename C, typename T>
+// M complex values of LDS.  MAXO: outputs per thread of the generic pass
+// (radices above 13); 0 when every radix has a register butterfly, which
+// keeps the register budget low enough for two 512-thread rows per CU.
+template <typename C, typename T, int MAXO>
 __device__ __forceinline__ void dft_row(int N, int M, const Passes &ps, const C *__restrict__ tw2,
                                         const int *__restrict__ src_pos, int mode, C scale, const T *src, T *dst,
                                         typename V2<C>::t *buf) {
@@ -135,7 +137,9 @@ __device__ __forceinline__ void dft_row(int N, int M, const Passes &ps, const C 
             case 7: pass_reg<C, 7>(buf, M, L, tw2, sgn); break;
             case 11: pass_reg<C, 11>(buf, M, L, tw2, sgn); break;
             case 13: pass_reg<C, 13>(buf, M, L, tw2, sgn); break;
-            default: pass_sum<C, 32>(buf, M, R, L, tw2, sgn); break;
+            default:
+                if constexpr (MAXO > 0) pass_sum<C, MAXO>(buf, M, R, L, tw2, sgn);
+                break;
         }
         __syncthreads();
     }

@@ -903,9 +903,14 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
             const double *ck = pd.d_ck;
             const int32_t *cke = pd.d_ckexp;
             const bool last = st + 1 == pd.stage_task_first.size();
-            prof::Scope ps(s, mfma   ? (last ? "k_ops_mfma[final]" : "k_ops_mfma[levels]")
-                              : bf16 ? (last ? "k_ops_bf16[final]" : "k_ops_bf16[levels]")
-                                     : (last ? "k_ops[final]" : "k_ops[levels]"));
+            static const char *const kLab[3][9] = {
+                {"k_ops[L0]", "k_ops[L1]", "k_ops[L2]", "k_ops[L3]", "k_ops[L4]", "k_ops[L5]", "k_ops[L6]",
+                 "k_ops[L7+]", "k_ops[final]"},
+                {"k_ops_mfma[L0]", "k_ops_mfma[L1]", "k_ops_mfma[L2]", "k_ops_mfma[L3]", "k_ops_mfma[L4]",
+                 "k_ops_mfma[L5]", "k_ops_mfma[L6]", "k_ops_mfma[L7+]", "k_ops_mfma[final]"},
+                {"k_ops_bf16[L0]", "k_ops_bf16[L1]", "k_ops_bf16[L2]", "k_ops_bf16[L3]", "k_ops_bf16[L4]",
+                 "k_ops_bf16[L5]", "k_ops_bf16[L6]", "k_ops_bf16[L7+]", "k_ops_bf16[final]"}};
+            prof::Scope ps(s, kLab[mfma ? 1 : bf16 ? 2 : 0][last ? 8 : std::min<size_t>(st, 7)]);
             if (bf16) {
                 const float *vf = (const float *)vals;
                 const float *inf = (const float *)(in + c0);

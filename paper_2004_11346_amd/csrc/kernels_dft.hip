@@ -33,14 +33,14 @@ namespace {
 
 using namespace dft;
 
-template <typename C, typename T>
+template <typename C, typename T, int MAXO>
 __global__ __launch_bounds__(512) void k_dft_rows(int N, int M, Passes ps, const C *__restrict__ tw2,
                                                   const int *__restrict__ src_pos, int mode, C scale, const T *in,
                                                   T *out) {
     extern __shared__ unsigned char smem_raw[];
     typename V2<C>::t *buf = reinterpret_cast<typename V2<C>::t *>(smem_raw);
     const int64_t base = 2 * ((int64_t)blockIdx.y * 2 * N * M + (int64_t)blockIdx.x * M);
-    dft_row<C, T>(N, M, ps, tw2, src_pos, mode, scale, in + base, out + base, buf);
+    dft_row<C, T, MAXO>(N, M, ps, tw2, src_pos, mode, scale, in + base, out + base, buf);
 }
 
 template <typename C, typename T>
@@ -55,15 +55,26 @@ hipError_t launch_rows(const DftPlan &p, int batch, int mode, double scale, cons
     const size_t lds = sizeof(typename V2<C>::t) * (size_t)p.M;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)&k_dft_rows<C, T>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
+        for (const void *fn : {(const void *)&k_dft_rows<C, T, 0>, (const void *)&k_dft_rows<C, T, 8>,
+                               (const void *)&k_dft_rows<C, T, 32>}) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e != hipSuccess) return e;
+        }
         attr_set = true;
     }
     const C *tw = sizeof(C) == 8 ? (const C *)p.tw2 : (const C *)p.tw2f;
+    int maxr = 0;
+    for (int i = 0; i < p.nrad; ++i) maxr = std::max(maxr, p.radix[i]);
     prof::Scope sc(s, mode == 0 ? "k_dft_synthesis" : "k_dft_analysis");
-    hipLaunchKernelGGL((k_dft_rows<C, T>), dim3(2 * p.N, batch), dim3(512), lds, s, p.N, p.M, ps, tw, p.src_pos,
-                       mode, (C)scale, (const T *)in, (T *)out);
+    if (maxr <= 13)
+        hipLaunchKernelGGL((k_dft_rows<C, T, 0>), dim3(2 * p.N, batch), dim3(512), lds, s, p.N, p.M, ps, tw,
+                           p.src_pos, mode, (C)scale, (const T *)in, (T *)out);
+    else if (p.M <= 8 * 512)
+        hipLaunchKernelGGL((k_dft_rows<C, T, 8>), dim3(2 * p.N, batch), dim3(512), lds, s, p.N, p.M, ps, tw,
+                           p.src_pos, mode, (C)scale, (const T *)in, (T *)out);
+    else
+        hipLaunchKernelGGL((k_dft_rows<C, T, 32>), dim3(2 * p.N, batch), dim3(512), lds, s, p.N, p.M, ps, tw,
+                           p.src_pos, mode, (C)scale, (const T *)in, (T *)out);
     return hipGetLastError();
 }
 

@@ -99,9 +99,9 @@ __global__ __launch_bounds__(512) void k_group_dft(const GTrans *__restrict__ tr
         const C *tw = sizeof(C) == 8 ? (const C *)d.tw2 : (const C *)d.tw2f;
         if (mode == 0) {
             T *row = (T *)d.f + base;
-            dev::dft::dft_row<C, T>(d.N, d.M, ps, tw, d.src_pos, 0, (C)1, row, row, buf);
+            dev::dft::dft_row<C, T, 8>(d.N, d.M, ps, tw, d.src_pos, 0, (C)1, row, row, buf);
         } else {
-            dev::dft::dft_row<C, T>(d.N, d.M, ps, tw, d.src_pos, 1, (C)(1.0 / d.M), (const T *)d.f + base,
+            dev::dft::dft_row<C, T, 8>(d.N, d.M, ps, tw, d.src_pos, 1, (C)(1.0 / d.M), (const T *)d.f + base,
                                     (T *)d.g + base, buf);
         }
         __syncthreads();
