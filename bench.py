@@ -153,33 +153,35 @@ def kernel_source_sha(files):
 
 
 DOMINANT = {
-    # method, uses matrix cores -> (kernel label, source files)
-    ("dense", True): ("k_dense_fwd_mfma", ["kernels_dense.hip"]),
-    ("dense", False): ("k_dense_fwd_valu", ["kernels_dense.hip"]),
-    ("idbf", True): ("k_ops_mfma", ["idbf_kernels.hip", "idbf_pack.cpp"]),
-    ("idbf", False): ("k_ops", ["idbf_kernels.hip", "idbf_pack.cpp"]),
+    # method, uses matrix cores -> (label, kernel labels summed per call, source files)
+    ("dense", True): ("k_dense_fwd_mfma", ["k_dense_fwd_mfma"], ["kernels_dense.hip", "dense_device.h"]),
+    ("dense", False): ("k_dense_fwd_valu", ["k_dense_fwd_valu"], ["kernels_dense.hip", "dense_device.h"]),
+    ("idbf", True): ("fast ALT kernels (k_ops_mfma stages + k_gen_fwd_mfma)", ["k_ops_mfma", "k_gen_fwd_mfma"],
+                     ["idbf_kernels.hip", "idbf_pack.cpp"]),
+    ("idbf", False): ("fast ALT kernels (k_ops stages + k_gen_fwd)", ["k_ops", "k_gen_fwd"],
+                      ["idbf_kernels.hip", "idbf_pack.cpp"]),
 }
 
 
 def roofline(method, N, batch, dtype, stats, kern, reps):
-    """Roofline object for the dominant kernel of the forward ALT.
+    """Roofline object for the dominant kernel(s) of the forward ALT.
 
     Algorithmic work per ALT call (all orders, one batch):
       plain form:  flops = 2 R N^2 (2N + 1)  (every entry of every half matrix
-                   times R = 4 batch real right-hand sides; FP64 MFMA bound)
-      fast form:   flops = 2 R nnz_plan; bytes = nnz_plan s + index bytes +
-                   batch (4N^2 + 2N M) c_s  (factor stream read once, vectors
-                   in and out; HBM bound below the FP64 ridge, R < 40)
-    The fast form runs as one launch per program stage; its "launch" here is
-    the sum over the stage launches of one call."""
+                   times R = 4 batch real right-hand sides)
+      fast form:   flops = 2 R (stored + regenerated entries); bytes = stored
+                   entries s + index bytes + recurrence states + batch (4N^2 +
+                   2N M) c_s  (factor stream read once, vectors in and out;
+                   HBM bound below the FP64 ridge, R < 40)
+    The fast form runs as one launch per program stage plus the regenerated
+    blocks' kernel; its "launch" here is the sum of those launches per call."""
     M = 4 * N - 1
     R = 4 * batch
     sb = 8 if dtype == "f64" else 4
     mfma_name = "k_dense_fwd_mfma" if method == "dense" else "k_ops_mfma"
     uses_mfma = any(name.startswith(mfma_name) for name in kern)
-    label, files = DOMINANT[(method, uses_mfma)]
-    # the fast form's op kernel is labelled per stage kind ("[levels]", "[final]")
-    parts = [v for name, v in kern.items() if name == label or name.startswith(label + "[")]
+    label, names, files = DOMINANT[(method, uses_mfma)]
+    parts = [v for name, v in kern.items() if any(name == n or name.startswith(n + "[") for n in names)]
     k = {"launches": sum(v["launches"] for v in parts) if parts else 0,
          "total_ms": sum(v["total_ms"] for v in parts) if parts else float("nan")}
     per_call_s = k["total_ms"] / reps / 1e3
@@ -190,8 +192,10 @@ def roofline(method, N, batch, dtype, stats, kern, reps):
     else:
         prog = stats.get("program", {})
         nnz = float(prog.get("stored_entries", 0))
-        flops = 2.0 * R * nnz
-        bytes_ = nnz * sb + float(prog.get("index_bytes", 0)) + batch * (4 * N * N + 2 * N * M) * 2 * sb
+        gen = float(prog.get("generated_entries", 0))
+        flops = 2.0 * R * (nnz + gen)
+        bytes_ = (nnz * sb + float(prog.get("fwd_index_bytes", 0)) + float(prog.get("fwd_state_bytes", 0))
+                  + batch * (4 * N * N + 2 * N * M) * 2 * sb)
     compute_bound = method == "dense" or (2.0 * R / sb) >= PEAK_FP64_TFLOPS / (PEAK_HBM_GBS / 1e3)
     if compute_bound:
         ach = flops / per_call_s / 1e12
@@ -202,7 +206,7 @@ def roofline(method, N, batch, dtype, stats, kern, reps):
         ach = bytes_ / per_call_s / 1e9
         r = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS}
     sha = kernel_source_sha(files)
-    t = TRAFFIC.get((method, N, batch, dtype, label))
+    t = TRAFFIC.get((method, N, batch, dtype, names[0]))
     r["traffic"] = t["bytes_per_call"] if t and t["sha"] == sha else None
     r.update({"kernel": label, "launches_per_call": launches_per_call, "kernel_ms_per_call": per_call_s * 1e3,
               "algorithmic_flops_per_call": flops, "algorithmic_bytes_per_call": bytes_, "kernel_src_sha": sha})

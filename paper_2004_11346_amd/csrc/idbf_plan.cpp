@@ -106,7 +106,18 @@ int build_program(int N, int batch, const LegendreTables &lt, const sht_plan_opt
        << ",\"fwd_stages\":" << out.packed.fwd.stages.size() << ",\"fwd_work_stages\":"
        << out.packed.fwd.n_work_stages << ",\"adj_stages\":" << out.packed.adj.stages.size()
        << ",\"fwd_ops\":" << out.packed.fwd.ops.size() << ",\"scratch_rows\":"
-       << std::max(out.packed.fwd.scr_rows, out.packed.adj.scr_rows) << "}";
+       << std::max(out.packed.fwd.scr_rows, out.packed.adj.scr_rows);
+    // per direction: index stream and recurrence states read by one call
+    const PackedPlan &pk = out.packed;
+    const int64_t fwd_idx = 4 * (int64_t)pk.fwd.idx.size() + (int64_t)pk.fwd.ops.size() * sizeof(Op) +
+                            (int64_t)pk.fwd.subs.size() * sizeof(SubOp) +
+                            (int64_t)pk.gen_fwd.items.size() * sizeof(GenForward::Item) +
+                            (int64_t)pk.gen_fwd.segs.size() * sizeof(GenForward::Seg);
+    const int64_t fwd_states = (int64_t)pk.fwd.ckexp.size() + (int64_t)pk.gen_fwd.ckexp.size();
+    const int64_t adj_states = (int64_t)pk.adj.ckexp.size() + (int64_t)pk.gen_adj.ckexp.size();
+    os << ",\"fwd_index_bytes\":" << fwd_idx << ",\"fwd_state_bytes\":" << 20 * fwd_states
+       << ",\"adj_state_bytes\":" << 20 * adj_states << ",\"gen_fwd_items\":" << pk.gen_fwd.items.size()
+       << ",\"gen_adj_items\":" << pk.gen_adj.items.size() << "}";
     out.stats_json = os.str();
     return SHT_OK;
 }
