@@ -132,13 +132,13 @@ def cpu_baseline(N: int):
 # SHA-256 of the kernel sources it was measured with; a changed source makes
 # the figure stale and it is reported as null.
 TRAFFIC = {
-    ("dense", 1024, 32, "f64", "k_dense_fwd_mfma"): {"bytes_per_call": 24.066e9, "sha": "6c367b5d614a6eb1",
+    ("dense", 1024, 32, "f64", "k_dense_fwd_mfma"): {"bytes_per_call": 24.078e9, "sha": "8aee453d1430ba7c",
                                                      "profile": "profiles/alt_fwd_dense_n1024_b32_f64.md"},
-    ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7339e9, "sha": "6c367b5d614a6eb1",
+    ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7492e9, "sha": "8aee453d1430ba7c",
                                                     "profile": "profiles/alt_fwd_dense_n1024_b1_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_ops_mfma"): {"bytes_per_call": 67.708e9, "sha": "9c31bca4b508372d",
+    ("idbf", 1024, 32, "f64", "k_ops_mfma"): {"bytes_per_call": 63.390e9, "sha": "8e865fdb9ff2fa70",
                                                "profile": "profiles/alt_fwd_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 1, "f64", "k_ops"): {"bytes_per_call": 11.774e9, "sha": "9c31bca4b508372d",
+    ("idbf", 1024, 1, "f64", "k_ops"): {"bytes_per_call": 6.436e9, "sha": "8e865fdb9ff2fa70",
                                          "profile": "profiles/alt_fwd_idbf_n1024_b1_f64.md"},
 }
 
