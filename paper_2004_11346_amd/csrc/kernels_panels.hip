@@ -25,132 +25,162 @@ __device__ __forceinline__ int64_t d_coef_offset(int N, int m) {
     return off;
 }
 
-// The coefficient side (beta) and the grid side (g) are the large arrays: the
-// thread maps make them contiguous across a wave (consecutive degrees of one
-// order, or consecutive orders of one grid row), and put the fields on the
-// fastest-varying workgroup index, so that the 32-byte pieces of panel rows
-// (4 values per field) written or read by neighbouring workgroups meet in L2.
+// Every kernel stages a tile in LDS so that both sides move in runs of at
+// least 256 bytes: a panel row holds R = 4 batch values (field f at columns
+// 4f .. 4f + 3), and the tiles take the fields in chunks of FC = 8 (32 panel
+// values, 256 bytes per panel row).
+constexpr int FC = 8;
 
-// beta -> X panels, orders a_lo..a_hi.  grid (ceil(batch / 4), ceil(max_cols / 64),
-// orders), block 256 = 4 fields x 64 column pairs.  Thread (f, j) moves the
-// degrees k = a + 2j (even task) and a + 2j + 1 (odd task) of orders +a, -a.
+// beta -> X panels.  grid (ceil(max_cols / 64), orders), block 256.  Tile:
+// one order a, column pairs j0 .. j0 + 63 (degrees a + 2j0 .. a + 2j0 + 127 of
+// orders +a and -a), FC fields at a time.
 template <typename B, typename T>
 __global__ __launch_bounds__(256) void k_pack(int N, int batch, int a_lo, const int64_t *__restrict__ x_off,
                                               const B *__restrict__ beta, T *__restrict__ X) {
-    const int a = a_lo + blockIdx.z;
-    const int f = 4 * blockIdx.x + (threadIdx.x >> 6);
-    const int j = 64 * blockIdx.y + (threadIdx.x & 63);
-    if (f >= batch) return;
+    __shared__ double tile[FC][2][128][2];  // field, sign, degree, re/im
+    const int a = a_lo + blockIdx.y;
+    const int j0 = 64 * blockIdx.x;
     const int64_t xe = x_off[2 * a], xo = x_off[2 * a + 1];
     const int ce = (int)(xo - xe), co = (int)(x_off[2 * a + 2] - xo);
-    if (j >= ce) return;
-    const int R = 4 * batch;
-    const B *bp = beta + 2 * ((int64_t)f * 4 * N * N + d_coef_offset(N, a) + 2 * j);
-    const B *bn = beta + 2 * ((int64_t)f * 4 * N * N + d_coef_offset(N, -a) + 2 * j);
-    const bool neg = a > 0;
-    T *x0 = X + (xe + j) * R + 4 * f;
-    x0[0] = (T)bp[0];
-    x0[1] = (T)bp[1];
-    x0[2] = neg ? (T)bn[0] : (T)0;
-    x0[3] = neg ? (T)bn[1] : (T)0;
-    if (j < co) {
-        T *x1 = X + (xo + j) * R + 4 * f;
-        x1[0] = (T)bp[2];
-        x1[1] = (T)bp[3];
-        x1[2] = neg ? (T)bn[2] : (T)0;
-        x1[3] = neg ? (T)bn[3] : (T)0;
+    if (j0 >= ce) return;
+    const int R = 4 * batch, n = 2 * N, nk = n - a;  // degrees of order a
+    const int k0 = 2 * j0;                           // first degree offset k - a
+    const int64_t offp = d_coef_offset(N, a), offn = d_coef_offset(N, -a);
+    const int tid = threadIdx.x;
+    for (int f0 = 0; f0 < batch; f0 += FC) {
+        __syncthreads();
+        // read: per (field, sign) 128 consecutive complex values (2 KB)
+        for (int e = tid; e < FC * 2 * 256; e += 256) {
+            const int fi = e >> 9, sg = (e >> 8) & 1, q = e & 255;  // q: 128 complex x re/im
+            const int kk = k0 + (q >> 1), f = f0 + fi;
+            double v = 0.0;
+            if (f < batch && kk < nk && (sg == 0 || a > 0))
+                v = (double)beta[2 * ((int64_t)f * 4 * N * N + (sg ? offn : offp) + kk) + (q & 1)];
+            tile[fi][sg][q >> 1][q & 1] = v;
+        }
+        __syncthreads();
+        // write: rows of both parity tasks, 4 FC values each (contiguous runs)
+        const int nf = min(FC, batch - f0);
+        for (int e = tid; e < 2 * 64 * 4 * FC; e += 256) {
+            const int par = e / (64 * 4 * FC), rem = e - par * (64 * 4 * FC);
+            const int jj = rem / (4 * FC), c = rem - jj * (4 * FC);
+            const int fi = c >> 2, sg = (c >> 1) & 1, ri = c & 1;
+            const int j = j0 + jj;
+            if (fi >= nf || j >= (par ? co : ce)) continue;
+            X[((par ? xo : xe) + j) * R + 4 * f0 + c] = (T)tile[fi][sg][2 * jj + par][ri];
+        }
     }
 }
 
-// X panels -> beta (transposed direction), same map as k_pack
+// X panels -> beta (transposed direction), the same tile read the other way
 template <typename B, typename T>
 __global__ __launch_bounds__(256) void k_scatter(int N, int batch, int a_lo, const int64_t *__restrict__ x_off,
                                                  const T *__restrict__ X, B *__restrict__ beta) {
-    const int a = a_lo + blockIdx.z;
-    const int f = 4 * blockIdx.x + (threadIdx.x >> 6);
-    const int j = 64 * blockIdx.y + (threadIdx.x & 63);
-    if (f >= batch) return;
+    __shared__ double tile[FC][2][128][2];
+    const int a = a_lo + blockIdx.y;
+    const int j0 = 64 * blockIdx.x;
     const int64_t xe = x_off[2 * a], xo = x_off[2 * a + 1];
     const int ce = (int)(xo - xe), co = (int)(x_off[2 * a + 2] - xo);
-    if (j >= ce) return;
-    const int R = 4 * batch;
-    B *bp = beta + 2 * ((int64_t)f * 4 * N * N + d_coef_offset(N, a) + 2 * j);
-    B *bn = beta + 2 * ((int64_t)f * 4 * N * N + d_coef_offset(N, -a) + 2 * j);
-    const bool neg = a > 0;
-    const T *x0 = X + (xe + j) * R + 4 * f;
-    bp[0] = (B)x0[0];
-    bp[1] = (B)x0[1];
-    if (neg) {
-        bn[0] = (B)x0[2];
-        bn[1] = (B)x0[3];
-    }
-    if (j < co) {
-        const T *x1 = X + (xo + j) * R + 4 * f;
-        bp[2] = (B)x1[0];
-        bp[3] = (B)x1[1];
-        if (neg) {
-            bn[2] = (B)x1[2];
-            bn[3] = (B)x1[3];
+    if (j0 >= ce) return;
+    const int R = 4 * batch, n = 2 * N, nk = n - a;
+    const int k0 = 2 * j0;
+    const int64_t offp = d_coef_offset(N, a), offn = d_coef_offset(N, -a);
+    const int tid = threadIdx.x;
+    for (int f0 = 0; f0 < batch; f0 += FC) {
+        const int nf = min(FC, batch - f0);
+        __syncthreads();
+        for (int e = tid; e < 2 * 64 * 4 * FC; e += 256) {
+            const int par = e / (64 * 4 * FC), rem = e - par * (64 * 4 * FC);
+            const int jj = rem / (4 * FC), c = rem - jj * (4 * FC);
+            const int fi = c >> 2, sg = (c >> 1) & 1, ri = c & 1;
+            const int j = j0 + jj;
+            double v = 0.0;
+            if (fi < nf && j < (par ? co : ce)) v = (double)X[((par ? xo : xe) + j) * R + 4 * f0 + c];
+            tile[fi][sg][2 * jj + par][ri] = v;
+        }
+        __syncthreads();
+        for (int e = tid; e < FC * 2 * 256; e += 256) {
+            const int fi = e >> 9, sg = (e >> 8) & 1, q = e & 255;
+            const int kk = k0 + (q >> 1), f = f0 + fi;
+            if (f < batch && kk < nk && (sg == 0 || a > 0))
+                beta[2 * ((int64_t)f * 4 * N * N + (sg ? offn : offp) + kk) + (q & 1)] = (B)tile[fi][sg][q >> 1][q & 1];
         }
     }
 }
 
 // Y panels -> g columns (parity recombination, Section 3.1.2):
-// g(l = 2N-1-r) = E + O, g(l' = r) = E - O.  grid (batch, ceil(orders / 64),
-// ceil(N / 4)), block 256 = 4 rows x 64 orders.
+// g(l = 2N-1-r) = E + O, g(l' = r) = E - O.  grid (ceil(orders / 16),
+// ceil(N / 4)), block 256.  Tile: 16 orders x 4 half-grid rows, FC fields.
 template <typename B, typename T>
 __global__ __launch_bounds__(256) void k_combine(int N, int M, int batch, int a_lo, int a_hi,
                                                  const T *__restrict__ Y, B *__restrict__ g) {
-    const int f = blockIdx.x;
-    const int a = a_lo + 64 * blockIdx.y + (threadIdx.x & 63);
-    const int r = 4 * blockIdx.z + (threadIdx.x >> 6);
-    if (a > a_hi || r >= N) return;
+    __shared__ double tile[2][16][4][4 * FC];  // parity, order, row, panel value
+    const int a0 = a_lo + 16 * blockIdx.x, r0 = 4 * blockIdx.y;
     const int R = 4 * batch, n = 2 * N;
-    const T *ye = Y + ((int64_t)(2 * a) * N + r) * R + 4 * f;
-    const T *yo = Y + ((int64_t)(2 * a + 1) * N + r) * R + 4 * f;
-    T E[4], O[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        E[q] = ye[q];
-        O[q] = yo[q];
-    }
-    B *gb = g + 2 * ((int64_t)f * n * M);
-    B *gl = gb + 2 * ((int64_t)(n - 1 - r) * M), *gm = gb + 2 * ((int64_t)r * M);
-    gl[2 * a] = (B)(E[0] + O[0]);
-    gl[2 * a + 1] = (B)(E[1] + O[1]);
-    gm[2 * a] = (B)(E[0] - O[0]);
-    gm[2 * a + 1] = (B)(E[1] - O[1]);
-    if (a > 0) {
-        gl[2 * (M - a)] = (B)(E[2] + O[2]);
-        gl[2 * (M - a) + 1] = (B)(E[3] + O[3]);
-        gm[2 * (M - a)] = (B)(E[2] - O[2]);
-        gm[2 * (M - a) + 1] = (B)(E[3] - O[3]);
+    const int tid = threadIdx.x;
+    for (int f0 = 0; f0 < batch; f0 += FC) {
+        const int nf = min(FC, batch - f0);
+        __syncthreads();
+        // read: 128 panel-row pieces of 4 FC values (256 bytes)
+        for (int e = tid; e < 2 * 16 * 4 * 4 * FC; e += 256) {
+            const int seg = e / (4 * FC), c = e - seg * (4 * FC);
+            const int par = seg >> 6, ai = (seg >> 2) & 15, ri = seg & 3;
+            const int a = a0 + ai, r = r0 + ri;
+            double v = 0.0;
+            if (a <= a_hi && r < N && (c >> 2) < nf) v = (double)Y[((int64_t)(2 * a + par) * N + r) * R + 4 * f0 + c];
+            tile[par][ai][ri][c] = v;
+        }
+        __syncthreads();
+        // write: per (field, grid row, sign) 16 consecutive orders
+        for (int e = tid; e < FC * 8 * 2 * 16 * 2; e += 256) {
+            const int ri2 = e & 1, ai = (e >> 1) & 15, sg = (e >> 5) & 1, li = (e >> 6) & 7, fi = e >> 9;
+            const int ri = li >> 1, mirror = li & 1;  // mirror 0: node 2N-1-r (E + O), 1: node r (E - O)
+            const int a = a0 + (sg ? 15 - ai : ai), r = r0 + ri;
+            if (fi >= nf || a > a_hi || r >= N || (sg && a == 0)) continue;
+            const int aj = sg ? 15 - ai : ai;
+            const int c = 4 * fi + 2 * sg + ri2;
+            const double E = tile[0][aj][ri][c], O = tile[1][aj][ri][c];
+            const int l = mirror ? r : n - 1 - r, col = sg ? M - a : a;
+            g[2 * ((int64_t)(f0 + fi) * n * M + (int64_t)l * M + col) + ri2] = (B)(mirror ? E - O : E + O);
+        }
     }
 }
 
 // g columns -> Y panels: H_even = w (g(l) + g(l')), H_odd = w (g(l) - g(l')).
-// grid (ceil(N R / 256), orders), block 256: consecutive threads take
-// consecutive panel values, so the panel rows are written whole.
 template <typename B, typename T>
-__global__ __launch_bounds__(256) void k_fold(int N, int M, int batch, int a_lo, const double *__restrict__ wh,
-                                              const B *__restrict__ g, T *__restrict__ Y) {
-    const int a = a_lo + blockIdx.y;
-    const int R = 4 * batch;
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (int64_t)N * R) return;
-    const int r = (int)(e / R), col = (int)(e - (int64_t)r * R);
-    const int f = col >> 2, s = (col >> 1) & 1, c = col & 1;
-    T u = (T)0, v = (T)0;
-    const int n = 2 * N;
-    if (!(s == 1 && a == 0)) {
-        const int cc = s ? M - a : a;
-        const B *gb = g + 2 * ((int64_t)f * n * M);
-        u = (T)gb[2 * ((int64_t)(n - 1 - r) * M + cc) + c];
-        v = (T)gb[2 * ((int64_t)r * M + cc) + c];
+__global__ __launch_bounds__(256) void k_fold(int N, int M, int batch, int a_lo, int a_hi,
+                                              const double *__restrict__ wh, const B *__restrict__ g,
+                                              T *__restrict__ Y) {
+    __shared__ double tile[2][16][4][4 * FC];  // mirror (node 2N-1-r, node r), order, row, value
+    const int a0 = a_lo + 16 * blockIdx.x, r0 = 4 * blockIdx.y;
+    const int R = 4 * batch, n = 2 * N;
+    const int tid = threadIdx.x;
+    for (int f0 = 0; f0 < batch; f0 += FC) {
+        const int nf = min(FC, batch - f0);
+        __syncthreads();
+        for (int e = tid; e < FC * 8 * 2 * 16 * 2; e += 256) {
+            const int ri2 = e & 1, ai = (e >> 1) & 15, sg = (e >> 5) & 1, li = (e >> 6) & 7, fi = e >> 9;
+            const int ri = li >> 1, mirror = li & 1;
+            const int aj = sg ? 15 - ai : ai;
+            const int a = a0 + aj, r = r0 + ri;
+            double v = 0.0;
+            if (fi < nf && a <= a_hi && r < N && !(sg && a == 0)) {
+                const int l = mirror ? r : n - 1 - r, col = sg ? M - a : a;
+                v = (double)g[2 * ((int64_t)(f0 + fi) * n * M + (int64_t)l * M + col) + ri2];
+            }
+            tile[mirror][aj][ri][4 * fi + 2 * sg + ri2] = v;
+        }
+        __syncthreads();
+        for (int e = tid; e < 2 * 16 * 4 * 4 * FC; e += 256) {
+            const int seg = e / (4 * FC), c = e - seg * (4 * FC);
+            const int par = seg >> 6, ai = (seg >> 2) & 15, ri = seg & 3;
+            const int a = a0 + ai, r = r0 + ri;
+            if (a > a_hi || r >= N || (c >> 2) >= nf) continue;
+            const double u = tile[0][ai][ri][c], v = tile[1][ai][ri][c];
+            const double w = wh ? wh[r] : 1.0;
+            Y[((int64_t)(2 * a + par) * N + r) * R + 4 * f0 + c] = (T)(w * (par ? u - v : u + v));
+        }
     }
-    const T w = wh ? (T)wh[r] : (T)1;
-    Y[((int64_t)(2 * a) * N + r) * R + col] = w * (u + v);
-    Y[((int64_t)(2 * a + 1) * N + r) * R + col] = w * (u - v);
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -162,7 +192,7 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 hipError_t panel_pack(int dtype, bool panel64, int N, int batch, int a_lo, int a_hi, const int64_t *x_off,
                       int64_t max_cols, const void *beta, void *X, hipStream_t s) {
     prof::Scope ps(s, "k_pack");
-    dim3 grid((batch + 3) / 4, (unsigned)((max_cols + 63) / 64), a_hi - a_lo + 1);
+    dim3 grid((unsigned)((max_cols + 63) / 64), a_hi - a_lo + 1);
     if (dtype == 0)
         hipLaunchKernelGGL((k_pack<double, double>), grid, dim3(256), 0, s, N, batch, a_lo, x_off,
                            (const double *)beta, (double *)X);
@@ -178,7 +208,7 @@ hipError_t panel_pack(int dtype, bool panel64, int N, int batch, int a_lo, int a
 hipError_t panel_scatter(int dtype, bool panel64, int N, int batch, int a_lo, int a_hi, const int64_t *x_off,
                          int64_t max_cols, const void *X, void *beta, hipStream_t s) {
     prof::Scope ps(s, "k_scatter");
-    dim3 grid((batch + 3) / 4, (unsigned)((max_cols + 63) / 64), a_hi - a_lo + 1);
+    dim3 grid((unsigned)((max_cols + 63) / 64), a_hi - a_lo + 1);
     if (dtype == 0)
         hipLaunchKernelGGL((k_scatter<double, double>), grid, dim3(256), 0, s, N, batch, a_lo, x_off,
                            (const double *)X, (double *)beta);
@@ -195,7 +225,7 @@ hipError_t panel_combine(int dtype, bool panel64, int N, int batch, int a_lo, in
                          hipStream_t s) {
     prof::Scope ps(s, "k_combine");
     const int M = 4 * N - 1;
-    dim3 grid(batch, (a_hi - a_lo + 64) / 64, (N + 3) / 4);
+    dim3 grid((a_hi - a_lo + 16) / 16, (N + 3) / 4);
     if (dtype == 0)
         hipLaunchKernelGGL((k_combine<double, double>), grid, dim3(256), 0, s, N, M, batch, a_lo, a_hi,
                            (const double *)Y, (double *)g);
@@ -211,16 +241,16 @@ hipError_t panel_combine(int dtype, bool panel64, int N, int batch, int a_lo, in
 hipError_t panel_fold(int dtype, bool panel64, int N, int batch, int a_lo, int a_hi, const double *wh,
                       const void *g, void *Y, hipStream_t s) {
     prof::Scope ps(s, "k_fold");
-    const int R = 4 * batch, M = 4 * N - 1;
-    dim3 grid(blocks_for((int64_t)N * R), a_hi - a_lo + 1);
+    const int M = 4 * N - 1;
+    dim3 grid((a_hi - a_lo + 16) / 16, (N + 3) / 4);
     if (dtype == 0)
-        hipLaunchKernelGGL((k_fold<double, double>), grid, dim3(256), 0, s, N, M, batch, a_lo, wh,
+        hipLaunchKernelGGL((k_fold<double, double>), grid, dim3(256), 0, s, N, M, batch, a_lo, a_hi, wh,
                            (const double *)g, (double *)Y);
     else if (panel64)
-        hipLaunchKernelGGL((k_fold<float, double>), grid, dim3(256), 0, s, N, M, batch, a_lo, wh, (const float *)g,
+        hipLaunchKernelGGL((k_fold<float, double>), grid, dim3(256), 0, s, N, M, batch, a_lo, a_hi, wh, (const float *)g,
                            (double *)Y);
     else
-        hipLaunchKernelGGL((k_fold<float, float>), grid, dim3(256), 0, s, N, M, batch, a_lo, wh, (const float *)g,
+        hipLaunchKernelGGL((k_fold<float, float>), grid, dim3(256), 0, s, N, M, batch, a_lo, a_hi, wh, (const float *)g,
                            (float *)Y);
     return hipGetLastError();
 }
