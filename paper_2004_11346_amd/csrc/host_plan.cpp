@@ -136,6 +136,30 @@ int sht_host_plan_stats(const sht_host_plan_t *hp, char *json, size_t cap) {
                     s += "[" + std::to_string(h[f][b]) + "," + std::to_string(nsub[f][b]) + "]" + (f == 1 && b == 3 ? "" : ",");
             s += "]";
         }
+        {
+            // forward program per stage: ops, sub-ops, stored values, outputs,
+            // gathered inputs, identity terms
+            std::string st = ",\"fwd_stage_detail\":[";
+            for (size_t si = 0; si < pk.fwd.stages.size(); ++si) {
+                int64_t nops = 0, nsub = 0, nval = 0, nout = 0, nin = 0, ndir = 0;
+                for (int q = pk.fwd.stages[si].op_begin; q < pk.fwd.stages[si].op_end; ++q) {
+                    const idbf::Op &op = pk.fwd.ops[q];
+                    ++nops;
+                    nout += op.n_out;
+                    for (int k = 0; k < op.nsub; ++k) {
+                        const idbf::SubOp &so = pk.fwd.subs[op.sub0 + k];
+                        ++nsub;
+                        nval += (int64_t)so.n_map * so.n_in;
+                        nin += so.n_in;
+                        ndir += so.n_dir;
+                    }
+                }
+                st += std::string(si ? "," : "") + "[" + std::to_string(nops) + "," + std::to_string(nsub) + "," +
+                      std::to_string(nval) + "," + std::to_string(nout) + "," + std::to_string(nin) + "," +
+                      std::to_string(ndir) + "]";
+            }
+            s += st + "]";
+        }
         s += ",\"gen_fwd_items\":" + std::to_string(pk.gen_fwd.items.size()) + ",\"gen_fwd_segs\":" +
              std::to_string(pk.gen_fwd.segs.size()) + ",\"gen_adj_items\":" + std::to_string(pk.gen_adj.items.size()) +
              ",\"gen_adj_segs\":" + std::to_string(pk.gen_adj.segs.size());

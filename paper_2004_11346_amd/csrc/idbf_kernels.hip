@@ -236,12 +236,14 @@ __global__ __launch_bounds__(64) void k_ops(const Op *__restrict__ ops, const Su
 
 // FP64 matrix-core variant for many right-hand sides (RCW columns per pass):
 // v_mfma_f64_16x16x4f64 with A = 16 outputs x 4 inputs of the output-major
-// matrix (read straight from HBM, 4 x 128-byte segments per wave) and B = 4
-// gathered input rows x 16 columns from LDS.  Wave w owns output tiles
-// w, w + 4, ... of a sub-op and all RCW / 16 column blocks, so each A fragment
-// feeds RCW / 16 MFMAs; the sub-op's A fragments (n_in <= 64, i.e. at most 16
-// k-steps) are loaded before the first MFMA.  Result element i of lane l is
-// output row l/16 + 4 i, column l % 16.
+// matrix (read straight from HBM) and B = 4 gathered input rows x 16 columns
+// from LDS.  Wave w owns output tile w of a sub-op (at most 64 outputs, so
+// at most four tiles) and all RCW / 16 column blocks.  Software pipeline:
+// while sub-op s computes, its successor's gathered input rows are already in
+// flight into registers, and each wave issues the A values of its tile before
+// the barriers that publish the inputs.  Result element i of lane l is output
+// row l/16 + 4 i, column l % 16.  (Regenerated blocks never reach this kernel:
+// with many right-hand sides they run in their own kernels.)
 typedef double d4v __attribute__((ext_vector_type(4)));
 
 template <int RCW>
@@ -250,135 +252,88 @@ __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, co
                                                   int op_begin, const double *__restrict__ in, int64_t in_stride,
                                                   double *__restrict__ out, int64_t out_stride,
                                                   double *__restrict__ scrA, double *__restrict__ scrB, int rc,
-                                                  int max_out, int max_in, const double *__restrict__ xh,
-                                                  const double *__restrict__ coef, const double *__restrict__ ck,
-                                                  const int32_t *__restrict__ ckexp) {
+                                                  int max_out, int max_in) {
     constexpr int NCB = RCW / 16;
+    constexpr int PF = 64 * RCW / 256;  // staged input values per thread (at most 64 inputs)
     extern __shared__ unsigned char smem_raw[];
-    double *gco = reinterpret_cast<double *>(smem_raw);
-    double *acc = gco + kGco;
+    double *acc = reinterpret_cast<double *>(smem_raw);
     double *xin = acc + (size_t)max_out * RCW;
-    double *gt = xin + (size_t)((max_in + 3) & ~3) * RCW;  // [64][kGT] generated block, outputs x inputs
     const Op op = ops[op_begin + blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int jl = lane >> 4, cl = lane & 15;
     const int n_out = op.n_out;
     for (int e = tid; e < n_out * RCW; e += 256) acc[e] = 0.0;
+    double pre[PF];
+    auto source = [&](const SubOp &sb, int64_t &stride) -> const double * {
+        if (sb.src == kIn) {
+            stride = in_stride;
+            return in;
+        }
+        stride = RCW;
+        return sb.src == kScrA ? scrA : scrB;
+    };
+    auto prefetch = [&](int s) {
+        const SubOp sb = subs[op.sub0 + s];
+        int64_t sstride;
+        const double *src = source(sb, sstride);
+        const int32_t *inr = idx + sb.in_off;
+        const int nin = sb.n_map > 0 ? sb.n_in : 0;
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int e = tid + 256 * i, j = e / RCW, c = e - j * RCW;
+            pre[i] = (j < nin && c < rc) ? src[(int64_t)inr[j] * sstride + c] : 0.0;
+        }
+    };
+    if (op.nsub > 0) prefetch(0);
     for (int s = 0; s < op.nsub; ++s) {
         const SubOp sb = subs[op.sub0 + s];
-        const bool gen = sb.src == kGen;
-        const double *src;
-        int64_t sstride;
-        if (sb.src == kIn || gen) {
-            src = in;
-            sstride = in_stride;
-        } else {
-            src = sb.src == kScrA ? scrA : scrB;
-            sstride = RCW;
-        }
-        __syncthreads();
         const int nin = sb.n_in, nmap = sb.n_map;
-        if (nmap > 0) {
-            const int32_t *inr = idx + sb.in_off;
-            const int nin4 = (nin + 3) & ~3;
-            for (int e = tid; e < nin4 * RCW; e += 256) {
-                const int j = e / RCW, c = e - j * RCW;
-                const int64_t row = gen ? (int64_t)sb.in_off + j : (int64_t)inr[j < nin ? j : 0];
-                xin[e] = (j < nin && c < rc) ? src[row * sstride + c] : 0.0;
+        const int ntile = (nmap + 15) >> 4;
+        const int q = wave * 16 + cl;
+        double areg[16];
+        if (wave < ntile) {
+#pragma unroll
+            for (int st = 0; st < 16; ++st) {
+                const int j = 4 * st + jl;
+                areg[st] = (q < nmap && j < nin) ? vals[sb.mat_off + (int64_t)j * nmap + q] : 0.0;
             }
-            if (gen) {
-                stage_coef(coef + 3 * (int64_t)sb.n_dir, sb.pad == 0 ? nin : nmap, tid, 256, gco);
-                __syncthreads();
+        }
+        __syncthreads();  // the previous sub-op no longer reads xin
+        const int nin4 = (nin + 3) & ~3;
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int e = tid + 256 * i;
+            if (e < nin4 * RCW) xin[e] = pre[i];
+        }
+        __syncthreads();
+        if (s + 1 < op.nsub) prefetch(s + 1);
+        if (nmap > 0 && wave < ntile) {
+            d4v D[NCB];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) D[cb] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int st = 0; st < 16; ++st) {
+                if (4 * st >= nin) break;
+                const double *xr = xin + (4 * st + jl) * RCW + cl;
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb)
+                    D[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[st], xr[cb * 16], D[cb], 0, 0, 0);
             }
-            const bool gfwd = gen && sb.pad == 0;
-            if (gen && !gfwd) {
-                // transposed generated block into LDS (outputs x inputs):
-                // thread (row i, quarter w) walks columns [16 w, 16 w + 16)
-                // from the state stored there
-                const int ngen = nin, ncol = nmap;
-                const int i = lane, c0 = 16 * wave;
-                if (i < ngen && c0 < ncol) {
-                    const int64_t si = sb.mat_off + (int64_t)wave * ngen + i;
-                    double p0 = ck[2 * si], p1 = ck[2 * si + 1];
-                    int ex = ckexp[si];
-                    double sc = scale_of(ex);
-                    const double x = xh[sb.dir_off + i];
-                    const double *cf = gco;
-                    const int c1 = min(ncol, c0 + 16);
-                    for (int t = c0; t < c1; ++t) {
-                        if (t > c0) gen_2step(cf + 3 * t, x * x, p0, p1, ex, sc);
-                        gt[t * kGT + i] = p1 * sc;
-                    }
-                }
-            }
-            __syncthreads();
             const int32_t *map = idx + sb.map_off;
-            const int ntile = (nmap + 15) >> 4;
-            const int jl = lane >> 4, cl = lane & 15;
-            for (int t = wave; t < ntile; t += 4) {
-                const int q = t * 16 + cl;
-                double areg[16];
-                if (gfwd) {
-                    // forward generated block: lane walks row q over all the
-                    // inputs and keeps the columns j = 4 st + jl of its A slots
-                    double p0 = 0.0, p1 = 0.0, x = 0.0, sc = 0.0;
-                    int ex = 0;
-                    if (q < nmap) {
-                        p0 = ck[2 * (sb.mat_off + q)];
-                        p1 = ck[2 * (sb.mat_off + q) + 1];
-                        ex = ckexp[sb.mat_off + q];
-                        sc = scale_of(ex);
-                        x = xh[sb.dir_off + q];
-                    }
-                    const double *cf = gco;
 #pragma unroll
-                    for (int st = 0; st < 16; ++st) {
-                        areg[st] = 0.0;
+            for (int i = 0; i < 4; ++i) {
+                const int qq = wave * 16 + jl + 4 * i;
+                if (qq < nmap) {
+                    double *ar = acc + map[qq] * RCW + cl;
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int j = 4 * st + u;
-                            if (j < nin) {
-                                if (j > 0) gen_2step(cf + 3 * j, x * x, p0, p1, ex, sc);
-                                if (u == jl) areg[st] = p1 * sc;
-                            }
-                        }
-                    }
-                } else if (gen) {
-#pragma unroll
-                    for (int st = 0; st < 16; ++st) {
-                        const int j = 4 * st + jl;
-                        areg[st] = (q < nmap && j < nin) ? gt[q * kGT + j] : 0.0;
-                    }
-                } else {
-#pragma unroll
-                    for (int st = 0; st < 16; ++st) {
-                        const int j = 4 * st + jl;
-                        areg[st] = (q < nmap && j < nin) ? vals[sb.mat_off + (int64_t)j * nmap + q] : 0.0;
-                    }
-                }
-                d4v D[NCB];
-#pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) D[cb] = d4v{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int st = 0; st < 16; ++st) {
-                    if (4 * st >= nin) break;
-                    const double *xr = xin + (4 * st + jl) * RCW + cl;
-#pragma unroll
-                    for (int cb = 0; cb < NCB; ++cb)
-                        D[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[st], xr[cb * 16], D[cb], 0, 0, 0);
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int qq = t * 16 + jl + 4 * i;
-                    if (qq < nmap) {
-                        double *ar = acc + (gen ? sb.map_off + qq : map[qq]) * RCW + cl;
-#pragma unroll
-                        for (int cb = 0; cb < NCB; ++cb) ar[cb * 16] += D[cb][i];
-                    }
+                    for (int cb = 0; cb < NCB; ++cb) ar[cb * 16] += D[cb][i];
                 }
             }
         }
         __syncthreads();
-        if (!gen && sb.n_dir > 0) {
+        if (sb.n_dir > 0) {
+            int64_t sstride;
+            const double *src = source(sb, sstride);
             const int32_t *dir = idx + sb.dir_off;
             for (int e = tid; e < sb.n_dir * RCW; e += 256) {
                 const int d = e / RCW, c = e - d * RCW;
@@ -938,21 +893,22 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
                 continue;
             }
             if (mfma) {
+                if (sg.gen) return hipErrorInvalidValue;  // regenerated blocks run in their own kernels here
                 const double *vd = (const double *)vals;
                 const double *ind = (const double *)(in + c0);
                 double *outd = (double *)(out + c0);
                 if (RC == 128)
                     hipLaunchKernelGGL((k_ops_mfma<128>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
                                        pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
-                                       (double *)scrB, rc, mo, mi, p.d_xh, p.d_coef2, ck, cke);
+                                       (double *)scrB, rc, mo, mi);
                 else if (RC == 64)
                     hipLaunchKernelGGL((k_ops_mfma<64>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
                                        pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
-                                       (double *)scrB, rc, mo, mi, p.d_xh, p.d_coef2, ck, cke);
+                                       (double *)scrB, rc, mo, mi);
                 else
                     hipLaunchKernelGGL((k_ops_mfma<32>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
                                        pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
-                                       (double *)scrB, rc, mo, mi, p.d_xh, p.d_coef2, ck, cke);
+                                       (double *)scrB, rc, mo, mi);
                 continue;
             }
 #define SHT_OPS_LAUNCH(RCV)                                                                                      \
