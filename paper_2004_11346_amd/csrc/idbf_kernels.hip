@@ -68,6 +68,23 @@ __device__ __forceinline__ int64_t d_tri_offset2(int N, int a) {
     return 2 * (int64_t)N * a - (int64_t)a * (a - 1) / 2;
 }
 
+// Workgroups go to the eight XCDs in turn (workgroup i to XCD i mod 8).  The
+// op and gen kernels hand out items (ops, items) in chunks of kXc consecutive ones: chunk c runs
+// on XCD c mod 8, so neighbouring items of a task, which read the same input
+// rows, share that XCD's L2, while the chunks (and the uneven work of the
+// tasks) still spread over all XCDs.  Grid: 8 kXc ceil(chunks / 8).
+constexpr int kXc = 16;
+__device__ __forceinline__ int xcd_item(int n, int xc) {
+    if (xc <= 0) return blockIdx.x;
+    const int x = blockIdx.x & 7, l = blockIdx.x >> 3;
+    return ((l / xc) * 8 + x) * xc + l % xc;
+}
+inline unsigned xcd_grid(int n) {
+    if (kXc <= 0) return (unsigned)n;
+    const int chunks = (n + kXc - 1) / kXc;
+    return 8u * kXc * (unsigned)((chunks + 7) / 8);
+}
+
 // One wave per op.  Lanes own matrix outputs: lane q of a sub-op streams
 // column q of its output-major matrix (consecutive lanes, consecutive words)
 // and keeps the RC right-hand-side sums in registers; the gathered input rows
@@ -75,7 +92,7 @@ __device__ __forceinline__ int64_t d_tri_offset2(int N, int a) {
 template <typename T, int RC>
 __global__ __launch_bounds__(64) void k_ops(const Op *__restrict__ ops, const SubOp *__restrict__ subs,
                                             const int32_t *__restrict__ idx, const T *__restrict__ vals,
-                                            int op_begin, const T *__restrict__ in, int64_t in_stride,
+                                            int op_begin, int n_ops, const T *__restrict__ in, int64_t in_stride,
                                             T *__restrict__ out, int64_t out_stride, T *__restrict__ scrA,
                                             T *__restrict__ scrB, int rc, int max_out, int max_in,
                                             const double *__restrict__ xh, const double *__restrict__ coef,
@@ -85,7 +102,9 @@ __global__ __launch_bounds__(64) void k_ops(const Op *__restrict__ ops, const Su
     T *acc = reinterpret_cast<T *>(gco + kGco);
     T *xin = acc + (size_t)max_out * RC;
     T *gt = xin + (size_t)max_in * RC;  // [16][kGT] tile of a transposed generated block
-    const Op op = ops[op_begin + blockIdx.x];
+    const int oi = xcd_item(n_ops, kXc);
+    if (oi >= n_ops) return;
+    const Op op = ops[op_begin + oi];
     const int lane = threadIdx.x;
     const int n_out = op.n_out;
     for (int e = lane; e < n_out * RC; e += 64) acc[e] = (T)0;
@@ -249,7 +268,7 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 template <int RCW>
 __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, const SubOp *__restrict__ subs,
                                                   const int32_t *__restrict__ idx, const double *__restrict__ vals,
-                                                  int op_begin, const double *__restrict__ in, int64_t in_stride,
+                                                  int op_begin, int n_ops, const double *__restrict__ in, int64_t in_stride,
                                                   double *__restrict__ out, int64_t out_stride,
                                                   double *__restrict__ scrA, double *__restrict__ scrB, int rc,
                                                   int max_out, int max_in) {
@@ -258,7 +277,9 @@ __global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, co
     extern __shared__ unsigned char smem_raw[];
     double *acc = reinterpret_cast<double *>(smem_raw);
     double *xin = acc + (size_t)max_out * RCW;
-    const Op op = ops[op_begin + blockIdx.x];
+    const int oi = xcd_item(n_ops, kXc);
+    if (oi >= n_ops) return;
+    const Op op = ops[op_begin + oi];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int jl = lane >> 4, cl = lane & 15;
     const int n_out = op.n_out;
@@ -390,7 +411,7 @@ __device__ __forceinline__ void split_bf16(float v, short *parts) {
 template <int RCW, int TERMS>
 __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, const SubOp *__restrict__ subs,
                                                   const int32_t *__restrict__ idx, const float *__restrict__ vals,
-                                                  int op_begin, const float *__restrict__ in, int64_t in_stride,
+                                                  int op_begin, int n_ops, const float *__restrict__ in, int64_t in_stride,
                                                   float *__restrict__ out, int64_t out_stride,
                                                   float *__restrict__ scrA, float *__restrict__ scrB, int rc,
                                                   int max_out, int max_in, const double *__restrict__ xh,
@@ -405,7 +426,9 @@ __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, co
     short *xp16 = reinterpret_cast<short *>(acc + (size_t)max_out * RCW);  // NP x [mi16 / 4][RCW][4]
     const size_t pstride = (size_t)mi16 * RCW;
     float *gt = reinterpret_cast<float *>(xp16 + NP * pstride);            // [64][kGT]
-    const Op op = ops[op_begin + blockIdx.x];
+    const int oi = xcd_item(n_ops, kXc);
+    if (oi >= n_ops) return;
+    const Op op = ops[op_begin + oi];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n_out = op.n_out;
     for (int e = tid; e < n_out * RCW; e += 256) acc[e] = 0.f;
@@ -584,7 +607,7 @@ struct GenSeg {
 };
 
 template <typename T, int RC>
-__global__ __launch_bounds__(64) void k_gen_fwd(const GenItem *__restrict__ items, int item0,
+__global__ __launch_bounds__(64) void k_gen_fwd(const GenItem *__restrict__ items, int n_items, int item0,
                                                 const GenSeg *__restrict__ segs, const double *__restrict__ ck,
                                                 const int32_t *__restrict__ ckexp, const double *__restrict__ xh,
                                                 const double *__restrict__ coef2, int N,
@@ -592,7 +615,9 @@ __global__ __launch_bounds__(64) void k_gen_fwd(const GenItem *__restrict__ item
                                                 int64_t R, int rc, T *__restrict__ Y) {
     __shared__ double s_c[64 * 3];
     __shared__ T s_x[64 * RC];
-    const GenItem it = items[item0 + blockIdx.x];
+    const int ii = xcd_item(n_items, kXc);
+    if (ii >= n_items) return;
+    const GenItem it = items[item0 + ii];
     const int lane = threadIdx.x;
     const int r = it.row0 + lane;
     const int a = it.task >> 1, par = it.task & 1;
@@ -634,11 +659,14 @@ __global__ __launch_bounds__(64) void k_gen_fwd(const GenItem *__restrict__ item
     }
 }
 
+
 // FP64 matrix cores: 64 rows x 16 CBP columns per wave; per 8-column tile the
 // lanes write their rows' values to LDS and v_mfma_f64_16x16x4f64 takes
-// A = values[16 rows][4 columns], B = X[4 columns][16 columns].
+// A = values[16 rows][4 columns], B = X[4 columns][16 columns].  The B
+// fragments of the next tile are loaded while the current one is generated
+// and multiplied; the recurrence coefficients are wave-uniform loads.
 template <int CBP>
-__global__ __launch_bounds__(64) void k_gen_fwd_mfma(const GenItem *__restrict__ items, int item0,
+__global__ __launch_bounds__(64) void k_gen_fwd_mfma(const GenItem *__restrict__ items, int n_items, int xc, int item0,
                                                      const GenSeg *__restrict__ segs, const double *__restrict__ ck,
                                                      const int32_t *__restrict__ ckexp,
                                                      const double *__restrict__ xh, const double *__restrict__ coef2,
@@ -648,7 +676,9 @@ __global__ __launch_bounds__(64) void k_gen_fwd_mfma(const GenItem *__restrict__
     constexpr int PAD = 9;
     __shared__ double tile[64 * PAD];
     __shared__ double s_c[8 * 3];
-    const GenItem it = items[item0 + blockIdx.x];
+    const int ii = xcd_item(n_items, xc);
+    if (ii >= n_items) return;
+    const GenItem it = items[item0 + ii];
     const int lane = threadIdx.x, jl = lane >> 4, cl = lane & 15;
     const int r = it.row0 + lane;
     const int a = it.task >> 1, par = it.task & 1;
@@ -662,24 +692,37 @@ __global__ __launch_bounds__(64) void k_gen_fwd_mfma(const GenItem *__restrict__
         for (int cb = 0; cb < CBP; ++cb) D[t][cb] = d4v{0.0, 0.0, 0.0, 0.0};
     for (int s = it.seg_begin; s < it.seg_end; ++s) {
         const GenSeg sg = segs[s];
-        double p0 = ck[2 * ((int64_t)sg.ck + lane)], p1 = ck[2 * ((int64_t)sg.ck + lane) + 1];
-        int ex = ckexp[sg.ck + lane];
-        double sc = scale_of(ex);
-        for (int t0 = 0; t0 < sg.ncol; t0 += 8) {
-            // B fragments: columns t0 + 4 h + jl (h = 0, 1), RHS col0 + 16 cb + cl
-            double B[2][CBP];
+        const double *cs = cfo + 6 * (int64_t)sg.c0;  // (alpha, beta, gamma) of segment column t at cs + 6 t
+        const double *Xs = Xt + (int64_t)sg.c0 * R;
+        // B fragments of the tile at t0: columns t0 + 4 h + jl, RHS col0 + 16 cb + cl
+        auto load_b = [&](double (&B)[2][CBP], int t0) {
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int cb = 0; cb < CBP; ++cb) {
                     const int t = t0 + 4 * h + jl, col = col0 + 16 * cb + cl;
-                    B[h][cb] = (t < sg.ncol && col < R) ? Xt[(int64_t)(sg.c0 + t) * R + col] : 0.0;
+                    B[h][cb] = (t < sg.ncol && col < R) ? Xs[(int64_t)t * R + col] : 0.0;
                 }
-            if (lane < 24) {
-                const int t = t0 + lane / 3;
-                s_c[lane] = t < sg.ncol ? cfo[3 * (2 * (int64_t)(sg.c0 + t)) + lane % 3] : 0.0;
-            }
+        };
+        // lanes 0..23 carry the (alpha, beta, gamma) triples of a tile's 8 columns
+        auto load_c = [&](int t0) {
+            const int t = t0 + lane / 3;
+            return (lane < 24 && t < sg.ncol) ? cs[6 * t + lane % 3] : 0.0;
+        };
+        double p0 = ck[2 * ((int64_t)sg.ck + lane)], p1 = ck[2 * ((int64_t)sg.ck + lane) + 1];
+        int ex = ckexp[sg.ck + lane];
+        double cv = load_c(0), cn = 0.0;
+        double B[2][CBP], Bn[2][CBP];
+        load_b(B, 0);
+        double sc = scale_of(ex);
+        for (int t0 = 0; t0 < sg.ncol; t0 += 8) {
+            const bool more = t0 + 8 < sg.ncol;
+            if (lane < 24) s_c[lane] = cv;
             __syncthreads();
+            if (more) {
+                cn = load_c(t0 + 8);
+                load_b(Bn, t0 + 8);
+            }
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int t = t0 + j;
@@ -700,6 +743,14 @@ __global__ __launch_bounds__(64) void k_gen_fwd_mfma(const GenItem *__restrict__
                     for (int cb = 0; cb < CBP; ++cb)
                         D[t][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(A, B[h][cb], D[t][cb], 0, 0, 0);
                 }
+            __syncthreads();
+            if (more) {
+                cv = cn;
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int cb = 0; cb < CBP; ++cb) B[h][cb] = Bn[h][cb];
+            }
         }
     }
     // element i of lane l: row l/16 + 4 i of row block t, column l % 16
@@ -718,10 +769,12 @@ __global__ __launch_bounds__(64) void k_gen_fwd_mfma(const GenItem *__restrict__
 }
 
 // Regenerated transposed blocks (after the op program): one wave per (task,
-// 64-column output tile).  For each segment (a block's 64-row chunk), the
-// lanes (rows) walk the tile's columns 16 at a time into an LDS tile and
-// v_mfma_f64_16x16x4f64 sums over the rows: A = values[16 columns][4 rows],
-// B = H[4 rows][16 right-hand sides] (H rows staged in LDS per segment).
+// 64-column output tile) and block of 16 CBP right-hand sides.  For each
+// segment (a block's 64-row chunk) the wave keeps the chunk's H fragments in
+// registers (B = H[4 rows][16 right-hand sides], rows 4 ks + l/16), and for
+// each 16-column group of the tile the lanes (rows) step the recurrence into
+// an LDS tile that is read back transposed as A = values[16 columns][4 rows];
+// v_mfma_f64_16x16x4f64 sums over the 64 rows.
 struct GenItemA {
     int32_t task, col0, seg_begin, seg_end;
 };
@@ -730,43 +783,54 @@ struct GenSegA {
 };
 
 template <typename T, int CBP>
-__global__ __launch_bounds__(64) void k_gen_adj(const GenItemA *__restrict__ items, int item0,
+__global__ __launch_bounds__(64) void k_gen_adj(const GenItemA *__restrict__ items, int n_items, int xc, int item0,
                                                 const GenSegA *__restrict__ segs, const double *__restrict__ ck,
                                                 const int32_t *__restrict__ ckexp, const double *__restrict__ xh,
                                                 const double *__restrict__ coef2, int N,
                                                 const int64_t *__restrict__ x_off, const T *__restrict__ H,
                                                 int64_t R, int rhs0, T *__restrict__ X) {
-    constexpr int PAD = 65, RW = 16 * CBP;
-    constexpr int NCH = 4 / CBP;  // independent accumulation chains per output block
+    constexpr int PAD = 65;
     __shared__ double tile[16 * PAD];
-    __shared__ double hs[64 * RW];
     __shared__ double s_c[64 * 3];
-    const GenItemA it = items[item0 + blockIdx.x];
+    const int ii = xcd_item(n_items, xc);
+    if (ii >= n_items) return;
+    const GenItemA it = items[item0 + ii];
     const int lane = threadIdx.x, jl = lane >> 4, cl = lane & 15;
     const int a = it.task >> 1, par = it.task & 1;
     const double *cfo = coef2 + 3 * (d_tri_offset2(N, a) + par);
     const int cols_task = (int)(x_off[it.task + 1] - x_off[it.task]);
-    d4v D[4][CBP][NCH];
+    const T *Ht = H + (int64_t)it.task * N * R;
+    d4v D[4][CBP];
 #pragma unroll
     for (int g = 0; g < 4; ++g)
 #pragma unroll
-        for (int cb = 0; cb < CBP; ++cb)
-#pragma unroll
-            for (int h = 0; h < NCH; ++h) D[g][cb][h] = d4v{0.0, 0.0, 0.0, 0.0};
+        for (int cb = 0; cb < CBP; ++cb) D[g][cb] = d4v{0.0, 0.0, 0.0, 0.0};
     for (int s = it.seg_begin; s < it.seg_end; ++s) {
         const GenSegA sg = segs[s];
+        // recurrence state first: the first steps need it before the H fragments
         const int r = sg.row0 + lane;
         const double x = xh[r < N ? r : N - 1], x2 = x * x;
         double p0 = ck[2 * ((int64_t)sg.ck + lane)], p1 = ck[2 * ((int64_t)sg.ck + lane) + 1];
         int ex = ckexp[sg.ck + lane];
-        double sc = scale_of(ex);
-        __syncthreads();
-        for (int e = lane; e < 64 * RW; e += 64) {
-            const int row = e / RW, cc = e - row * RW;
-            const int rr = sg.row0 + row, col = rhs0 + cc;
-            hs[e] = (rr < N && col < R) ? (double)H[((int64_t)it.task * N + rr) * R + col] : 0.0;
+        const double *cs = cfo + 6 * (int64_t)sg.c0;
+        double cv[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int e = lane + 64 * i;
+            cv[i] = e < 3 * sg.ncol ? cs[6 * (e / 3) + e % 3] : 0.0;
         }
-        for (int e = lane; e < 3 * sg.ncol; e += 64) s_c[e] = cfo[3 * (2 * (int64_t)(sg.c0 + e / 3)) + e % 3];
+        double B[16][CBP];
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+#pragma unroll
+            for (int cb = 0; cb < CBP; ++cb) {
+                const int rr = sg.row0 + 4 * ks + jl, col = rhs0 + 16 * cb + cl;
+                B[ks][cb] = (rr < N && col < R) ? (double)Ht[(int64_t)rr * R + col] : 0.0;
+            }
+        double sc = scale_of(ex);
+        __syncthreads();  // the previous segment no longer reads s_c
+#pragma unroll
+        for (int i = 0; i < 3; ++i) s_c[lane + 64 * i] = cv[i];
         __syncthreads();
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -787,8 +851,7 @@ __global__ __launch_bounds__(64) void k_gen_adj(const GenItemA *__restrict__ ite
                 const double A = tile[cl * PAD + 4 * ks + jl];
 #pragma unroll
                 for (int cb = 0; cb < CBP; ++cb)
-                    D[g][cb][ks % NCH] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                        A, hs[(4 * ks + jl) * RW + 16 * cb + cl], D[g][cb][ks % NCH], 0, 0, 0);
+                    D[g][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(A, B[ks][cb], D[g][cb], 0, 0, 0);
             }
             __syncthreads();
         }
@@ -804,11 +867,8 @@ __global__ __launch_bounds__(64) void k_gen_adj(const GenItemA *__restrict__ ite
             for (int i = 0; i < 4; ++i) {
                 const int oc = it.col0 + 16 * g + jl + 4 * i;
                 if (oc < cols_task) {
-                    double v = 0.0;
-#pragma unroll
-                    for (int h = 0; h < NCH; ++h) v += D[g][cb][h][i];
                     T *xo = X + (x_off[it.task] + oc) * R + col;
-                    *xo = (T)((double)*xo + v);
+                    *xo = (T)((double)*xo + D[g][cb][i]);
                 }
             }
         }
@@ -871,7 +931,8 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
                 const float *inf = (const float *)(in + c0);
                 float *outf = (float *)(out + c0);
 #define SHT_BF16_LAUNCH(W, TM)                                                                                    \
-    hipLaunchKernelGGL((k_ops_bf16<W, TM>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs, pd.d_idx, vf, ob,  \
+    hipLaunchKernelGGL((k_ops_bf16<W, TM>), dim3(xcd_grid(oe - ob)), dim3(256), lds, s, pd.d_ops, pd.d_subs, pd.d_idx, vf, \
+                       ob, oe - ob,                                                                                   \
                        inf, (int64_t)R, outf, (int64_t)R, (float *)scrA, (float *)scrB, rc, mo, mi, p.d_xh, p.d_coef2, \
                        ck, cke)
                 if (p.bf16_terms == 3) {
@@ -898,21 +959,22 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
                 const double *ind = (const double *)(in + c0);
                 double *outd = (double *)(out + c0);
                 if (RC == 128)
-                    hipLaunchKernelGGL((k_ops_mfma<128>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
-                                       pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
+                    hipLaunchKernelGGL((k_ops_mfma<128>), dim3(xcd_grid(oe - ob)), dim3(256), lds, s, pd.d_ops,
+                                       pd.d_subs, pd.d_idx, vd, ob, oe - ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
                                        (double *)scrB, rc, mo, mi);
                 else if (RC == 64)
-                    hipLaunchKernelGGL((k_ops_mfma<64>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
-                                       pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
+                    hipLaunchKernelGGL((k_ops_mfma<64>), dim3(xcd_grid(oe - ob)), dim3(256), lds, s, pd.d_ops,
+                                       pd.d_subs, pd.d_idx, vd, ob, oe - ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
                                        (double *)scrB, rc, mo, mi);
                 else
-                    hipLaunchKernelGGL((k_ops_mfma<32>), dim3(oe - ob), dim3(256), lds, s, pd.d_ops, pd.d_subs,
-                                       pd.d_idx, vd, ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
+                    hipLaunchKernelGGL((k_ops_mfma<32>), dim3(xcd_grid(oe - ob)), dim3(256), lds, s, pd.d_ops,
+                                       pd.d_subs, pd.d_idx, vd, ob, oe - ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
                                        (double *)scrB, rc, mo, mi);
                 continue;
             }
 #define SHT_OPS_LAUNCH(RCV)                                                                                      \
-    hipLaunchKernelGGL((k_ops<T, RCV>), dim3(oe - ob), dim3(64), lds, s, pd.d_ops, pd.d_subs, pd.d_idx, vals, ob, \
+    hipLaunchKernelGGL((k_ops<T, RCV>), dim3(xcd_grid(oe - ob)), dim3(64), lds, s, pd.d_ops, pd.d_subs, pd.d_idx, vals, \
+                       ob, oe - ob,                                                                                  \
                        (const T *)(in + c0), (int64_t)R, out + c0, (int64_t)R, scrA, scrB, rc, mo, mi, p.d_xh, p.d_coef2, ck, cke)
             if (RC == 4)
                 SHT_OPS_LAUNCH(4);
@@ -931,13 +993,14 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
             const GenSeg *gs = (const GenSeg *)p.gen.d_segs;
             if (mfma) {
                 for (int c0 = 0; c0 < R; c0 += 32)
-                    hipLaunchKernelGGL((k_gen_fwd_mfma<2>), dim3(i1 - i0), dim3(64), 0, s, gi, i0, gs, p.gen.d_ck,
-                                       p.gen.d_ckexp, p.d_xh, p.d_coef2, N, p.d_x_off, (const double *)X,
-                                       (int64_t)R, c0, (double *)Y);
+                    hipLaunchKernelGGL((k_gen_fwd_mfma<2>), dim3(xcd_grid(i1 - i0)), dim3(64), 0, s, gi, i1 - i0, kXc,
+                                       i0, gs, p.gen.d_ck, p.gen.d_ckexp, p.d_xh, p.d_coef2, N, p.d_x_off,
+                                       (const double *)X, (int64_t)R, c0, (double *)Y);
             } else {
 #define SHT_GEN_LAUNCH(RCV)                                                                                      \
     for (int c0 = 0; c0 < R; c0 += RCV)                                                                          \
-        hipLaunchKernelGGL((k_gen_fwd<T, RCV>), dim3(i1 - i0), dim3(64), 0, s, gi, i0, gs, p.gen.d_ck, p.gen.d_ckexp, \
+        hipLaunchKernelGGL((k_gen_fwd<T, RCV>), dim3(xcd_grid(i1 - i0)), dim3(64), 0, s, gi, i1 - i0, i0, gs, p.gen.d_ck, \
+                           p.gen.d_ckexp, \
                            p.d_xh, p.d_coef2, N, p.d_x_off, (const T *)X + c0, (int64_t)R, std::min(RCV, R - c0), \
                            Y + c0)
                 if (p.RC == 4)
@@ -959,11 +1022,13 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
             const GenItemA *gi = (const GenItemA *)p.gena.d_items;
             const GenSegA *gs = (const GenSegA *)p.gena.d_segs;
             if (R <= 16)
-                hipLaunchKernelGGL((k_gen_adj<T, 1>), dim3(i1 - i0), dim3(64), 0, s, gi, i0, gs, p.gena.d_ck,
+                hipLaunchKernelGGL((k_gen_adj<T, 1>), dim3(xcd_grid(i1 - i0)), dim3(64), 0, s, gi, i1 - i0, kXc, i0, gs,
+                                   p.gena.d_ck,
                                    p.gena.d_ckexp, p.d_xh, p.d_coef2, N, p.d_x_off, (const T *)Y, (int64_t)R, 0, X);
             else
                 for (int c0 = 0; c0 < R; c0 += 32)
-                    hipLaunchKernelGGL((k_gen_adj<T, 2>), dim3(i1 - i0), dim3(64), 0, s, gi, i0, gs, p.gena.d_ck,
+                    hipLaunchKernelGGL((k_gen_adj<T, 2>), dim3(xcd_grid(i1 - i0)), dim3(64), 0, s, gi, i1 - i0, kXc, i0, gs,
+                                       p.gena.d_ck,
                                        p.gena.d_ckexp, p.d_xh, p.d_coef2, N, p.d_x_off, (const T *)Y, (int64_t)R,
                                        c0, X);
             hipError_t ge = hipGetLastError();
