@@ -253,124 +253,116 @@ __global__ __launch_bounds__(64) void k_ops(const Op *__restrict__ ops, const Su
     }
 }
 
-// FP64 matrix-core variant for many right-hand sides (RCW columns per pass):
-// v_mfma_f64_16x16x4f64 with A = 16 outputs x 4 inputs of the output-major
-// matrix (read straight from HBM) and B = 4 gathered input rows x 16 columns
-// from LDS.  Wave w owns output tile w of a sub-op (at most 64 outputs, so
-// at most four tiles) and all RCW / 16 column blocks.  Software pipeline:
-// while sub-op s computes, its successor's gathered input rows are already in
-// flight into registers, and each wave issues the A values of its tile before
-// the barriers that publish the inputs.  Result element i of lane l is output
-// row l/16 + 4 i, column l % 16.  (Regenerated blocks never reach this kernel:
-// with many right-hand sides they run in their own kernels.)
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-template <int RCW>
-__global__ __launch_bounds__(256) void k_ops_mfma(const Op *__restrict__ ops, const SubOp *__restrict__ subs,
-                                                  const int32_t *__restrict__ idx, const double *__restrict__ vals,
-                                                  int op_begin, int n_ops, const double *__restrict__ in, int64_t in_stride,
-                                                  double *__restrict__ out, int64_t out_stride,
-                                                  double *__restrict__ scrA, double *__restrict__ scrB, int rc,
-                                                  int max_out, int max_in) {
-    constexpr int NCB = RCW / 16;
-    constexpr int PF = 64 * RCW / 256;  // staged input values per thread (at most 64 inputs)
+// FP64 matrix-core op kernel, one wave per (op, block of 16 right-hand-side
+// columns).  For each sub-op the wave gathers its input fragments into
+// registers (B = inputs[4 st + l/16][column l % 16], st < 16) and streams the
+// output-major values from memory as A = values[16 outputs][4 inputs];
+// v_mfma_f64_16x16x4f64 leaves output 16 t + l/16 + 4 i, column l % 16 in
+// element i of lane l, which is added into the op's outputs held in LDS
+// (n_out x 16) through the sub-op's output map; the identity part is added
+// there too and the outputs are stored once.  The column blocks of an op are
+// neighbouring work items (same XCD, about the same time), so its values come
+// from HBM about once per pass and from L2 for the other blocks.
+__global__ __launch_bounds__(64) void k_ops_mfma(const Op *__restrict__ ops, const SubOp *__restrict__ subs,
+                                                   const int32_t *__restrict__ idx, const double *__restrict__ vals,
+                                                   int op_begin, int n_items, int ncb, const double *__restrict__ in,
+                                                   int64_t in_stride, double *__restrict__ out, int64_t out_stride,
+                                                   double *__restrict__ scrA, double *__restrict__ scrB,
+                                                   int64_t scr_stride, int rc) {
     extern __shared__ unsigned char smem_raw[];
     double *acc = reinterpret_cast<double *>(smem_raw);
-    double *xin = acc + (size_t)max_out * RCW;
-    const int oi = xcd_item(n_ops, kXc);
-    if (oi >= n_ops) return;
+    const int wi = xcd_item(n_items, kXc);
+    if (wi >= n_items) return;
+    const int oi = wi / ncb, cb = wi - oi * ncb;
     const Op op = ops[op_begin + oi];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int jl = lane >> 4, cl = lane & 15;
+    const int lane = threadIdx.x, jl = lane >> 4, cl = lane & 15;
+    const int col = 16 * cb + cl;
+    const bool cok = col < rc;
     const int n_out = op.n_out;
-    for (int e = tid; e < n_out * RCW; e += 256) acc[e] = 0.0;
-    double pre[PF];
-    auto source = [&](const SubOp &sb, int64_t &stride) -> const double * {
-        if (sb.src == kIn) {
-            stride = in_stride;
-            return in;
-        }
-        stride = RCW;
-        return sb.src == kScrA ? scrA : scrB;
-    };
-    auto prefetch = [&](int s) {
-        const SubOp sb = subs[op.sub0 + s];
-        int64_t sstride;
-        const double *src = source(sb, sstride);
-        const int32_t *inr = idx + sb.in_off;
-        const int nin = sb.n_map > 0 ? sb.n_in : 0;
-#pragma unroll
-        for (int i = 0; i < PF; ++i) {
-            const int e = tid + 256 * i, j = e / RCW, c = e - j * RCW;
-            pre[i] = (j < nin && c < rc) ? src[(int64_t)inr[j] * sstride + c] : 0.0;
-        }
-    };
-    if (op.nsub > 0) prefetch(0);
+    for (int e = lane; e < n_out * 16; e += 64) acc[e] = 0.0;
+    __syncthreads();
     for (int s = 0; s < op.nsub; ++s) {
         const SubOp sb = subs[op.sub0 + s];
+        const double *src;
+        int64_t sstride;
+        if (sb.src == kIn) {
+            src = in;
+            sstride = in_stride;
+        } else {
+            src = sb.src == kScrA ? scrA : scrB;
+            sstride = scr_stride;
+        }
         const int nin = sb.n_in, nmap = sb.n_map;
-        const int ntile = (nmap + 15) >> 4;
-        const int q = wave * 16 + cl;
-        double areg[16];
-        if (wave < ntile) {
+        if (nmap > 0) {
+            const int32_t *inr = idx + sb.in_off;
+            int rows[16];
 #pragma unroll
             for (int st = 0; st < 16; ++st) {
                 const int j = 4 * st + jl;
-                areg[st] = (q < nmap && j < nin) ? vals[sb.mat_off + (int64_t)j * nmap + q] : 0.0;
+                rows[st] = j < nin ? inr[j] : -1;
             }
-        }
-        __syncthreads();  // the previous sub-op no longer reads xin
-        const int nin4 = (nin + 3) & ~3;
+            double B[16];
 #pragma unroll
-        for (int i = 0; i < PF; ++i) {
-            const int e = tid + 256 * i;
-            if (e < nin4 * RCW) xin[e] = pre[i];
-        }
-        __syncthreads();
-        if (s + 1 < op.nsub) prefetch(s + 1);
-        if (nmap > 0 && wave < ntile) {
-            d4v D[NCB];
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) D[cb] = d4v{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int st = 0; st < 16; ++st) {
-                if (4 * st >= nin) break;
-                const double *xr = xin + (4 * st + jl) * RCW + cl;
-#pragma unroll
-                for (int cb = 0; cb < NCB; ++cb)
-                    D[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[st], xr[cb * 16], D[cb], 0, 0, 0);
-            }
+            for (int st = 0; st < 16; ++st)
+                B[st] = (rows[st] >= 0 && cok) ? src[(int64_t)rows[st] * sstride + col] : 0.0;
             const int32_t *map = idx + sb.map_off;
+            const double *mv = vals + sb.mat_off;
+            const int ntile = (nmap + 15) >> 4;
+            for (int t = 0; t < ntile; ++t) {
+                const int q = 16 * t + cl;
+                double A[16];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int qq = wave * 16 + jl + 4 * i;
-                if (qq < nmap) {
-                    double *ar = acc + map[qq] * RCW + cl;
-#pragma unroll
-                    for (int cb = 0; cb < NCB; ++cb) ar[cb * 16] += D[cb][i];
+                for (int st = 0; st < 16; ++st) {
+                    const int j = 4 * st + jl;
+                    A[st] = (q < nmap && j < nin) ? mv[(int64_t)j * nmap + q] : 0.0;
                 }
+                int dst[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int qq = 16 * t + jl + 4 * i;
+                    dst[i] = qq < nmap ? map[qq] : -1;
+                }
+                d4v D = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int st = 0; st < 16; ++st) {
+                    if (4 * st >= nin) break;
+                    D = __builtin_amdgcn_mfma_f64_16x16x4f64(A[st], B[st], D, 0, 0, 0);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (dst[i] >= 0) acc[dst[i] * 16 + cl] += D[i];
+            }
+        }
+        if (sb.n_dir > 0) {
+            __syncthreads();
+            const int32_t *dir = idx + sb.dir_off;
+            // identity part: four rows per step, lanes = 16 columns; eight steps batched
+            for (int d0 = 0; d0 < sb.n_dir; d0 += 32) {
+                int sr[8], dr[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int d = d0 + 4 * k + jl;
+                    sr[k] = d < sb.n_dir ? dir[2 * d] : -1;
+                    dr[k] = d < sb.n_dir ? dir[2 * d + 1] : -1;
+                }
+                double v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[k] = (sr[k] >= 0 && cok) ? src[(int64_t)sr[k] * sstride + col] : 0.0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (dr[k] >= 0) acc[dr[k] * 16 + cl] += v[k];
             }
         }
         __syncthreads();
-        if (sb.n_dir > 0) {
-            int64_t sstride;
-            const double *src = source(sb, sstride);
-            const int32_t *dir = idx + sb.dir_off;
-            for (int e = tid; e < sb.n_dir * RCW; e += 256) {
-                const int d = e / RCW, c = e - d * RCW;
-                if (c < rc) acc[dir[2 * d + 1] * RCW + c] += src[(int64_t)dir[2 * d] * sstride + c];
-            }
-        }
     }
-    __syncthreads();
+    if (!cok) return;
     if (op.dst == kOut) {
-        for (int e = tid; e < n_out * RCW; e += 256) {
-            const int i = e / RCW, c = e - i * RCW;
-            if (c < rc) out[(op.dst_row + i) * out_stride + c] = acc[e];
-        }
+        for (int i = jl; i < n_out; i += 4) out[(op.dst_row + i) * out_stride + col] = acc[i * 16 + cl];
     } else {
         double *dst = op.dst == kScrA ? scrA : scrB;
-        for (int e = tid; e < n_out * RCW; e += 256) dst[op.dst_row * RCW + e] = acc[e];
+        for (int i = jl; i < n_out; i += 4) dst[(op.dst_row + i) * scr_stride + col] = acc[i * 16 + cl];
     }
 }
 
@@ -914,6 +906,7 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
                 lds = 4 * (size_t)mo * RC + (p.bf16_terms == 3 ? 2 : 3) * 2 * (size_t)((mi + 15) & ~15) * RC +
                       4 * gtile;
             lds += 8 * kGco;  // coefficients of a generated sub-op
+            if (mfma) lds = (size_t)mo * 16 * 8;  // outputs x 16 columns
             if (lds > 160 * 1024) return hipErrorInvalidValue;
             const double *ck = pd.d_ck;
             const int32_t *cke = pd.d_ckexp;
@@ -958,18 +951,11 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
                 const double *vd = (const double *)vals;
                 const double *ind = (const double *)(in + c0);
                 double *outd = (double *)(out + c0);
-                if (RC == 128)
-                    hipLaunchKernelGGL((k_ops_mfma<128>), dim3(xcd_grid(oe - ob)), dim3(256), lds, s, pd.d_ops,
-                                       pd.d_subs, pd.d_idx, vd, ob, oe - ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
-                                       (double *)scrB, rc, mo, mi);
-                else if (RC == 64)
-                    hipLaunchKernelGGL((k_ops_mfma<64>), dim3(xcd_grid(oe - ob)), dim3(256), lds, s, pd.d_ops,
-                                       pd.d_subs, pd.d_idx, vd, ob, oe - ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
-                                       (double *)scrB, rc, mo, mi);
-                else
-                    hipLaunchKernelGGL((k_ops_mfma<32>), dim3(xcd_grid(oe - ob)), dim3(256), lds, s, pd.d_ops,
-                                       pd.d_subs, pd.d_idx, vd, ob, oe - ob, ind, (int64_t)R, outd, (int64_t)R, (double *)scrA,
-                                       (double *)scrB, rc, mo, mi);
+                const int ncb = (rc + 15) / 16;
+                const int n_items = (oe - ob) * ncb;
+                hipLaunchKernelGGL(k_ops_mfma, dim3(xcd_grid(n_items)), dim3(64), lds, s, pd.d_ops,
+                                   pd.d_subs, pd.d_idx, vd, ob, n_items, ncb, ind, (int64_t)R, outd, (int64_t)R,
+                                   (double *)scrA, (double *)scrB, (int64_t)RC, rc);
                 continue;
             }
 #define SHT_OPS_LAUNCH(RCV)                                                                                      \
@@ -1045,8 +1031,7 @@ hipError_t set_kernel_attributes() {
     const void *fns[] = {(const void *)&k_ops<double, 4>,   (const void *)&k_ops<double, 8>,
                          (const void *)&k_ops<double, 16>,  (const void *)&k_ops<float, 4>,
                          (const void *)&k_ops<float, 8>,    (const void *)&k_ops<float, 16>,
-                         (const void *)&k_ops_mfma<32>,     (const void *)&k_ops_mfma<64>,
-                         (const void *)&k_ops_mfma<128>,    (const void *)&k_ops_bf16<16, 3>,
+                         (const void *)&k_ops_bf16<16, 3>,
                          (const void *)&k_ops_bf16<32, 3>,  (const void *)&k_ops_bf16<64, 3>,
                          (const void *)&k_ops_bf16<16, 6>,  (const void *)&k_ops_bf16<32, 6>,
                          (const void *)&k_ops_bf16<64, 6>};

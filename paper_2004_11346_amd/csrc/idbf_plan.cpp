@@ -88,8 +88,9 @@ int build_program(int N, int batch, const LegendreTables &lt, const sht_plan_opt
     HostPlanData hp;
     int rc = build_all(N, opts, hp);
     if (rc) return rc;
-    // transposed regenerated blocks: matrix-core kernel from 16 right-hand sides
-    pack_programs(hp, out.packed, 4 * batch >= 16);
+    (void)batch;
+    // regenerated blocks of both directions run in their own kernels
+    pack_programs(hp, out.packed, true);
     out.N = N;
     out.f32_mode = opts.f32_mode;
     out.stats = hp.stats;
@@ -132,21 +133,20 @@ int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, co
     d.dtype = dtype;
     const int R = 4 * batch;
     d.RC = R <= 4 ? 4 : R <= 8 ? 8 : 16;
-    // FP64 with many right-hand sides: matrix-core executor, 32/64/128 columns
-    // per pass (SHT_IDBF_RCW overrides the choice; 0 disables)
+    // FP64 with many right-hand sides: matrix-core executor, all columns (at
+    // most 256, a multiple of 16) per pass (SHT_IDBF_RCW overrides the pass
+    // width: a multiple of 16 up to 256; 0 disables)
     d.RCW = 0;
-    if (dtype == SHT_F64 && R >= 32) d.RCW = R >= 128 ? 64 : 32;
+    if (dtype == SHT_F64 && R >= 16) d.RCW = std::min(256, (R + 15) & ~15);
     if (const char *e = std::getenv("SHT_IDBF_RCW")) {
         int v = std::atoi(e);
-        d.RCW = (dtype == SHT_F64 && (v == 32 || v == 64 || v == 128)) ? v : 0;
+        d.RCW = (dtype == SHT_F64 && v >= 16 && v <= 256 && v % 16 == 0) ? v : 0;
     }
     if (dtype == SHT_F32 && (hp.f32_mode == SHT_F32_SPLIT_BF16 || hp.f32_mode == SHT_F32_SPLIT_BF16_6)) {
         d.bf16 = true;
         d.bf16_terms = hp.f32_mode == SHT_F32_SPLIT_BF16 ? 3 : 6;
         d.RCW = R <= 16 ? 16 : R <= 32 ? 32 : 64;
     }
-    if (d.RCW == 128 && (!hp.packed.fwd.ckexp.empty() || !hp.packed.adj.ckexp.empty()))
-        d.RCW = 64;  // 128 columns leave no LDS for the tile of a generated block
     d.d_wh = d_wh;
     d.d_xh = d_xh;
     d.d_coef2 = d_coef2;
