@@ -312,11 +312,13 @@ __global__ __launch_bounds__(64) void k_ops_mfma(const Op *__restrict__ ops, con
             const int ntile = (nmap + 15) >> 4;
             for (int t = 0; t < ntile; ++t) {
                 const int q = 16 * t + cl;
+                // value (4 st + jl, q): wave-uniform row-group base + 32-bit lane offset
+                const int aoff = jl * nmap + q;
                 double A[16];
 #pragma unroll
                 for (int st = 0; st < 16; ++st) {
-                    const int j = 4 * st + jl;
-                    A[st] = (q < nmap && j < nin) ? mv[(int64_t)j * nmap + q] : 0.0;
+                    const double *mg = mv + (int64_t)(4 * st) * nmap;
+                    A[st] = (q < nmap && 4 * st + jl < nin) ? mg[aoff] : 0.0;
                 }
                 int dst[4];
 #pragma unroll
@@ -689,12 +691,14 @@ __global__ __launch_bounds__(64) void k_gen_fwd_mfma(const GenItem *__restrict__
         // B fragments of the tile at t0: columns t0 + 4 h + jl, RHS col0 + 16 cb + cl
         auto load_b = [&](double (&B)[2][CBP], int t0) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < 2; ++h) {
+                const double *xg = Xs + (int64_t)(t0 + 4 * h) * R;  // wave-uniform base
 #pragma unroll
                 for (int cb = 0; cb < CBP; ++cb) {
                     const int t = t0 + 4 * h + jl, col = col0 + 16 * cb + cl;
-                    B[h][cb] = (t < sg.ncol && col < R) ? Xs[(int64_t)t * R + col] : 0.0;
+                    B[h][cb] = (t < sg.ncol && col < R) ? xg[jl * (int)R + col] : 0.0;
                 }
+            }
         };
         // lanes 0..23 carry the (alpha, beta, gamma) triples of a tile's 8 columns
         auto load_c = [&](int t0) {
@@ -813,12 +817,14 @@ __global__ __launch_bounds__(64) void k_gen_adj(const GenItemA *__restrict__ ite
         }
         double B[16][CBP];
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks)
+        for (int ks = 0; ks < 16; ++ks) {
+            const T *hg = Ht + (int64_t)(sg.row0 + 4 * ks) * R;  // wave-uniform base
 #pragma unroll
             for (int cb = 0; cb < CBP; ++cb) {
                 const int rr = sg.row0 + 4 * ks + jl, col = rhs0 + 16 * cb + cl;
-                B[ks][cb] = (rr < N && col < R) ? (double)Ht[(int64_t)rr * R + col] : 0.0;
+                B[ks][cb] = (rr < N && col < R) ? (double)hg[jl * (int)R + col] : 0.0;
             }
+        }
         double sc = scale_of(ex);
         __syncthreads();  // the previous segment no longer reads s_c
 #pragma unroll

@@ -30,6 +30,11 @@ __device__ __forceinline__ int64_t d_coef_offset(int N, int m) {
 // 4f .. 4f + 3), and the tiles take the fields in chunks of FC = 8 (32 panel
 // values, 256 bytes per panel row).
 constexpr int FC = 8;
+constexpr int kIt = 16;  // tile values per thread: every tile holds 4096 values, 256 threads
+static_assert(FC * 2 * 256 == 256 * kIt, "pack / scatter tile: [FC][2][128][2]");
+static_assert(2 * 64 * 4 * FC == 256 * kIt, "pack / scatter panel side: 2 parities x 64 rows x 4 FC");
+static_assert(2 * 64 * 4 * FC == 256 * kIt, "combine / fold tile: [2][64][4 FC]");
+static_assert(FC * 2 * 2 * 64 * 2 == 256 * kIt, "combine / fold grid side: FC x mirror x sign x 64 x re/im");
 
 // beta -> X panels.  grid (ceil(max_cols / 64), orders), block 256.  Tile:
 // one order a, column pairs j0 .. j0 + 63 (degrees a + 2j0 .. a + 2j0 + 127 of
@@ -49,25 +54,34 @@ __global__ __launch_bounds__(256) void k_pack(int N, int batch, int a_lo, const 
     const int tid = threadIdx.x;
     for (int f0 = 0; f0 < batch; f0 += FC) {
         __syncthreads();
-        // read: per (field, sign) 128 consecutive complex values (2 KB)
-        for (int e = tid; e < FC * 2 * 256; e += 256) {
+        // read: per (field, sign) 128 consecutive complex values (2 KB); all of
+        // a thread's loads are issued before the tile is written
+        double v[kIt];
+#pragma unroll
+        for (int i = 0; i < kIt; ++i) {
+            const int e = tid + 256 * i;
             const int fi = e >> 9, sg = (e >> 8) & 1, q = e & 255;  // q: 128 complex x re/im
             const int kk = k0 + (q >> 1), f = f0 + fi;
-            double v = 0.0;
-            if (f < batch && kk < nk && (sg == 0 || a > 0))
-                v = (double)beta[2 * ((int64_t)f * 4 * N * N + (sg ? offn : offp) + kk) + (q & 1)];
-            tile[fi][sg][q >> 1][q & 1] = v;
+            v[i] = (f < batch && kk < nk && (sg == 0 || a > 0))
+                       ? (double)beta[2 * ((int64_t)f * 4 * N * N + (sg ? offn : offp) + kk) + (q & 1)]
+                       : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < kIt; ++i) {
+            const int e = tid + 256 * i;
+            tile[e >> 9][(e >> 8) & 1][(e & 255) >> 1][e & 1] = v[i];
         }
         __syncthreads();
         // write: rows of both parity tasks, 4 FC values each (contiguous runs)
         const int nf = min(FC, batch - f0);
-        for (int e = tid; e < 2 * 64 * 4 * FC; e += 256) {
+#pragma unroll
+        for (int i = 0; i < kIt; ++i) {
+            const int e = tid + 256 * i;
             const int par = e / (64 * 4 * FC), rem = e - par * (64 * 4 * FC);
             const int jj = rem / (4 * FC), c = rem - jj * (4 * FC);
             const int fi = c >> 2, sg = (c >> 1) & 1, ri = c & 1;
             const int j = j0 + jj;
-            if (fi >= nf || j >= (par ? co : ce)) continue;
-            X[((par ? xo : xe) + j) * R + 4 * f0 + c] = (T)tile[fi][sg][2 * jj + par][ri];
+            if (fi < nf && j < (par ? co : ce)) X[((par ? xo : xe) + j) * R + 4 * f0 + c] = (T)tile[fi][sg][2 * jj + par][ri];
         }
     }
 }
@@ -89,17 +103,26 @@ __global__ __launch_bounds__(256) void k_scatter(int N, int batch, int a_lo, con
     for (int f0 = 0; f0 < batch; f0 += FC) {
         const int nf = min(FC, batch - f0);
         __syncthreads();
-        for (int e = tid; e < 2 * 64 * 4 * FC; e += 256) {
+        double v[kIt];
+#pragma unroll
+        for (int i = 0; i < kIt; ++i) {
+            const int e = tid + 256 * i;
             const int par = e / (64 * 4 * FC), rem = e - par * (64 * 4 * FC);
             const int jj = rem / (4 * FC), c = rem - jj * (4 * FC);
-            const int fi = c >> 2, sg = (c >> 1) & 1, ri = c & 1;
             const int j = j0 + jj;
-            double v = 0.0;
-            if (fi < nf && j < (par ? co : ce)) v = (double)X[((par ? xo : xe) + j) * R + 4 * f0 + c];
-            tile[fi][sg][2 * jj + par][ri] = v;
+            v[i] = ((c >> 2) < nf && j < (par ? co : ce)) ? (double)X[((par ? xo : xe) + j) * R + 4 * f0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < kIt; ++i) {
+            const int e = tid + 256 * i;
+            const int par = e / (64 * 4 * FC), rem = e - par * (64 * 4 * FC);
+            const int jj = rem / (4 * FC), c = rem - jj * (4 * FC);
+            tile[c >> 2][(c >> 1) & 1][2 * jj + par][c & 1] = v[i];
         }
         __syncthreads();
-        for (int e = tid; e < FC * 2 * 256; e += 256) {
+#pragma unroll
+        for (int i = 0; i < kIt; ++i) {
+            const int e = tid + 256 * i;
             const int fi = e >> 9, sg = (e >> 8) & 1, q = e & 255;
             const int kk = k0 + (q >> 1), f = f0 + fi;
             if (f < batch && kk < nk && (sg == 0 || a > 0))
@@ -109,37 +132,44 @@ __global__ __launch_bounds__(256) void k_scatter(int N, int batch, int a_lo, con
 }
 
 // Y panels -> g columns (parity recombination, Section 3.1.2):
-// g(l = 2N-1-r) = E + O, g(l' = r) = E - O.  grid (ceil(orders / 16),
-// ceil(N / 4)), block 256.  Tile: 16 orders x 4 half-grid rows, FC fields.
+// g(l = 2N-1-r) = E + O, g(l' = r) = E - O.  grid (ceil(orders / 64), N),
+// block 256.  Tile: 64 orders x one half-grid row r, FC fields; each grid row
+// receives runs of 64 consecutive orders (1 KB) per field and sign.
 template <typename B, typename T>
 __global__ __launch_bounds__(256) void k_combine(int N, int M, int batch, int a_lo, int a_hi,
                                                  const T *__restrict__ Y, B *__restrict__ g) {
-    __shared__ double tile[2][16][4][4 * FC];  // parity, order, row, panel value
-    const int a0 = a_lo + 16 * blockIdx.x, r0 = 4 * blockIdx.y;
+    __shared__ double tile[2][64][4 * FC];  // parity, order, panel value
+    const int a0 = a_lo + 64 * blockIdx.x, r = blockIdx.y;
     const int R = 4 * batch, n = 2 * N;
     const int tid = threadIdx.x;
     for (int f0 = 0; f0 < batch; f0 += FC) {
         const int nf = min(FC, batch - f0);
         __syncthreads();
         // read: 128 panel-row pieces of 4 FC values (256 bytes)
-        for (int e = tid; e < 2 * 16 * 4 * 4 * FC; e += 256) {
+        double v[kIt];
+#pragma unroll
+        for (int i = 0; i < kIt; ++i) {
+            const int e = tid + 256 * i;
             const int seg = e / (4 * FC), c = e - seg * (4 * FC);
-            const int par = seg >> 6, ai = (seg >> 2) & 15, ri = seg & 3;
-            const int a = a0 + ai, r = r0 + ri;
-            double v = 0.0;
-            if (a <= a_hi && r < N && (c >> 2) < nf) v = (double)Y[((int64_t)(2 * a + par) * N + r) * R + 4 * f0 + c];
-            tile[par][ai][ri][c] = v;
+            const int par = seg >> 6, a = a0 + (seg & 63);
+            v[i] = (a <= a_hi && (c >> 2) < nf) ? (double)Y[((int64_t)(2 * a + par) * N + r) * R + 4 * f0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < kIt; ++i) {
+            const int e = tid + 256 * i;
+            const int seg = e / (4 * FC), c = e - seg * (4 * FC);
+            tile[seg >> 6][seg & 63][c] = v[i];
         }
         __syncthreads();
-        // write: per (field, grid row, sign) 16 consecutive orders
-        for (int e = tid; e < FC * 8 * 2 * 16 * 2; e += 256) {
-            const int ri2 = e & 1, ai = (e >> 1) & 15, sg = (e >> 5) & 1, li = (e >> 6) & 7, fi = e >> 9;
-            const int ri = li >> 1, mirror = li & 1;  // mirror 0: node 2N-1-r (E + O), 1: node r (E - O)
-            const int a = a0 + (sg ? 15 - ai : ai), r = r0 + ri;
-            if (fi >= nf || a > a_hi || r >= N || (sg && a == 0)) continue;
-            const int aj = sg ? 15 - ai : ai;
+        // write: per (field, mirror row, sign) 64 consecutive orders
+#pragma unroll
+        for (int i = 0; i < kIt; ++i) {
+            const int e = tid + 256 * i;
+            const int ri2 = e & 1, ai = (e >> 1) & 63, sg = (e >> 7) & 1, mirror = (e >> 8) & 1, fi = e >> 9;
+            const int aj = sg ? 63 - ai : ai, a = a0 + aj;  // mirror 0: node 2N-1-r (E + O), 1: node r (E - O)
+            if (fi >= nf || a > a_hi || (sg && a == 0)) continue;
             const int c = 4 * fi + 2 * sg + ri2;
-            const double E = tile[0][aj][ri][c], O = tile[1][aj][ri][c];
+            const double E = tile[0][aj][c], O = tile[1][aj][c];
             const int l = mirror ? r : n - 1 - r, col = sg ? M - a : a;
             g[2 * ((int64_t)(f0 + fi) * n * M + (int64_t)l * M + col) + ri2] = (B)(mirror ? E - O : E + O);
         }
@@ -147,38 +177,46 @@ __global__ __launch_bounds__(256) void k_combine(int N, int M, int batch, int a_
 }
 
 // g columns -> Y panels: H_even = w (g(l) + g(l')), H_odd = w (g(l) - g(l')).
+// grid (ceil(orders / 64), N), block 256; the tile of k_combine read the
+// other way.
 template <typename B, typename T>
 __global__ __launch_bounds__(256) void k_fold(int N, int M, int batch, int a_lo, int a_hi,
                                               const double *__restrict__ wh, const B *__restrict__ g,
                                               T *__restrict__ Y) {
-    __shared__ double tile[2][16][4][4 * FC];  // mirror (node 2N-1-r, node r), order, row, value
-    const int a0 = a_lo + 16 * blockIdx.x, r0 = 4 * blockIdx.y;
+    __shared__ double tile[2][64][4 * FC];  // mirror (node 2N-1-r, node r), order, value
+    const int a0 = a_lo + 64 * blockIdx.x, r = blockIdx.y;
     const int R = 4 * batch, n = 2 * N;
     const int tid = threadIdx.x;
+    const double w = wh ? wh[r] : 1.0;
     for (int f0 = 0; f0 < batch; f0 += FC) {
         const int nf = min(FC, batch - f0);
         __syncthreads();
-        for (int e = tid; e < FC * 8 * 2 * 16 * 2; e += 256) {
-            const int ri2 = e & 1, ai = (e >> 1) & 15, sg = (e >> 5) & 1, li = (e >> 6) & 7, fi = e >> 9;
-            const int ri = li >> 1, mirror = li & 1;
-            const int aj = sg ? 15 - ai : ai;
-            const int a = a0 + aj, r = r0 + ri;
-            double v = 0.0;
-            if (fi < nf && a <= a_hi && r < N && !(sg && a == 0)) {
-                const int l = mirror ? r : n - 1 - r, col = sg ? M - a : a;
-                v = (double)g[2 * ((int64_t)(f0 + fi) * n * M + (int64_t)l * M + col) + ri2];
-            }
-            tile[mirror][aj][ri][4 * fi + 2 * sg + ri2] = v;
+        double v[kIt];
+#pragma unroll
+        for (int i = 0; i < kIt; ++i) {
+            const int e = tid + 256 * i;
+            const int ri2 = e & 1, ai = (e >> 1) & 63, sg = (e >> 7) & 1, mirror = (e >> 8) & 1, fi = e >> 9;
+            const int a = a0 + (sg ? 63 - ai : ai);
+            const int l = mirror ? r : n - 1 - r, col = sg ? M - a : a;
+            v[i] = (fi < nf && a <= a_hi && !(sg && a == 0))
+                       ? (double)g[2 * ((int64_t)(f0 + fi) * n * M + (int64_t)l * M + col) + ri2]
+                       : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < kIt; ++i) {
+            const int e = tid + 256 * i;
+            const int ri2 = e & 1, ai = (e >> 1) & 63, sg = (e >> 7) & 1, mirror = (e >> 8) & 1, fi = e >> 9;
+            tile[mirror][sg ? 63 - ai : ai][4 * fi + 2 * sg + ri2] = v[i];
         }
         __syncthreads();
-        for (int e = tid; e < 2 * 16 * 4 * 4 * FC; e += 256) {
+#pragma unroll
+        for (int i = 0; i < kIt; ++i) {
+            const int e = tid + 256 * i;
             const int seg = e / (4 * FC), c = e - seg * (4 * FC);
-            const int par = seg >> 6, ai = (seg >> 2) & 15, ri = seg & 3;
-            const int a = a0 + ai, r = r0 + ri;
-            if (a > a_hi || r >= N || (c >> 2) >= nf) continue;
-            const double u = tile[0][ai][ri][c], v = tile[1][ai][ri][c];
-            const double w = wh ? wh[r] : 1.0;
-            Y[((int64_t)(2 * a + par) * N + r) * R + 4 * f0 + c] = (T)(w * (par ? u - v : u + v));
+            const int par = seg >> 6, ai = seg & 63, a = a0 + ai;
+            if (a > a_hi || (c >> 2) >= nf) continue;
+            const double u = tile[0][ai][c], v2 = tile[1][ai][c];
+            Y[((int64_t)(2 * a + par) * N + r) * R + 4 * f0 + c] = (T)(w * (par ? u - v2 : u + v2));
         }
     }
 }
@@ -350,7 +388,7 @@ hipError_t panel_combine(int dtype, bool panel64, int N, int batch, int a_lo, in
         return hipGetLastError();
     }
     const int M = 4 * N - 1;
-    dim3 grid((a_hi - a_lo + 16) / 16, (N + 3) / 4);
+    dim3 grid((a_hi - a_lo + 64) / 64, N);
     if (dtype == 0)
         hipLaunchKernelGGL((k_combine<double, double>), grid, dim3(256), 0, s, N, M, batch, a_lo, a_hi,
                            (const double *)Y, (double *)g);
@@ -381,7 +419,7 @@ hipError_t panel_fold(int dtype, bool panel64, int N, int batch, int a_lo, int a
         return hipGetLastError();
     }
     const int M = 4 * N - 1;
-    dim3 grid((a_hi - a_lo + 16) / 16, (N + 3) / 4);
+    dim3 grid((a_hi - a_lo + 64) / 64, N);
     if (dtype == 0)
         hipLaunchKernelGGL((k_fold<double, double>), grid, dim3(256), 0, s, N, M, batch, a_lo, a_hi, wh,
                            (const double *)g, (double *)Y);
