@@ -64,6 +64,36 @@ __device__ __forceinline__ void gen_2step(const double *__restrict__ c3, double 
     }
 }
 
+// n consecutive columns of the same parity with no column guard (tiles that
+// lie inside their segment, past its first column): values p_k * 2^e go to
+// out[j * stride], and the rescale test runs once at the end.  Scaling by
+// 2^-200 is exact, so the values equal those of n gen_2step calls; n steps
+// grow |p| far less than from 2^200 to the top of the FP64 range.
+template <int n>
+__device__ __forceinline__ void gen_run(const double *__restrict__ c3, double x2, double &p0, double &p1, int &e,
+                                        double &sc, double *out, int stride) {
+    static_assert(n % 2 == 0, "steps come in pairs");
+    double q0 = p0, q1 = p1;
+#pragma unroll
+    for (int j = 0; j < n; j += 2) {
+        const double *c = c3 + 3 * j;
+        const double r2 = fma(c[0], x2, c[1]) * q1 + c[2] * q0;
+        out[j * stride] = r2 * sc;
+        const double r3 = fma(c[3], x2, c[4]) * r2 + c[5] * q1;
+        out[(j + 1) * stride] = r3 * sc;
+        q0 = r2;
+        q1 = r3;
+    }
+    p0 = q0;
+    p1 = q1;
+    if (fabs(p1) > 0x1p200 || fabs(p0) > 0x1p200) {
+        p0 *= 0x1p-200;
+        p1 *= 0x1p-200;
+        e += 200;
+        sc = scale_of(e);
+    }
+}
+
 __device__ __forceinline__ int64_t d_tri_offset2(int N, int a) {
     return 2 * (int64_t)N * a - (int64_t)a * (a - 1) / 2;
 }
@@ -719,15 +749,19 @@ __global__ __launch_bounds__(64) void k_gen_fwd_mfma(const GenItem *__restrict__
                 cn = load_c(t0 + 8);
                 load_b(Bn, t0 + 8);
             }
+            if (t0 > 0 && t0 + 8 <= sg.ncol) {
+                gen_run<8>(s_c, x2, p0, p1, ex, sc, tile + lane * PAD, 1);
+            } else {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int t = t0 + j;
-                double v = 0.0;
-                if (t < sg.ncol) {
-                    if (t > 0) gen_2step(s_c + 3 * j, x2, p0, p1, ex, sc);
-                    v = p1 * sc;
+                for (int j = 0; j < 8; ++j) {
+                    const int t = t0 + j;
+                    double v = 0.0;
+                    if (t < sg.ncol) {
+                        if (t > 0) gen_2step(s_c + 3 * j, x2, p0, p1, ex, sc);
+                        v = p1 * sc;
+                    }
+                    tile[lane * PAD + j] = v;
                 }
-                tile[lane * PAD + j] = v;
             }
             __syncthreads();
 #pragma unroll
@@ -834,14 +868,18 @@ __global__ __launch_bounds__(64) void k_gen_adj(const GenItemA *__restrict__ ite
         for (int g = 0; g < 4; ++g) {
             const int gc0 = it.col0 + 16 * g;  // first output column of the group
             if (gc0 + 16 <= sg.c0 || gc0 >= sg.c0 + sg.ncol) continue;
-            for (int j = 0; j < 16; ++j) {
-                const int t = gc0 + j - sg.c0;  // column index in the segment
-                double v = 0.0;
-                if (t >= 0 && t < sg.ncol) {
-                    if (t > 0) gen_2step(s_c + 3 * t, x2, p0, p1, ex, sc);
-                    v = p1 * sc;
+            if (gc0 > sg.c0 && gc0 + 16 <= sg.c0 + sg.ncol) {
+                gen_run<16>(s_c + 3 * (gc0 - sg.c0), x2, p0, p1, ex, sc, tile + lane, PAD);
+            } else {
+                for (int j = 0; j < 16; ++j) {
+                    const int t = gc0 + j - sg.c0;  // column index in the segment
+                    double v = 0.0;
+                    if (t >= 0 && t < sg.ncol) {
+                        if (t > 0) gen_2step(s_c + 3 * t, x2, p0, p1, ex, sc);
+                        v = p1 * sc;
+                    }
+                    tile[j * PAD + lane] = v;
                 }
-                tile[j * PAD + lane] = v;
             }
             __syncthreads();
 #pragma unroll
