@@ -81,11 +81,11 @@ int sht_host_plan_apply(const sht_host_plan_t *hp, int absm, int parity, int dir
     const int64_t ob = fwd ? pk.y_off[task] : pk.x_off[task];
     const int nin = fwd ? t.cols : t.rows, nout = fwd ? t.rows : t.cols;
     std::memcpy(&pin[(size_t)ib * R], in, sizeof(double) * (size_t)nin * R);
-    idbf::host_run_program(p, R, pin.data(), pout.data(), hp->data.lt.xh.data(), hp->data.lt.coef2.data());
-    if (fwd && pk.gen_kernels)
+    idbf::host_run_program(p, R, pin.data(), pout.data());
+    if (fwd)
         idbf::host_run_gen_forward(pk.gen_fwd, N, task, task, R, pk.x_off, pk.y_off, pin.data(), pout.data(),
                                    hp->data.lt.xh.data(), hp->data.lt.coef2.data());
-    if (!fwd && pk.adj_gen_kernel)
+    else
         idbf::host_run_gen_adjoint(pk.gen_adj, N, task, task, R, pk.x_off, pk.y_off, pin.data(), pout.data(),
                                    hp->data.lt.xh.data(), hp->data.lt.coef2.data());
     std::memcpy(out, &pout[(size_t)ob * R], sizeof(double) * (size_t)nout * R);
@@ -124,7 +124,7 @@ int sht_host_plan_stats(const sht_host_plan_t *hp, char *json, size_t cap) {
                 for (int q = pr.stages[si].op_begin; q < pr.stages[si].op_end; ++q)
                     for (int k = 0; k < pr.ops[q].nsub; ++k) {
                         const idbf::SubOp &so = pr.subs[pr.ops[q].sub0 + k];
-                        if (so.src == idbf::kGen || so.n_map == 0) continue;
+                        if (so.n_map == 0) continue;
                         const int b = so.n_map <= 8 ? 0 : so.n_map <= 16 ? 1 : so.n_map <= 32 ? 2 : 3;
                         h[fin][b] += (int64_t)so.n_map * so.n_in;
                         nsub[fin][b] += 1;

@@ -17,9 +17,6 @@ struct DeviceProgramDir {
     Op *d_ops = nullptr;
     SubOp *d_subs = nullptr;
     int32_t *d_idx = nullptr;
-    double *d_ck = nullptr;      // recurrence states (p0, p1) of generated sub-ops
-    int32_t *d_ckexp = nullptr;  // their exponents
-    bool gen = false;
     // stage_task_first[s][t]: first op (global index) of task t in stage s;
     // entry ntask is the stage end
     std::vector<std::vector<int32_t>> stage_task_first;

@@ -37,17 +37,8 @@ __device__ __forceinline__ int64_t d_coef_offset(int N, int m) {
     return off;
 }
 
-constexpr int kGT = 65;  // row stride of the LDS tile of a generated block
 
 __device__ __forceinline__ double scale_of(int e) { return e < -1074 ? 0.0 : ldexp(1.0, e); }
-
-constexpr int kGco = 64 * 3;  // LDS doubles for the coefficients of one generated sub-op
-
-// copy the (alpha, beta, gamma) triples of the sub-op's ncol columns to LDS
-__device__ __forceinline__ void stage_coef(const double *__restrict__ src, int ncol, int tid, int nthreads,
-                                           double *gco) {
-    for (int e = tid; e < 3 * ncol; e += nthreads) gco[e] = src[6 * (e / 3) + e % 3];
-}
 
 // next column of the same parity: the composed two-step recurrence
 // p_k = (alpha_k x^2 + beta_k) p_{k-2} + gamma_k p_{k-4}; c3 = (alpha, beta, gamma)
@@ -124,14 +115,10 @@ __global__ __launch_bounds__(64) void k_ops(const Op *__restrict__ ops, const Su
                                             const int32_t *__restrict__ idx, const T *__restrict__ vals,
                                             int op_begin, int n_ops, const T *__restrict__ in, int64_t in_stride,
                                             T *__restrict__ out, int64_t out_stride, T *__restrict__ scrA,
-                                            T *__restrict__ scrB, int rc, int max_out, int max_in,
-                                            const double *__restrict__ xh, const double *__restrict__ coef,
-                                            const double *__restrict__ ck, const int32_t *__restrict__ ckexp) {
+                                            T *__restrict__ scrB, int rc, int max_out, int max_in) {
     extern __shared__ unsigned char smem_raw[];
-    double *gco = reinterpret_cast<double *>(smem_raw);  // [64][3] recurrence coefficients of a generated sub-op
-    T *acc = reinterpret_cast<T *>(gco + kGco);
+    T *acc = reinterpret_cast<T *>(smem_raw);
     T *xin = acc + (size_t)max_out * RC;
-    T *gt = xin + (size_t)max_in * RC;  // [16][kGT] tile of a transposed generated block
     const int oi = xcd_item(n_ops, kXc);
     if (oi >= n_ops) return;
     const Op op = ops[op_begin + oi];
@@ -140,77 +127,6 @@ __global__ __launch_bounds__(64) void k_ops(const Op *__restrict__ ops, const Su
     for (int e = lane; e < n_out * RC; e += 64) acc[e] = (T)0;
     for (int s = 0; s < op.nsub; ++s) {
         const SubOp sb = subs[op.sub0 + s];
-        if (sb.src == kGen) {
-            const int nin = sb.n_in, nmap = sb.n_map;
-            const bool fwd = sb.pad == 0;
-            const int ngen = fwd ? nmap : nin, ncol = fwd ? nin : nmap;
-            __syncthreads();
-            for (int e = lane; e < nin * RC; e += 64) {
-                const int j = e / RC, r = e - j * RC;
-                xin[e] = r < rc ? in[(int64_t)(sb.in_off + j) * in_stride + r] : (T)0;
-            }
-            stage_coef(coef + 3 * (int64_t)sb.n_dir, ncol, lane, 64, gco);
-            __syncthreads();
-            double p0 = 0.0, p1 = 0.0, x = 0.0, sc = 0.0;
-            int ex = 0;
-            if (lane < ngen) {
-                p0 = ck[2 * (sb.mat_off + lane)];
-                p1 = ck[2 * (sb.mat_off + lane) + 1];
-                ex = ckexp[sb.mat_off + lane];
-                sc = scale_of(ex);
-                x = xh[sb.dir_off + lane];
-            }
-            const double *cf = gco;
-            if (fwd) {
-                T a[RC];
-#pragma unroll
-                for (int r = 0; r < RC; ++r) a[r] = (T)0;
-                for (int t = 0; t < ncol; ++t) {
-                    if (t > 0) gen_2step(cf + 3 * t, x * x, p0, p1, ex, sc);
-                    const T v = (T)(p1 * sc);
-#pragma unroll
-                    for (int r = 0; r < RC; ++r) a[r] += v * xin[t * RC + r];
-                }
-                if (lane < ngen)
-#pragma unroll
-                    for (int r = 0; r < RC; ++r) acc[(sb.map_off + lane) * RC + r] += a[r];
-            } else {
-                // transposed: the block's rows walk 16 columns at a time into
-                // an LDS tile; lane (column tq, row quarter qq) then sums 16
-                // rows and the four quarters are combined across lanes
-                const int tq = lane & 15, qq = lane >> 4;
-                for (int t0 = 0; t0 < ncol; t0 += 16) {
-                    const int tn = min(16, ncol - t0);
-                    for (int tt = 0; tt < tn; ++tt) {
-                        const int t = t0 + tt;
-                        if (t > 0) gen_2step(cf + 3 * t, x * x, p0, p1, ex, sc);
-                        gt[tt * kGT + lane] = lane < ngen ? (T)(p1 * sc) : (T)0;
-                    }
-                    __syncthreads();
-                    T a[RC];
-#pragma unroll
-                    for (int r = 0; r < RC; ++r) a[r] = (T)0;
-                    if (tq < tn) {
-                        const int i1 = min(ngen, 16 * qq + 16);
-                        for (int i = 16 * qq; i < i1; ++i) {
-                            const T g = gt[tq * kGT + i];
-#pragma unroll
-                            for (int r = 0; r < RC; ++r) a[r] += g * xin[i * RC + r];
-                        }
-                    }
-#pragma unroll
-                    for (int r = 0; r < RC; ++r) {
-                        a[r] += __shfl_xor(a[r], 16);
-                        a[r] += __shfl_xor(a[r], 32);
-                    }
-                    if (qq == 0 && tq < tn)
-#pragma unroll
-                        for (int r = 0; r < RC; ++r) acc[(sb.map_off + t0 + tq) * RC + r] += a[r];
-                    __syncthreads();
-                }
-            }
-            continue;
-        }
         const T *src;
         int64_t sstride;
         if (sb.src == kIn) {
@@ -438,18 +354,14 @@ __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, co
                                                   int op_begin, int n_ops, const float *__restrict__ in, int64_t in_stride,
                                                   float *__restrict__ out, int64_t out_stride,
                                                   float *__restrict__ scrA, float *__restrict__ scrB, int rc,
-                                                  int max_out, int max_in, const double *__restrict__ xh,
-                                                  const double *__restrict__ coef, const double *__restrict__ ck,
-                                                  const int32_t *__restrict__ ckexp) {
+                                                  int max_out, int max_in) {
     constexpr int NCB = RCW / 16;
     constexpr int NP = TERMS == 3 ? 2 : 3;  // BF16 parts per value
     extern __shared__ unsigned char smem_raw[];
-    double *gco = reinterpret_cast<double *>(smem_raw);
-    float *acc = reinterpret_cast<float *>(gco + kGco);
+    float *acc = reinterpret_cast<float *>(smem_raw);
     const int mi16 = (max_in + 15) & ~15;
     short *xp16 = reinterpret_cast<short *>(acc + (size_t)max_out * RCW);  // NP x [mi16 / 4][RCW][4]
     const size_t pstride = (size_t)mi16 * RCW;
-    float *gt = reinterpret_cast<float *>(xp16 + NP * pstride);            // [64][kGT]
     const int oi = xcd_item(n_ops, kXc);
     if (oi >= n_ops) return;
     const Op op = ops[op_begin + oi];
@@ -458,10 +370,9 @@ __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, co
     for (int e = tid; e < n_out * RCW; e += 256) acc[e] = 0.f;
     for (int s = 0; s < op.nsub; ++s) {
         const SubOp sb = subs[op.sub0 + s];
-        const bool gen = sb.src == kGen;
         const float *src;
         int64_t sstride;
-        if (sb.src == kIn || gen) {
+        if (sb.src == kIn) {
             src = in;
             sstride = in_stride;
         } else {
@@ -475,35 +386,13 @@ __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, co
             const int nin16 = (nin + 15) & ~15;
             for (int e = tid; e < nin16 * RCW; e += 256) {
                 const int j = e / RCW, c = e - j * RCW;
-                const int64_t row = gen ? (int64_t)sb.in_off + j : (int64_t)inr[j < nin ? j : 0];
+                const int64_t row = inr[j < nin ? j : 0];
                 const float v = (j < nin && c < rc) ? src[row * sstride + c] : 0.f;
                 short pt[NP];
                 split_bf16<NP>(v, pt);
                 const int o = ((j >> 2) * RCW + c) * 4 + (j & 3);
 #pragma unroll
                 for (int k = 0; k < NP; ++k) xp16[k * pstride + o] = pt[k];
-            }
-            if (gen) {
-                stage_coef(coef + 3 * (int64_t)sb.n_dir, sb.pad == 0 ? nin : nmap, tid, 256, gco);
-                __syncthreads();
-            }
-            const bool gfwd = gen && sb.pad == 0;
-            if (gen && !gfwd) {
-                const int ngen = nin, ncol = nmap;
-                const int i = lane, c0 = 16 * wave;
-                if (i < ngen && c0 < ncol) {
-                    const int64_t si = sb.mat_off + (int64_t)wave * ngen + i;
-                    double p0 = ck[2 * si], p1 = ck[2 * si + 1];
-                    int ex = ckexp[si];
-                    double sc = scale_of(ex);
-                    const double x = xh[sb.dir_off + i];
-                    const double *cf = gco;
-                    const int c1 = min(ncol, c0 + 16);
-                    for (int t = c0; t < c1; ++t) {
-                        if (t > c0) gen_2step(cf + 3 * t, x * x, p0, p1, ex, sc);
-                        gt[t * kGT + i] = (float)(p1 * sc);
-                    }
-                }
             }
             __syncthreads();
             const int32_t *map = idx + sb.map_off;
@@ -513,38 +402,7 @@ __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, co
             for (int t = wave; t < ntile; t += 4) {
                 const int q = t * 16 + cl;
                 float av[16];  // A values: k-step st, slot i -> input 16 st + 4 jl + i
-                if (gfwd) {
-                    double p0 = 0.0, p1 = 0.0, x = 0.0, sc = 0.0;
-                    int ex = 0;
-                    if (q < nmap) {
-                        p0 = ck[2 * (sb.mat_off + q)];
-                        p1 = ck[2 * (sb.mat_off + q) + 1];
-                        ex = ckexp[sb.mat_off + q];
-                        sc = scale_of(ex);
-                        x = xh[sb.dir_off + q];
-                    }
-                    const double *cf = gco;
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) av[v] = 0.f;
-#pragma unroll
-                    for (int st = 0; st < 4; ++st)
-#pragma unroll
-                        for (int u = 0; u < 16; ++u) {
-                            const int j = 16 * st + u;
-                            if (j < nin) {
-                                if (j > 0) gen_2step(cf + 3 * j, x * x, p0, p1, ex, sc);
-                                if ((u >> 2) == jl) av[4 * st + (u & 3)] = (float)(p1 * sc);
-                            }
-                        }
-                } else if (gen) {
-#pragma unroll
-                    for (int st = 0; st < 4; ++st)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int j = 16 * st + 4 * jl + i;
-                            av[4 * st + i] = (q < nmap && j < nin) ? gt[q * kGT + j] : 0.f;
-                        }
-                } else {
+                {
 #pragma unroll
                     for (int st = 0; st < 4; ++st)
 #pragma unroll
@@ -589,7 +447,7 @@ __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, co
                 for (int i = 0; i < 4; ++i) {
                     const int qq = t * 16 + 4 * jl + i;
                     if (qq < nmap) {
-                        float *ar = acc + (gen ? sb.map_off + qq : map[qq]) * RCW + cl;
+                        float *ar = acc + map[qq] * RCW + cl;
 #pragma unroll
                         for (int cb = 0; cb < NCB; ++cb) ar[cb * 16] += D[cb][i];
                     }
@@ -597,7 +455,7 @@ __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, co
             }
         }
         __syncthreads();
-        if (!gen && sb.n_dir > 0) {
+        if (sb.n_dir > 0) {
             const int32_t *dir = idx + sb.dir_off;
             for (int e = tid; e < sb.n_dir * RCW; e += 256) {
                 const int d = e / RCW, c = e - d * RCW;
@@ -942,18 +800,11 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
             if (oe <= ob) continue;
             const Stage &sg = pd.stages[st];
             const int mo = std::max(1, (int)sg.max_out), mi = std::max(4, ((int)sg.max_in + 3) & ~3);
-            // LDS tile of transposed generated blocks: 64 x 64 (matrix cores)
-            // or 16 x 64 (VALU)
-            const size_t gtile = (sg.gen & 2) ? (size_t)((mfma || bf16) ? 64 : 16) * kGT : 0;
-            size_t lds = sizeof(T) * ((size_t)(mo + mi) * RC + gtile);
-            if (bf16)  // FP32 accumulators, split BF16 inputs, FP32 tile
-                lds = 4 * (size_t)mo * RC + (p.bf16_terms == 3 ? 2 : 3) * 2 * (size_t)((mi + 15) & ~15) * RC +
-                      4 * gtile;
-            lds += 8 * kGco;  // coefficients of a generated sub-op
+            size_t lds = sizeof(T) * (size_t)(mo + mi) * RC;  // outputs + gathered inputs
+            if (bf16)  // FP32 accumulators and the split BF16 inputs
+                lds = 4 * (size_t)mo * RC + (p.bf16_terms == 3 ? 2 : 3) * 2 * (size_t)((mi + 15) & ~15) * RC;
             if (mfma) lds = (size_t)mo * 16 * 8;  // outputs x 16 columns
             if (lds > 160 * 1024) return hipErrorInvalidValue;
-            const double *ck = pd.d_ck;
-            const int32_t *cke = pd.d_ckexp;
             const bool last = st + 1 == pd.stage_task_first.size();
             static const char *const kLab[3][9] = {
                 {"k_ops[L0]", "k_ops[L1]", "k_ops[L2]", "k_ops[L3]", "k_ops[L4]", "k_ops[L5]", "k_ops[L6]",
@@ -970,8 +821,7 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
 #define SHT_BF16_LAUNCH(W, TM)                                                                                    \
     hipLaunchKernelGGL((k_ops_bf16<W, TM>), dim3(xcd_grid(oe - ob)), dim3(256), lds, s, pd.d_ops, pd.d_subs, pd.d_idx, vf, \
                        ob, oe - ob,                                                                                   \
-                       inf, (int64_t)R, outf, (int64_t)R, (float *)scrA, (float *)scrB, rc, mo, mi, p.d_xh, p.d_coef2, \
-                       ck, cke)
+                       inf, (int64_t)R, outf, (int64_t)R, (float *)scrA, (float *)scrB, rc, mo, mi)
                 if (p.bf16_terms == 3) {
                     if (RC == 64)
                         SHT_BF16_LAUNCH(64, 3);
@@ -991,7 +841,6 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
                 continue;
             }
             if (mfma) {
-                if (sg.gen) return hipErrorInvalidValue;  // regenerated blocks run in their own kernels here
                 const double *vd = (const double *)vals;
                 const double *ind = (const double *)(in + c0);
                 double *outd = (double *)(out + c0);
@@ -1005,7 +854,7 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
 #define SHT_OPS_LAUNCH(RCV)                                                                                      \
     hipLaunchKernelGGL((k_ops<T, RCV>), dim3(xcd_grid(oe - ob)), dim3(64), lds, s, pd.d_ops, pd.d_subs, pd.d_idx, vals, \
                        ob, oe - ob,                                                                                  \
-                       (const T *)(in + c0), (int64_t)R, out + c0, (int64_t)R, scrA, scrB, rc, mo, mi, p.d_xh, p.d_coef2, ck, cke)
+                       (const T *)(in + c0), (int64_t)R, out + c0, (int64_t)R, scrA, scrB, rc, mo, mi)
             if (RC == 4)
                 SHT_OPS_LAUNCH(4);
             else if (RC == 8)

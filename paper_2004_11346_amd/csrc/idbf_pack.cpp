@@ -402,34 +402,8 @@ struct Emitter {
     }
 };
 
-// Generated sub-op over task rows [r0, r0 + ng) and columns [c0, c0 + nc) of
-// the regenerated block b of task (a, par); recurrence states every 16 columns.
-void emit_gen(const LegendreTables &lt, int a, int par, const Block &b, int mode, int r0, int ng, int c0, int nc,
-              int64_t in_row, int64_t out_pos, Program &p, std::vector<SubOp> &out) {
-    SubOp so{};
-    so.src = kGen;
-    so.pad = mode;
-    so.n_in = mode == 0 ? nc : ng;
-    so.n_map = mode == 0 ? ng : nc;
-    so.in_off = (int32_t)in_row;
-    so.map_off = (int32_t)out_pos;
-    so.dir_off = r0;
-    so.n_dir = (int32_t)(tri_offset(lt.N, a) + par + 2 * (int64_t)c0);
-    so.mat_off = (int64_t)p.ckexp.size();
-    for (int s = 0; s * 16 < nc; ++s)
-        for (int i = 0; i < ng; ++i) {
-            const RecState st = gen_state(lt, a, par, b, r0 + i, c0 + 16 * s);
-            p.ck.push_back(st.pm2);  // same-parity pair (k - 2, k)
-            p.ck.push_back(st.p1);
-            p.ckexp.push_back(st.e);
-        }
-    p.max_n_in = std::max(p.max_n_in, (int)so.n_in);
-    out.push_back(so);
-}
-
 void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t> &out_off,
-              const std::vector<int64_t> &in_off, bool fwd, bool gen_kernel, const LegendreTables &lt,
-              int64_t value_hint, Program &p) {
+              const std::vector<int64_t> &in_off, bool fwd, int64_t value_hint, Program &p) {
     const int64_t in_rows = in_off[ntask];
     int D = 0;  // number of work stages
     for (auto &b : bps) D = std::max(D, (int)b.levels.size());
@@ -443,8 +417,6 @@ void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t>
     p.subs.clear();
     p.idx.clear();
     p.vals.clear();
-    p.ck.clear();
-    p.ckexp.clear();
     p.vals.reserve((size_t)value_hint);
     {
         // index stream: inputs, maps and identity pairs of every sub-op; final
@@ -572,32 +544,13 @@ void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t>
                     srcinfo(bi, ls.src_level, buf, base);
                     em.emit(ls, sel, dsel, buf, base, T0, subs);
                 }
-                if (b.gen && !gen_kernel) {
-                    const Block &g = *b.gen;
-                    const int a = t / 2, par = t % 2;
-                    const int64_t lo = T0 - r0, hi = T1 - r0;  // tile in task-local rows / columns
-                    if (fwd) {
-                        const int ra = (int)std::max<int64_t>(g.r0, lo), rb = (int)std::min<int64_t>(g.r1, hi);
-                        for (int cs = g.c0; ra < rb && cs < g.c1; cs += kMaxIn)
-                            emit_gen(lt, a, par, g, 0, ra, rb - ra, cs, std::min(kMaxIn, g.c1 - cs),
-                                     in_off[t] + cs, r0 + ra - T0, p, subs);
-                    } else {
-                        const int ca = (int)std::max<int64_t>(g.c0, lo), cb = (int)std::min<int64_t>(g.c1, hi);
-                        for (int rs = g.r0; ca < cb && rs < g.r1; rs += kMaxIn)
-                            emit_gen(lt, a, par, g, 1, rs, std::min(kMaxIn, g.r1 - rs), ca, cb - ca,
-                                     in_off[t] + rs, r0 + ca - T0, p, subs);
-                    }
-                }
             }
             op.nsub = (int32_t)subs.size();
             p.subs.insert(p.subs.end(), subs.begin(), subs.end());
             p.ops.push_back(op);
             p.op_task.push_back(t);
             fst.max_out = std::max(fst.max_out, op.n_out);
-            for (auto &so : subs) {
-                fst.max_in = std::max(fst.max_in, so.n_in);
-                if (so.src == kGen) fst.gen |= so.pad == 0 ? 1 : 2;
-            }
+            for (auto &so : subs) fst.max_in = std::max(fst.max_in, so.n_in);
         }
     }
     fst.op_end = (int32_t)p.ops.size();
@@ -695,7 +648,7 @@ void build_gen_adjoint(const HostPlanData &hp, GenAdjoint &ga) {
 
 }  // namespace
 
-void pack_programs(const HostPlanData &hp, PackedPlan &pk, bool adj_gen_kernel) {
+void pack_programs(const HostPlanData &hp, PackedPlan &pk) {
     const int N = hp.N;
     const int ntask = 4 * N;
     Offsets of;
@@ -731,19 +684,17 @@ void pack_programs(const HostPlanData &hp, PackedPlan &pk, bool adj_gen_kernel) 
             }
         auto t1 = T();
         if (fwd)
-            schedule(bps, ntask, of.y, of.x, true, pk.gen_kernels, hp.lt, hint, pk.fwd);
+            schedule(bps, ntask, of.y, of.x, true, hint, pk.fwd);
         else
-            schedule(bps, ntask, of.x, of.y, false, pk.adj_gen_kernel, hp.lt, hint, pk.adj);
+            schedule(bps, ntask, of.x, of.y, false, hint, pk.adj);
         if (verbose)
             std::fprintf(stderr, "[sht] %s chains %.2fs schedule %.2fs\n", fwd ? "fwd" : "adj", D(t0, t1), D(t1, T()));
     };
-    pk.gen_kernels = true;
-    pk.adj_gen_kernel = adj_gen_kernel;
     std::thread th([&] { pack_dir(false); });
     pack_dir(true);
     th.join();
     std::thread tg([&] {
-        if (adj_gen_kernel) build_gen_adjoint(hp, pk.gen_adj);
+        build_gen_adjoint(hp, pk.gen_adj);
     });
     build_gen_forward(hp, pk.gen_fwd);
     tg.join();
@@ -823,8 +774,7 @@ void host_run_gen_adjoint(const GenAdjoint &ga, int N, int t_lo, int t_hi, int R
     }
 }
 
-void host_run_program(const Program &p, int R, const double *in, double *out, const double *xh,
-                      const double *coef2) {
+void host_run_program(const Program &p, int R, const double *in, double *out) {
     std::vector<double> scr[2];
     scr[0].assign((size_t)std::max<int64_t>(1, p.scr_rows) * R, 0.0);
     scr[1].assign((size_t)std::max<int64_t>(1, p.scr_rows) * R, 0.0);
@@ -835,34 +785,6 @@ void host_run_program(const Program &p, int R, const double *in, double *out, co
             acc.assign((size_t)op.n_out * R, 0.0);
             for (int s = 0; s < op.nsub; ++s) {
                 const SubOp &sb = p.subs[op.sub0 + s];
-                if (sb.src == kGen) {
-                    // regenerate the block row by row from its first state
-                    const int ngen = sb.pad == 0 ? sb.n_map : sb.n_in, ncol = sb.pad == 0 ? sb.n_in : sb.n_map;
-                    for (int i = 0; i < ngen; ++i) {
-                        double p0 = p.ck[2 * (sb.mat_off + i)], p1 = p.ck[2 * (sb.mat_off + i) + 1];
-                        int e = p.ckexp[sb.mat_off + i];
-                        const double x = xh[sb.dir_off + i], x2 = x * x;
-                        for (int t = 0; t < ncol; ++t) {
-                            if (t > 0) {
-                                const double *c = coef2 + 3 * ((int64_t)sb.n_dir + 2 * t);
-                                const double p2 = (c[0] * x2 + c[1]) * p1 + c[2] * p0;
-                                p0 = p1;
-                                p1 = p2;
-                                if (std::fabs(p1) > 0x1p200) {
-                                    p0 *= 0x1p-200;
-                                    p1 *= 0x1p-200;
-                                    e += 200;
-                                }
-                            }
-                            const double v = e < -1074 ? 0.0 : p1 * std::ldexp(1.0, e);
-                            const int jin = sb.pad == 0 ? t : i, qout = sb.pad == 0 ? i : t;
-                            const double *xr = in + (size_t)(sb.in_off + jin) * R;
-                            double *a = &acc[(size_t)(sb.map_off + qout) * R];
-                            for (int r = 0; r < R; ++r) a[r] += v * xr[r];
-                        }
-                    }
-                    continue;
-                }
                 const double *src = sb.src == kIn ? in : sb.src == kScrA ? scr[0].data() : scr[1].data();
                 const int32_t *inr = &p.idx[sb.in_off];
                 const int32_t *map = &p.idx[sb.map_off];

@@ -51,18 +51,13 @@ struct GenAdjoint {
 struct PackedPlan {
     Program fwd, adj;  // each with its own output-major value stream
     std::vector<int64_t> x_off, y_off;  // panel row offsets per task (+ total)
-    // regenerated blocks applied by their own kernels after the op programs
-    // (the programs then leave them out)
+    // regenerated blocks, applied by their own kernels after the op programs
+    // (the programs leave them out)
     GenForward gen_fwd;
     GenAdjoint gen_adj;
-    bool gen_kernels = false;      // forward: regenerated blocks by their own kernel
-    bool adj_gen_kernel = false;   // transposed: same (else inside the transposed program)
 };
 
-// adj_gen_kernel: the transposed regenerated blocks run on the matrix cores by
-// their own kernel (many right-hand sides); otherwise they stay sub-ops of the
-// transposed program (few right-hand sides, VALU).
-void pack_programs(const HostPlanData &hp, PackedPlan &pk, bool adj_gen_kernel = true);
+void pack_programs(const HostPlanData &hp, PackedPlan &pk);
 
 // Host application of the regenerated transposed blocks of tasks t_lo..t_hi
 // (verification): out (X panels) += blocks^T x in (Y panels).

@@ -35,13 +35,6 @@ hipError_t upload_dir(Program &p, int ntask, int dtype, DeviceProgramDir &d) {
     if ((e = up(p.ops, &d.d_ops)) != hipSuccess) return e;
     if ((e = up(p.subs, &d.d_subs)) != hipSuccess) return e;
     if ((e = up(p.idx, &d.d_idx)) != hipSuccess) return e;
-    if ((e = up(p.ck, &d.d_ck)) != hipSuccess) return e;
-    if ((e = up(p.ckexp, &d.d_ckexp)) != hipSuccess) return e;
-    d.gen = !p.ckexp.empty();
-    p.ck.clear();
-    p.ck.shrink_to_fit();
-    p.ckexp.clear();
-    p.ckexp.shrink_to_fit();
     d.stages = p.stages;
     d.stage_task_first.clear();
     for (const Stage &st : p.stages) {
@@ -68,8 +61,7 @@ int fail(hipError_t e, const char *what) {
 
 void DeviceProgram::release() {
     for (void *p : {d_X, d_Y, d_scrA, d_scrB, (void *)d_x_off, fwd.d_vals, (void *)fwd.d_ops, (void *)fwd.d_subs,
-                    (void *)fwd.d_idx, (void *)fwd.d_ck, (void *)fwd.d_ckexp, adj.d_vals, (void *)adj.d_ops,
-                    (void *)adj.d_subs, (void *)adj.d_idx, (void *)adj.d_ck, (void *)adj.d_ckexp})
+                    (void *)fwd.d_idx, adj.d_vals, (void *)adj.d_ops, (void *)adj.d_subs, (void *)adj.d_idx})
         if (p) (void)hipFree(p);
     for (Gen *g : {&gen, &gena}) {
         for (void *q : {g->d_items, g->d_segs, (void *)g->d_ck, (void *)g->d_ckexp})
@@ -89,8 +81,7 @@ int build_program(int N, int batch, const LegendreTables &lt, const sht_plan_opt
     int rc = build_all(N, opts, hp);
     if (rc) return rc;
     (void)batch;
-    // regenerated blocks of both directions run in their own kernels
-    pack_programs(hp, out.packed, true);
+    pack_programs(hp, out.packed);
     out.N = N;
     out.f32_mode = opts.f32_mode;
     out.stats = hp.stats;
@@ -102,8 +93,8 @@ int build_program(int N, int batch, const LegendreTables &lt, const sht_plan_opt
                         (int64_t)(out.packed.fwd.subs.size() + out.packed.adj.subs.size()) * sizeof(SubOp);
     os << base << ",\"fwd_values\":" << out.packed.fwd.vals.size() << ",\"adj_values\":" << out.packed.adj.vals.size()
        << ",\"index_bytes\":" << idx_bytes << ",\"ckpt_states\":"
-       << (out.packed.fwd.ckexp.size() + out.packed.adj.ckexp.size()) << ",\"ckpt_bytes\":"
-       << 20 * (int64_t)(out.packed.fwd.ckexp.size() + out.packed.adj.ckexp.size())
+       << (out.packed.gen_fwd.ckexp.size() + out.packed.gen_adj.ckexp.size()) << ",\"ckpt_bytes\":"
+       << 20 * (int64_t)(out.packed.gen_fwd.ckexp.size() + out.packed.gen_adj.ckexp.size())
        << ",\"fwd_stages\":" << out.packed.fwd.stages.size() << ",\"fwd_work_stages\":"
        << out.packed.fwd.n_work_stages << ",\"adj_stages\":" << out.packed.adj.stages.size()
        << ",\"fwd_ops\":" << out.packed.fwd.ops.size() << ",\"scratch_rows\":"
@@ -114,8 +105,8 @@ int build_program(int N, int batch, const LegendreTables &lt, const sht_plan_opt
                             (int64_t)pk.fwd.subs.size() * sizeof(SubOp) +
                             (int64_t)pk.gen_fwd.items.size() * sizeof(GenForward::Item) +
                             (int64_t)pk.gen_fwd.segs.size() * sizeof(GenForward::Seg);
-    const int64_t fwd_states = (int64_t)pk.fwd.ckexp.size() + (int64_t)pk.gen_fwd.ckexp.size();
-    const int64_t adj_states = (int64_t)pk.adj.ckexp.size() + (int64_t)pk.gen_adj.ckexp.size();
+    const int64_t fwd_states = (int64_t)pk.gen_fwd.ckexp.size();
+    const int64_t adj_states = (int64_t)pk.gen_adj.ckexp.size();
     os << ",\"fwd_index_bytes\":" << fwd_idx << ",\"fwd_state_bytes\":" << 20 * fwd_states
        << ",\"adj_state_bytes\":" << 20 * adj_states << ",\"gen_fwd_items\":" << pk.gen_fwd.items.size()
        << ",\"gen_adj_items\":" << pk.gen_adj.items.size() << "}";
@@ -152,7 +143,7 @@ int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, co
     d.d_coef2 = d_coef2;
     if ((e = upload_dir(hp.packed.fwd, ntask, dtype, d.fwd)) != hipSuccess) return fail(e, "upload program");
     if ((e = upload_dir(hp.packed.adj, ntask, dtype, d.adj)) != hipSuccess) return fail(e, "upload program");
-    if (pk.gen_kernels) {
+    {
         GenForward &gf = pk.gen_fwd;
         d.gen.n_items = (int)gf.items.size();
         d.gen.task_first_h = gf.task_first;

@@ -13,10 +13,6 @@
 // their transposes, the middle butterfly couplings, trimmed dense blocks and
 // low-rank factors all take this form.
 //
-// Generated sub-ops (src == kGen) stand for a dense block whose entries are
-// not stored: they are regenerated by the three-term recurrence in the degree
-// from recurrence states stored every 16 columns (see SubOp).
-//
 // Non-final ops write their rows to a scratch buffer (two buffers alternate
 // between stages).  Final ops are output tiles: every row of every task's
 // output panel belongs to exactly one final op, which gathers all block
@@ -30,7 +26,7 @@ namespace sht {
 namespace idbf {
 
 // source / destination buffers
-enum Buf : int32_t { kIn = 0, kScrA = 1, kScrB = 2, kOut = 3, kGen = 4 };
+enum Buf : int32_t { kIn = 0, kScrA = 1, kScrB = 2, kOut = 3 };
 
 struct SubOp {
     int64_t mat_off;  // value offset of the output-major matrix (n_in x n_map)
@@ -43,21 +39,6 @@ struct SubOp {
     int32_t dir_off;  // idx offset: n_dir (src row, out pos) pairs
     int32_t pad;
 };
-// A generated sub-op (src == kGen) covers task rows [row0, row0 + ngen) and
-// task columns [col0, col0 + ncol) of a dense block; ngen, ncol <= 64.  Its
-// entries are P(r, c) = Pbar_k^a(xh[r]), k = a + parity + 2 c.  Fields:
-//   pad      mode: 0 = forward (outputs = rows, inputs = columns),
-//                  1 = transposed (outputs = columns, inputs = rows);
-//   n_in, n_map   inputs / outputs (ngen and ncol in the order of the mode);
-//   in_off   first input row of the input panel (inputs are contiguous);
-//   map_off  first output position in the op (outputs are contiguous);
-//   dir_off  row0 (node index into xh);
-//   n_dir    index of degree k(col0) in the recurrence tables of the order;
-//   mat_off  first recurrence state: state (row0 + i, col0 + 16 s) is
-//            ck[mat_off + s * ngen + i] = (entries of degrees k - 2 and k)
-//            with exponent ckexp[...].
-// Column t follows from the two before it by the composed two-step
-// recurrence with coefficients coef2[n_dir + 2 t] (same parity).
 
 struct Op {
     int32_t n_out;
@@ -70,7 +51,6 @@ struct Op {
 struct Stage {
     int32_t op_begin, op_end;  // range in Program::ops
     int32_t max_out, max_in;   // largest n_out / n_in of the stage (LDS sizing)
-    int32_t gen;               // generated sub-ops: bit 0 forward mode, bit 1 transposed mode
 };
 
 struct Program {
@@ -79,8 +59,6 @@ struct Program {
     std::vector<SubOp> subs;
     std::vector<int32_t> idx;
     std::vector<double> vals;      // value stream of this program
-    std::vector<double> ck;        // recurrence states (p0, p1) of generated sub-ops
-    std::vector<int32_t> ckexp;    // their binary exponents
     std::vector<Stage> stages;
     int n_work_stages = 0;         // stages[0 .. n_work_stages) write scratch
     int64_t scr_rows = 0;          // rows of each scratch buffer
@@ -89,10 +67,9 @@ struct Program {
 };
 
 // Host execution of a program (verification): in [in_rows][R], out
-// [out_rows][R] (overwritten).  xh, coef2: half-grid nodes and the composed
-// two-step recurrence coefficients (used by generated sub-ops).
-void host_run_program(const Program &p, int R, const double *in, double *out, const double *xh,
-                      const double *coef2);
+// [out_rows][R] (overwritten).  Regenerated dense blocks are not part of a
+// program; they run separately (see the regenerated-block executors).
+void host_run_program(const Program &p, int R, const double *in, double *out);
 
 }  // namespace idbf
 }  // namespace sht
