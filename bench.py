@@ -334,6 +334,45 @@ def uneven(args):
                                  "fields": sum(fields)}, "results": out}), flush=True)
 
 
+def fp32_legs(S, inputs, timer, N, batch, beta_np, no_check):
+    """FP32 plans at the same workload: plain form, fast form on the VALU and
+    fast form on the BF16 matrix cores (split-BF16, three and six products),
+    with the ALT error against the FP64 oracle at sampled orders (field 0)."""
+    import numpy as np
+    import torch
+
+    from paper_2004_11346_amd import lib as L
+    M = 4 * N - 1
+    beta32 = torch.from_numpy(beta_np.astype(np.complex64)).cuda()
+    absm = [0, 1, N // 2, N, 3 * N // 2, 2 * N - 1] + list(inputs.sample_indices(2 * N, 10, 11))
+    ref = None
+    if not no_check:
+        import oracle
+        ref = oracle.alt_forward_orders(N, beta_np[0].astype(np.complex64).astype(np.complex128), absm)
+    legs = {}
+    for name, meth, mode in (("dense_f32", "dense", L.SHT_F32_VALU), ("idbf_f32", "idbf", L.SHT_F32_VALU),
+                             ("idbf_split_bf16x3", "idbf", L.SHT_F32_SPLIT_BF16),
+                             ("idbf_split_bf16x6", "idbf", L.SHT_F32_SPLIT_BF16_6)):
+        kw = {} if meth == "dense" else {"f32_mode": mode}
+        p = S.Plan(N, batch, dtype=torch.complex64, method=meth, **kw)
+        g = p.empty_grid()
+        ob = p.empty_coefs()
+        taf = timer.time(lambda: p.alt(0, 2 * N - 1, "fwd", beta32, g), reps=3)
+        tai = timer.time(lambda: p.alt(0, 2 * N - 1, "inv", g, ob), reps=3)
+        leg = {"batch": batch, "alt_fwd_ms": taf * 1e3, "alt_inv_ms": tai * 1e3,
+               "alt_fwd_gcoef_s": batch * 4 * N * N / taf / 1e9, "alt_inv_gcoef_s": batch * 4 * N * N / tai / 1e9}
+        if ref is not None:
+            p.alt(0, 2 * N - 1, "fwd", beta32, g)
+            gh = g[0].cpu().numpy().astype(np.complex128)
+            got = np.stack([np.stack([gh[:, a % M], gh[:, (-a) % M]]) for a in absm])
+            leg["alt_fwd_sampled_orders_rel_l2"] = rel_l2(got, ref)
+            leg["alt_fwd_sampled_orders_rel_max"] = rel_max(got, ref)
+        legs[name] = leg
+        p.close()
+        torch.cuda.empty_cache()
+    return legs
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -475,7 +514,12 @@ def main():
                 if p is not plan:
                     p.close()
         if "dense_b%d" % batch in det and "idbf_b%d" % batch in det:
-            det["idbf_speedup_alt_fwd"] = det[f"dense_b{batch}"]["alt_fwd_ms"] / det[f"idbf_b{batch}"]["alt_fwd_ms"]
+            for bb in (1, batch):
+                for d in ("fwd", "inv"):
+                    det[f"idbf_speedup_alt_{d}_b{bb}"] = (det[f"dense_b{bb}"][f"alt_{d}_ms"] /
+                                                          det[f"idbf_b{bb}"][f"alt_{d}_ms"])
+        if args.dtype == "f64" and method == "idbf":
+            det.update(fp32_legs(S, inputs, timer, N, batch, beta_np, args.no_check))
         out["details"] = det
 
     if not args.no_cpu_baseline:

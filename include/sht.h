@@ -76,9 +76,13 @@ extern "C" {
 #define SHT_ADJ 2 /* g -> beta:  beta = A_m^T g    (transpose, no weights) */
 
 /* F32 arithmetic for the IDBF block products */
-#define SHT_F32_VALU 0       /* FP32 products on the vector ALUs */
+#define SHT_F32_VALU 0       /* FP32 factors and vectors; products on the vector
+                                ALUs below 16 right-hand sides (4 batch), on
+                                the FP64 matrix cores (FP64 products and sums)
+                                from 16 */
 #define SHT_F32_SPLIT_BF16 1 /* split-BF16 three-product MFMA, FP32 accumulate
-                                (two BF16 parts per value: about 4e-6 relative) */
+                                (two BF16 parts per value: a few 1e-6 to 1e-5
+                                relative) */
 #define SHT_F32_SPLIT_BF16_6 2 /* six products of three BF16 parts per value
                                   (FP32 accuracy on the BF16 matrix cores) */
 
@@ -107,9 +111,11 @@ typedef struct sht_plan_opts {
                           (FP32 plans of the fast form) */
     int min_idbf;      /* smallest block side given an IDBF (default 4*leaf) */
     int dense_gen;     /* 1 (default): dense blocks of the fast form are not
-                          stored; the kernels regenerate their entries with the
-                          three-term recurrence from per-row checkpoints taken
-                          every 16 columns.  0: store their values. */
+                          stored; their own kernels regenerate the entries with
+                          the three-term recurrence from per-row checkpoints
+                          (at the block's first column per 64-row tile, and
+                          per 64-column output tile for the transpose).
+                          0: store their values. */
     int m_lo, m_hi;    /* orders |m| in [m_lo, m_hi] covered by the fast form's
                           factors (default 0 and -1 = all).  A plan restricted
                           to a range serves sht_alt_apply inside it (one GPU's

@@ -210,12 +210,15 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 // (n_out x 16) through the sub-op's output map; the identity part is added
 // there too and the outputs are stored once.  The column blocks of an op are
 // neighbouring work items (same XCD, about the same time), so its values come
-// from HBM about once per pass and from L2 for the other blocks.
+// from HBM about once per pass and from L2 for the other blocks.  T is the
+// storage type of values and vectors (FP32 plans keep FP32 factors and
+// panels); products and sums are FP64.
+template <typename T>
 __global__ __launch_bounds__(64) void k_ops_mfma(const Op *__restrict__ ops, const SubOp *__restrict__ subs,
-                                                   const int32_t *__restrict__ idx, const double *__restrict__ vals,
-                                                   int op_begin, int n_items, int ncb, const double *__restrict__ in,
-                                                   int64_t in_stride, double *__restrict__ out, int64_t out_stride,
-                                                   double *__restrict__ scrA, double *__restrict__ scrB,
+                                                   const int32_t *__restrict__ idx, const T *__restrict__ vals,
+                                                   int op_begin, int n_items, int ncb, const T *__restrict__ in,
+                                                   int64_t in_stride, T *__restrict__ out, int64_t out_stride,
+                                                   T *__restrict__ scrA, T *__restrict__ scrB,
                                                    int64_t scr_stride, int rc) {
     extern __shared__ unsigned char smem_raw[];
     double *acc = reinterpret_cast<double *>(smem_raw);
@@ -231,7 +234,7 @@ __global__ __launch_bounds__(64) void k_ops_mfma(const Op *__restrict__ ops, con
     __syncthreads();
     for (int s = 0; s < op.nsub; ++s) {
         const SubOp sb = subs[op.sub0 + s];
-        const double *src;
+        const T *src;
         int64_t sstride;
         if (sb.src == kIn) {
             src = in;
@@ -252,9 +255,9 @@ __global__ __launch_bounds__(64) void k_ops_mfma(const Op *__restrict__ ops, con
             double B[16];
 #pragma unroll
             for (int st = 0; st < 16; ++st)
-                B[st] = (rows[st] >= 0 && cok) ? src[(int64_t)rows[st] * sstride + col] : 0.0;
+                B[st] = (rows[st] >= 0 && cok) ? (double)src[(int64_t)rows[st] * sstride + col] : 0.0;
             const int32_t *map = idx + sb.map_off;
-            const double *mv = vals + sb.mat_off;
+            const T *mv = vals + sb.mat_off;
             const int ntile = (nmap + 15) >> 4;
             for (int t = 0; t < ntile; ++t) {
                 const int q = 16 * t + cl;
@@ -263,8 +266,8 @@ __global__ __launch_bounds__(64) void k_ops_mfma(const Op *__restrict__ ops, con
                 double A[16];
 #pragma unroll
                 for (int st = 0; st < 16; ++st) {
-                    const double *mg = mv + (int64_t)(4 * st) * nmap;
-                    A[st] = (q < nmap && 4 * st + jl < nin) ? mg[aoff] : 0.0;
+                    const T *mg = mv + (int64_t)(4 * st) * nmap;
+                    A[st] = (q < nmap && 4 * st + jl < nin) ? (double)mg[aoff] : 0.0;
                 }
                 int dst[4];
 #pragma unroll
@@ -297,7 +300,7 @@ __global__ __launch_bounds__(64) void k_ops_mfma(const Op *__restrict__ ops, con
                 }
                 double v[8];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) v[k] = (sr[k] >= 0 && cok) ? src[(int64_t)sr[k] * sstride + col] : 0.0;
+                for (int k = 0; k < 8; ++k) v[k] = (sr[k] >= 0 && cok) ? (double)src[(int64_t)sr[k] * sstride + col] : 0.0;
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
                     if (dr[k] >= 0) acc[dr[k] * 16 + cl] += v[k];
@@ -307,10 +310,10 @@ __global__ __launch_bounds__(64) void k_ops_mfma(const Op *__restrict__ ops, con
     }
     if (!cok) return;
     if (op.dst == kOut) {
-        for (int i = jl; i < n_out; i += 4) out[(op.dst_row + i) * out_stride + col] = acc[i * 16 + cl];
+        for (int i = jl; i < n_out; i += 4) out[(op.dst_row + i) * out_stride + col] = (T)acc[i * 16 + cl];
     } else {
-        double *dst = op.dst == kScrA ? scrA : scrB;
-        for (int i = jl; i < n_out; i += 4) dst[(op.dst_row + i) * scr_stride + col] = acc[i * 16 + cl];
+        T *dst = op.dst == kScrA ? scrA : scrB;
+        for (int i = jl; i < n_out; i += 4) dst[(op.dst_row + i) * scr_stride + col] = (T)acc[i * 16 + cl];
     }
 }
 
@@ -547,14 +550,14 @@ __global__ __launch_bounds__(64) void k_gen_fwd(const GenItem *__restrict__ item
 // A = values[16 rows][4 columns], B = X[4 columns][16 columns].  The B
 // fragments of the next tile are loaded while the current one is generated
 // and multiplied; the recurrence coefficients are wave-uniform loads.
-template <int CBP>
+template <typename T, int CBP>
 __global__ __launch_bounds__(64) void k_gen_fwd_mfma(const GenItem *__restrict__ items, int n_items, int xc, int item0,
                                                      const GenSeg *__restrict__ segs, const double *__restrict__ ck,
                                                      const int32_t *__restrict__ ckexp,
                                                      const double *__restrict__ xh, const double *__restrict__ coef2,
                                                      int N, const int64_t *__restrict__ x_off,
-                                                     const double *__restrict__ X, int64_t R, int col0,
-                                                     double *__restrict__ Y) {
+                                                     const T *__restrict__ X, int64_t R, int col0,
+                                                     T *__restrict__ Y) {
     constexpr int PAD = 9;
     __shared__ double tile[64 * PAD];
     __shared__ double s_c[8 * 3];
@@ -566,7 +569,7 @@ __global__ __launch_bounds__(64) void k_gen_fwd_mfma(const GenItem *__restrict__
     const int a = it.task >> 1, par = it.task & 1;
     const double x = xh[r < N ? r : N - 1], x2 = x * x;
     const double *cfo = coef2 + 3 * (d_tri_offset2(N, a) + par);
-    const double *Xt = X + x_off[it.task] * R;
+    const T *Xt = X + x_off[it.task] * R;
     d4v D[4][CBP];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -575,16 +578,16 @@ __global__ __launch_bounds__(64) void k_gen_fwd_mfma(const GenItem *__restrict__
     for (int s = it.seg_begin; s < it.seg_end; ++s) {
         const GenSeg sg = segs[s];
         const double *cs = cfo + 6 * (int64_t)sg.c0;  // (alpha, beta, gamma) of segment column t at cs + 6 t
-        const double *Xs = Xt + (int64_t)sg.c0 * R;
+        const T *Xs = Xt + (int64_t)sg.c0 * R;
         // B fragments of the tile at t0: columns t0 + 4 h + jl, RHS col0 + 16 cb + cl
         auto load_b = [&](double (&B)[2][CBP], int t0) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const double *xg = Xs + (int64_t)(t0 + 4 * h) * R;  // wave-uniform base
+                const T *xg = Xs + (int64_t)(t0 + 4 * h) * R;  // wave-uniform base
 #pragma unroll
                 for (int cb = 0; cb < CBP; ++cb) {
                     const int t = t0 + 4 * h + jl, col = col0 + 16 * cb + cl;
-                    B[h][cb] = (t < sg.ncol && col < R) ? xg[jl * (int)R + col] : 0.0;
+                    B[h][cb] = (t < sg.ncol && col < R) ? (double)xg[jl * (int)R + col] : 0.0;
                 }
             }
         };
@@ -651,7 +654,10 @@ __global__ __launch_bounds__(64) void k_gen_fwd_mfma(const GenItem *__restrict__
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = it.row0 + 16 * t + jl + 4 * i;
-                if (row < N) Y[((int64_t)it.task * N + row) * R + col] += D[t][cb][i];
+                if (row < N) {
+                    T *y = Y + ((int64_t)it.task * N + row) * R + col;
+                    *y = (T)((double)*y + D[t][cb][i]);
+                }
             }
         }
 }
@@ -789,7 +795,7 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
     T *in = fwd ? X : Y;
     T *out = fwd ? Y : X;
     const T *vals = (const T *)pd.d_vals;
-    const bool mfma = sizeof(T) == 8 && p.RCW > 0;
+    const bool mfma = p.RCW > 0 && !p.bf16;
     const bool bf16 = sizeof(T) == 4 && p.bf16;
     const int RC = (mfma || bf16) ? p.RCW : p.RC;
     for (int c0 = 0; c0 < R; c0 += RC) {
@@ -841,14 +847,11 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
                 continue;
             }
             if (mfma) {
-                const double *vd = (const double *)vals;
-                const double *ind = (const double *)(in + c0);
-                double *outd = (double *)(out + c0);
                 const int ncb = (rc + 15) / 16;
                 const int n_items = (oe - ob) * ncb;
-                hipLaunchKernelGGL(k_ops_mfma, dim3(xcd_grid(n_items)), dim3(64), lds, s, pd.d_ops,
-                                   pd.d_subs, pd.d_idx, vd, ob, n_items, ncb, ind, (int64_t)R, outd, (int64_t)R,
-                                   (double *)scrA, (double *)scrB, (int64_t)RC, rc);
+                hipLaunchKernelGGL(k_ops_mfma<T>, dim3(xcd_grid(n_items)), dim3(64), lds, s, pd.d_ops, pd.d_subs,
+                                   pd.d_idx, vals, ob, n_items, ncb, (const T *)(in + c0), (int64_t)R, out + c0,
+                                   (int64_t)R, scrA, scrB, (int64_t)RC, rc);
                 continue;
             }
 #define SHT_OPS_LAUNCH(RCV)                                                                                      \
@@ -872,9 +875,9 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
             const GenSeg *gs = (const GenSeg *)p.gen.d_segs;
             if (mfma) {
                 for (int c0 = 0; c0 < R; c0 += 32)
-                    hipLaunchKernelGGL((k_gen_fwd_mfma<2>), dim3(xcd_grid(i1 - i0)), dim3(64), 0, s, gi, i1 - i0, kXc,
-                                       i0, gs, p.gen.d_ck, p.gen.d_ckexp, p.d_xh, p.d_coef2, N, p.d_x_off,
-                                       (const double *)X, (int64_t)R, c0, (double *)Y);
+                    hipLaunchKernelGGL((k_gen_fwd_mfma<T, 2>), dim3(xcd_grid(i1 - i0)), dim3(64), 0, s, gi, i1 - i0,
+                                       kXc, i0, gs, p.gen.d_ck, p.gen.d_ckexp, p.d_xh, p.d_coef2, N, p.d_x_off,
+                                       (const T *)X, (int64_t)R, c0, Y);
             } else {
 #define SHT_GEN_LAUNCH(RCV)                                                                                      \
     for (int c0 = 0; c0 < R; c0 += RCV)                                                                          \

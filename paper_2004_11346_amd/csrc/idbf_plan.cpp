@@ -124,14 +124,15 @@ int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, co
     d.dtype = dtype;
     const int R = 4 * batch;
     d.RC = R <= 4 ? 4 : R <= 8 ? 8 : 16;
-    // FP64 with many right-hand sides: matrix-core executor, all columns (at
-    // most 256, a multiple of 16) per pass (SHT_IDBF_RCW overrides the pass
-    // width: a multiple of 16 up to 256; 0 disables)
+    // Many right-hand sides: FP64 matrix-core executor (FP32 plans keep FP32
+    // storage), all columns (at most 256, a multiple of 16) per pass
+    // (SHT_IDBF_RCW overrides the pass width: a multiple of 16 up to 256; 0
+    // disables)
     d.RCW = 0;
-    if (dtype == SHT_F64 && R >= 16) d.RCW = std::min(256, (R + 15) & ~15);
+    if (R >= 16) d.RCW = std::min(256, (R + 15) & ~15);
     if (const char *e = std::getenv("SHT_IDBF_RCW")) {
         int v = std::atoi(e);
-        d.RCW = (dtype == SHT_F64 && v >= 16 && v <= 256 && v % 16 == 0) ? v : 0;
+        d.RCW = (v >= 16 && v <= 256 && v % 16 == 0) ? v : 0;
     }
     if (dtype == SHT_F32 && (hp.f32_mode == SHT_F32_SPLIT_BF16 || hp.f32_mode == SHT_F32_SPLIT_BF16_6)) {
         d.bf16 = true;
