@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -47,6 +48,9 @@ struct sht_plan {
     void *d_X = nullptr;         // dense path FP64 panels
     void *d_Y = nullptr;
     int64_t *d_x_off = nullptr;
+    int32_t *d_adj_items = nullptr, *d_adj_task_first = nullptr;  // dense transposed product
+    double *d_ck = nullptr;
+    int32_t *d_ckexp = nullptr;
     dev::DensePanels panels;
     // IDBF program (device)
     idbf::DeviceProgram prog;
@@ -77,6 +81,10 @@ sht_plan::~sht_plan() {
     dfree(d_X);
     dfree(d_Y);
     dfree(d_x_off);
+    dfree(d_adj_items);
+    dfree(d_adj_task_first);
+    dfree(d_ck);
+    dfree(d_ckexp);
     prog.release();
 }
 
@@ -217,7 +225,7 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
     if ((rc = upload(lt.diag_m, &p->d_dmant, "upload diag"))) return rc;
     if ((rc = upload(lt.diag_e, &p->d_dexp, "upload diag exponents"))) return rc;
     if ((rc = upload(lt.coef, &p->d_coef, "upload recurrence coefficients"))) return rc;
-    if (method == SHT_IDBF && (rc = upload(lt.coef2, &p->d_coef2, "upload recurrence coefficients"))) return rc;
+    if ((rc = upload(lt.coef2, &p->d_coef2, "upload recurrence coefficients"))) return rc;
     p->dense.N = N;
     p->dense.M = p->M;
     p->dense.xh = p->d_xh;
@@ -225,6 +233,7 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
     p->dense.dmant = p->d_dmant;
     p->dense.dexp = p->d_dexp;
     p->dense.coef = p->d_coef;
+    p->dense.coef2 = p->d_coef2;
 
     // phi DFT: radices and the e^{i pi r / M} table (long double, rounded)
     {
@@ -275,6 +284,36 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
         p->panels.Y = p->d_Y;
         p->panels.x_off = p->d_x_off;
         p->panels.max_cols = maxc;
+        // transposed product: items (task, first column) of 64-column output
+        // tiles; recurrence states of one chunk of tasks at a time (64-node
+        // padded rows per item), by default at most 64M states (1.3 GB)
+        std::vector<int32_t> items, tfirst(4 * (size_t)N + 1, 0);
+        int64_t max_task_items = 0;
+        for (int t = 0; t < 4 * N; ++t) {
+            const int c = std::max(0, half_cols(N, t / 2, t % 2));
+            for (int c0 = 0; c0 < c; c0 += 64) {
+                items.push_back(t);
+                items.push_back(c0);
+            }
+            tfirst[t + 1] = (int32_t)(items.size() / 2);
+            max_task_items = std::max<int64_t>(max_task_items, tfirst[t + 1] - tfirst[t]);
+        }
+        const int64_t NP = 64 * (int64_t)((N + 63) / 64);
+        int64_t cap = 64ll << 20;
+        if (const char *ev = std::getenv("SHT_DENSE_CKPT_STATES")) cap = std::atoll(ev);
+        cap = std::max(cap, max_task_items * NP);
+        cap = std::min(cap, std::max<int64_t>(1, (int64_t)tfirst[4 * N]) * NP);
+        cap = (cap / NP) * NP;
+        if ((rc = upload(items, &p->d_adj_items, "upload transposed items"))) return rc;
+        if ((rc = upload(tfirst, &p->d_adj_task_first, "upload transposed items"))) return rc;
+        HIP_TRY(hipMalloc(&p->d_ck, sizeof(double) * 2 * (size_t)cap), "transposed checkpoints");
+        HIP_TRY(hipMalloc(&p->d_ckexp, sizeof(int32_t) * (size_t)cap), "transposed checkpoints");
+        p->panels.adj_items = p->d_adj_items;
+        p->panels.adj_task_first = tfirst;
+        p->panels.adj_task_first_d = p->d_adj_task_first;
+        p->panels.ck = p->d_ck;
+        p->panels.ckexp = p->d_ckexp;
+        p->panels.ck_cap = cap;
     } else {
         idbf::HostProgram hp;
         int brc;

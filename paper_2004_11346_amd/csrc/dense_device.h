@@ -59,6 +59,45 @@ __device__ __forceinline__ void rescale(double &p0, double &p1, int &e, double &
     }
 }
 
+// same-parity step: with (p0, p1) = (Pbar_{k-2}, Pbar_k), the composed
+// two-step recurrence Pbar_{k+2} = (alpha x^2 + beta) Pbar_k + gamma Pbar_{k-2}
+// (c3 = (alpha, beta, gamma) of degree k + 2); rescaled like rstep
+__device__ __forceinline__ void two_step(const double *__restrict__ c3, double x2, double &p0, double &p1, int &e,
+                                         double &sc) {
+    const double p2 = fma(c3[0], x2, c3[1]) * p1 + c3[2] * p0;
+    p0 = p1;
+    p1 = p2;
+    rescale(p0, p1, e, sc);
+}
+
+// n same-parity steps without a column guard (pairs, no register copies),
+// values p * 2^e to out[j * stride], one rescale test at the end; scaling by
+// 2^-200 is exact, so the values equal those of n two_step calls
+template <int n>
+__device__ __forceinline__ void two_step_run(const double *__restrict__ c3, double x2, double &p0, double &p1, int &e,
+                                             double &sc, double *out, int stride) {
+    static_assert(n % 2 == 0, "steps come in pairs");
+    double q0 = p0, q1 = p1;
+#pragma unroll
+    for (int j = 0; j < n; j += 2) {
+        const double *c = c3 + 3 * j;
+        const double r2 = fma(c[0], x2, c[1]) * q1 + c[2] * q0;
+        out[j * stride] = r2 * sc;
+        const double r3 = fma(c[3], x2, c[4]) * r2 + c[5] * q1;
+        out[(j + 1) * stride] = r3 * sc;
+        q0 = r2;
+        q1 = r3;
+    }
+    p0 = q0;
+    p1 = q1;
+    if (fabs(p1) > kBig || fabs(p0) > kBig) {
+        p0 *= kShrink;
+        p1 *= kShrink;
+        e += 200;
+        sc = scale_of(e);
+    }
+}
+
 typedef double d4v __attribute__((ext_vector_type(4)));
 
 

@@ -107,6 +107,24 @@ int build_program(int N, int batch, const LegendreTables &lt, const sht_plan_opt
                             (int64_t)pk.gen_fwd.segs.size() * sizeof(GenForward::Seg);
     const int64_t fwd_states = (int64_t)pk.gen_fwd.ckexp.size();
     const int64_t adj_states = (int64_t)pk.gen_adj.ckexp.size();
+    // rows moved by the op kernels per right-hand side: gathered inputs (matrix
+    // and identity parts) and written outputs, per direction
+    auto rows_moved = [](const Program &pr, int64_t &in_rows, int64_t &out_rows) {
+        in_rows = 0;
+        out_rows = 0;
+        for (const Op &op : pr.ops) {
+            out_rows += op.n_out;
+            for (int k = 0; k < op.nsub; ++k) {
+                const SubOp &so = pr.subs[op.sub0 + k];
+                in_rows += (so.n_map > 0 ? so.n_in : 0) + so.n_dir;
+            }
+        }
+    };
+    int64_t fin = 0, fout = 0, ain = 0, aout = 0;
+    rows_moved(pk.fwd, fin, fout);
+    rows_moved(pk.adj, ain, aout);
+    os << ",\"fwd_gather_rows\":" << fin << ",\"fwd_out_rows\":" << fout << ",\"adj_gather_rows\":" << ain
+       << ",\"adj_out_rows\":" << aout;
     os << ",\"fwd_index_bytes\":" << fwd_idx << ",\"fwd_state_bytes\":" << 20 * fwd_states
        << ",\"adj_state_bytes\":" << 20 * adj_states << ",\"gen_fwd_items\":" << pk.gen_fwd.items.size()
        << ",\"gen_adj_items\":" << pk.gen_adj.items.size() << "}";

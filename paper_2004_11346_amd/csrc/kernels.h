@@ -18,15 +18,26 @@ struct DenseTables {
     const double *wh = nullptr;     // [N]
     const double *dmant = nullptr;  // [2N][N]
     const int *dexp = nullptr;      // [2N][N]
-    const double *coef = nullptr;   // [tri][2]
+    const double *coef = nullptr;   // [tri][2] one-step recurrence
+    const double *coef2 = nullptr;  // [tri][3] same-parity two-step recurrence
 };
 
-// FP64 panels used by the plain path when it runs on the matrix cores.
+// FP64 panels used by the plain path when it runs on the matrix cores, and
+// the checkpoints of its transposed product: one item per (task, 64-column
+// output tile), items sorted by task; the recurrence states of every item's
+// rows at its first column are recomputed per call, a chunk of tasks at a
+// time, into a buffer of ck_cap states.
 struct DensePanels {
     void *X = nullptr;             // [N (2N + 1)][R] coefficient panels
     void *Y = nullptr;             // [4 N^2][R] half-grid panels
     const int64_t *x_off = nullptr;  // device [4N + 1]
     int64_t max_cols = 0;
+    const int32_t *adj_items = nullptr;  // device [items][2]: task, first column
+    std::vector<int32_t> adj_task_first; // host [4N + 1]: first item of every task
+    const int32_t *adj_task_first_d = nullptr;  // its device copy
+    double *ck = nullptr;                // device [2 ck_cap]: (Pbar_{k-2}, Pbar_k) per state
+    int32_t *ckexp = nullptr;            // device [ck_cap]: their binary exponent
+    int64_t ck_cap = 0;                  // states per chunk (multiple of the padded row count)
 };
 bool dense_uses_panels(int batch);
 

@@ -171,3 +171,18 @@ def test_dense_n1024_four_fields_sampled():
         for i, a in enumerate(absm):
             gin[:, a % M] = ref[i, 0]
             gin[:, (-a) % M] = ref[i, 1]
+
+
+@pytest.mark.parametrize("N,batch", [(70, 4), (130, 3)])
+def test_dense_transpose_in_state_chunks(N, batch, monkeypatch):
+    """The transposed product records its recurrence states a chunk of tasks
+    at a time; a tiny state buffer forces one or two tasks per chunk."""
+    monkeypatch.setenv("SHT_DENSE_CKPT_STATES", "1")
+    print(f"dense transpose chunks N={N} batch={batch}", flush=True)
+    p = _plan(N, batch)
+    grid = inputs.make_grid(N, batch, 3)
+    bi = p.inverse(_to_dev(grid, torch.complex128)).cpu().numpy()
+    ba = p.backward(_to_dev(grid, torch.complex128)).cpu().numpy()
+    for b in sorted({0, batch - 1}):
+        assert rel_l2(bi[b], oracle.sht_inverse(N, grid[b])) <= 1e-12
+        assert rel_l2(ba[b], oracle.sht_adjoint(N, grid[b])) <= 1e-12
