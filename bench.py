@@ -132,14 +132,21 @@ def cpu_baseline(N: int):
 # SHA-256 of the kernel sources it was measured with; a changed source makes
 # the figure stale and it is reported as null.
 TRAFFIC = {
-    ("dense", 1024, 32, "f64", "k_dense_fwd_mfma"): {"bytes_per_call": 24.078e9, "sha": "8aee453d1430ba7c",
+    # HBM bytes per forward ALT call of each kernel family: rocprofv3 FETCH_SIZE
+    # and WRITE_SIZE runs (two calls each), scaled by what the counters read
+    # for a 1 GiB copy in the same run; valid for the kernel sources of "sha"
+    ("dense", 1024, 32, "f64", "k_dense_fwd_mfma"): {"bytes_per_call": 24.077e9, "sha": "f96c61d886e8597d",
                                                      "profile": "profiles/alt_fwd_dense_n1024_b32_f64.md"},
-    ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7492e9, "sha": "8aee453d1430ba7c",
+    ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7503e9, "sha": "f96c61d886e8597d",
                                                     "profile": "profiles/alt_fwd_dense_n1024_b1_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_ops_mfma"): {"bytes_per_call": 63.390e9, "sha": "8e865fdb9ff2fa70",
+    ("idbf", 1024, 32, "f64", "k_gen_fwd_mfma"): {"bytes_per_call": 10.384e9, "sha": "b10c97f2c19018c5",
+                                                   "profile": "profiles/alt_fwd_idbf_n1024_b32_f64.md"},
+    ("idbf", 1024, 32, "f64", "k_ops_mfma"): {"bytes_per_call": 40.401e9, "sha": "b10c97f2c19018c5",
                                                "profile": "profiles/alt_fwd_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 1, "f64", "k_ops"): {"bytes_per_call": 6.436e9, "sha": "8e865fdb9ff2fa70",
+    ("idbf", 1024, 1, "f64", "k_ops"): {"bytes_per_call": 5.113e9, "sha": "b10c97f2c19018c5",
                                          "profile": "profiles/alt_fwd_idbf_n1024_b1_f64.md"},
+    ("idbf", 1024, 1, "f64", "k_gen_fwd"): {"bytes_per_call": 0.5512e9, "sha": "b10c97f2c19018c5",
+                                             "profile": "profiles/alt_fwd_idbf_n1024_b1_f64.md"},
 }
 
 
@@ -152,64 +159,83 @@ def kernel_source_sha(files):
     return h.hexdigest()[:16]
 
 
-DOMINANT = {
-    # method, uses matrix cores -> (label, kernel labels summed per call, source files)
-    ("dense", True): ("k_dense_fwd_mfma", ["k_dense_fwd_mfma"], ["kernels_dense.hip", "dense_device.h"]),
-    ("dense", False): ("k_dense_fwd_valu", ["k_dense_fwd_valu"], ["kernels_dense.hip", "dense_device.h"]),
-    ("idbf", True): ("fast ALT kernels (k_ops_mfma stages + k_gen_fwd_mfma)", ["k_ops_mfma", "k_gen_fwd_mfma"],
-                     ["idbf_kernels.hip", "idbf_pack.cpp"]),
-    ("idbf", False): ("fast ALT kernels (k_ops stages + k_gen_fwd)", ["k_ops", "k_gen_fwd"],
-                      ["idbf_kernels.hip", "idbf_pack.cpp"]),
-}
+def _kernel_sum(kern, names):
+    parts = [v for name, v in kern.items() if any(name == n or name.startswith(n + "[") for n in names)]
+    return (sum(v["launches"] for v in parts) if parts else 0,
+            sum(v["total_ms"] for v in parts) if parts else float("nan"))
+
+
+def _roof(bound, work, per_call_s, unit_peak):
+    unit, peak = unit_peak
+    ach = work / per_call_s / (1e12 if unit == "TFLOP/s" else 1e9)
+    return {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak}
+
+
+TFLOPS = ("TFLOP/s", PEAK_FP64_TFLOPS)
+GBS = ("GB/s", PEAK_HBM_GBS)
 
 
 def roofline(method, N, batch, dtype, stats, kern, reps):
-    """Roofline object for the dominant kernel(s) of the forward ALT.
+    """Roofline objects of the forward ALT: the dominant kernel, and (fast
+    form) the other kernel family beside it.
 
-    Algorithmic work per ALT call (all orders, one batch):
-      plain form:  flops = 2 R N^2 (2N + 1)  (every entry of every half matrix
-                   times R = 4 batch real right-hand sides)
-      fast form:   flops = 2 R (stored + regenerated entries); bytes = stored
-                   entries s + index bytes + recurrence states + batch (4N^2 +
-                   2N M) c_s  (factor stream read once, vectors in and out;
-                   HBM bound below the FP64 ridge, R < 40)
-    The fast form runs as one launch per program stage plus the regenerated
-    blocks' kernel; its "launch" here is the sum of those launches per call."""
-    M = 4 * N - 1
+    Algorithmic work per ALT call (all orders, one batch, R = 4 batch real
+    right-hand sides, s bytes per stored value and vector entry):
+      plain form (k_dense_fwd_*): flops = 2 R N^2 (2N + 1), every entry of
+        every half matrix once per right-hand side (regeneration not counted);
+      regenerated blocks (k_gen_fwd*): flops = 2 R (regenerated entries);
+      op stages (k_ops*, one launch per program stage): bytes = stored values
+        s + index bytes + (gathered rows + written rows) R s, the rows that the
+        level-by-level schedule moves through HBM.
+    With matrix cores (R >= 16) the regenerated blocks are the single largest
+    kernel (MFMA bound); with few right-hand sides the op stages are (HBM
+    bound).  "launch" = every launch of that kernel family per call."""
     R = 4 * batch
     sb = 8 if dtype == "f64" else 4
-    mfma_name = "k_dense_fwd_mfma" if method == "dense" else "k_ops_mfma"
-    uses_mfma = any(name.startswith(mfma_name) for name in kern)
-    label, names, files = DOMINANT[(method, uses_mfma)]
-    parts = [v for name, v in kern.items() if any(name == n or name.startswith(n + "[") for n in names)]
-    k = {"launches": sum(v["launches"] for v in parts) if parts else 0,
-         "total_ms": sum(v["total_ms"] for v in parts) if parts else float("nan")}
-    per_call_s = k["total_ms"] / reps / 1e3
-    launches_per_call = k["launches"] / reps
     if method == "dense":
+        mf = any(n.startswith("k_dense_fwd_mfma") for n in kern)
+        name = "k_dense_fwd_mfma" if mf else "k_dense_fwd_valu"
+        launches, ms = _kernel_sum(kern, [name])
+        per = ms / reps / 1e3
         flops = 2.0 * R * N * N * (2 * N + 1)
-        bytes_ = batch * (4 * N * N + 2 * N * M) * 2 * sb
-    else:
-        prog = stats.get("program", {})
-        nnz = float(prog.get("stored_entries", 0))
-        gen = float(prog.get("generated_entries", 0))
-        flops = 2.0 * R * (nnz + gen)
-        bytes_ = (nnz * sb + float(prog.get("fwd_index_bytes", 0)) + float(prog.get("fwd_state_bytes", 0))
-                  + batch * (4 * N * N + 2 * N * M) * 2 * sb)
-    compute_bound = method == "dense" or (2.0 * R / sb) >= PEAK_FP64_TFLOPS / (PEAK_HBM_GBS / 1e3)
-    if compute_bound:
-        ach = flops / per_call_s / 1e12
-        peak = PEAK_FP64_TFLOPS
-        r = {"bound": "mfma" if uses_mfma else "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-             "frac": ach / peak}
-    else:
-        ach = bytes_ / per_call_s / 1e9
-        r = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS}
+        prim = _roof("mfma" if mf else "alu", flops, per, TFLOPS)
+        prim.update({"kernel": name, "launches_per_call": launches / reps, "kernel_ms_per_call": per * 1e3,
+                     "dispatches_per_call": launches / reps, "algorithmic_flops_per_call": flops})
+        files = ["kernels_dense.hip", "dense_device.h"]
+        return _traffic(prim, method, N, batch, dtype, name, files), None
+    prog = stats.get("program", {})
+    mf = any(n.startswith("k_ops_mfma") for n in kern)
+    ops_name, gen_name = ("k_ops_mfma", "k_gen_fwd_mfma") if mf else ("k_ops", "k_gen_fwd")
+    files = ["idbf_kernels.hip", "idbf_pack.cpp"]
+    gl, gms = _kernel_sum(kern, [gen_name])
+    gper = gms / reps / 1e3
+    gflops = 2.0 * R * float(prog.get("generated_entries", 0))
+    gen = _roof("mfma" if mf else "alu", gflops, gper, TFLOPS)
+    rc_valu = 4 if R <= 4 else 8 if R <= 8 else 16
+    gen.update({"kernel": gen_name, "launches_per_call": gl / reps, "kernel_ms_per_call": gper * 1e3,
+                "dispatches_per_call": (R + 31) // 32 if mf else (R + rc_valu - 1) // rc_valu,
+                "algorithmic_flops_per_call": gflops})
+    ol, oms = _kernel_sum(kern, [ops_name])
+    oper = oms / reps / 1e3
+    obytes = (float(prog.get("stored_entries", 0)) * sb + float(prog.get("fwd_index_bytes", 0))
+              + (float(prog.get("fwd_gather_rows", 0)) + float(prog.get("fwd_out_rows", 0))) * R * sb)
+    ops = _roof("hbm", obytes, oper, GBS)
+    ops.update({"kernel": ops_name + " (all program stages)", "launches_per_call": ol / reps,
+                "dispatches_per_call": ol / reps,
+                "kernel_ms_per_call": oper * 1e3, "algorithmic_bytes_per_call": obytes,
+                "algorithmic_flops_per_call": 2.0 * R * float(prog.get("stored_entries", 0))})
+    if mf:
+        return _traffic(gen, method, N, batch, dtype, gen_name, files), _traffic(ops, method, N, batch, dtype,
+                                                                                   ops_name, files)
+    return _traffic(ops, method, N, batch, dtype, ops_name, files), _traffic(gen, method, N, batch, dtype,
+                                                                               gen_name, files)
+
+
+def _traffic(r, method, N, batch, dtype, name, files):
     sha = kernel_source_sha(files)
-    t = TRAFFIC.get((method, N, batch, dtype, names[0]))
+    t = TRAFFIC.get((method, N, batch, dtype, name))
     r["traffic"] = t["bytes_per_call"] if t and t["sha"] == sha else None
-    r.update({"kernel": label, "launches_per_call": launches_per_call, "kernel_ms_per_call": per_call_s * 1e3,
-              "algorithmic_flops_per_call": flops, "algorithmic_bytes_per_call": bytes_, "kernel_src_sha": sha})
+    r["kernel_src_sha"] = sha
     return r
 
 
@@ -449,7 +475,7 @@ def main():
     kern = plan.profile_report()
     plan.profile(False)
     stats = plan.stats()
-    roof = roofline(method, N, batch, args.dtype, stats, kern, reps)
+    roof, roof2 = roofline(method, N, batch, args.dtype, stats, kern, reps)
 
     out = {
         "metric": "SHT/s + ALT Gcoef/s at N=1024/4096, IDBF vs dense, FP64 & FP32, vs FP64 oracle",
@@ -471,6 +497,7 @@ def main():
         "alt_gcoef_per_s_inv": batch * 4 * N * N / t_alt_inv / 1e9,
         "plan_build_s": t_build,
         "roofline": roof,
+        "roofline_other": roof2,
         "alt_kernels_fwd": kern,
     }
 
