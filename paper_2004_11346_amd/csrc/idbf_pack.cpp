@@ -247,7 +247,7 @@ void forward_chain(const Block &b, const Offsets &of, int task, BlockProg &bp) {
 
 // ---- transposed chains ------------------------------------------------
 void transpose_chain(const Block &b, const Offsets &of, int task, BlockProg &bp) {
-    const int m = b.r1 - b.r0, n = b.c1 - b.c0;
+    const int n = b.c1 - b.c0;
     const int64_t xb = of.x[task], yb = of.y[task];
     bp.task = task;
     if (b.type == kDense && b.gen) {

@@ -167,10 +167,23 @@ def test_dense_n1024_four_fields_sampled():
         ref = oracle.alt_forward_orders(N, beta[b], absm)
         got = np.stack([np.stack([g[b][:, a % M], g[b][:, (-a) % M]]) for a in absm])
         assert rel_l2(got, ref) <= 1e-12
-        gin = np.zeros((2 * N, M), complex)
+    # transposed with weights at the same orders (inputs: the oracle's g)
+    gin = np.zeros((batch, 2 * N, M), complex)
+    refs = {}
+    for b in (0, 3):
+        refs[b] = oracle.alt_forward_orders(N, beta[b], absm)
         for i, a in enumerate(absm):
-            gin[:, a % M] = ref[i, 0]
-            gin[:, (-a) % M] = ref[i, 1]
+            gin[b][:, a % M] = refs[b][i, 0]
+            gin[b][:, (-a) % M] = refs[b][i, 1]
+    bo = torch.zeros((batch, 4 * N * N), dtype=torch.complex128, device="cuda")
+    p.alt(0, 2 * N - 1, "inv", _to_dev(gin, torch.complex128), bo)
+    bo = bo.cpu().numpy()
+    k_of, m_of = inputs.layout(N)
+    for b in (0, 3):
+        bref = oracle.alt_transpose_orders(N, refs[b], absm, weights=True)
+        for i, a in enumerate(absm):
+            for sgn, m in enumerate((a, -a) if a else (0,)):
+                assert rel_l2(bo[b][m_of == m], bref[i, sgn, : 2 * N - a]) <= 1e-12
 
 
 @pytest.mark.parametrize("N,batch", [(70, 4), (130, 3)])
