@@ -135,17 +135,17 @@ TRAFFIC = {
     # HBM bytes per forward ALT call of each kernel family: rocprofv3 FETCH_SIZE
     # and WRITE_SIZE runs (two calls each), scaled by what the counters read
     # for a 1 GiB copy in the same run; valid for the kernel sources of "sha"
-    ("dense", 1024, 32, "f64", "k_dense_fwd_mfma"): {"bytes_per_call": 24.077e9, "sha": "f96c61d886e8597d",
+    ("dense", 1024, 32, "f64", "k_dense_fwd_mfma"): {"bytes_per_call": 24.068e9, "sha": "f96c61d886e8597d",
                                                      "profile": "profiles/alt_fwd_dense_n1024_b32_f64.md"},
-    ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7503e9, "sha": "f96c61d886e8597d",
+    ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7480e9, "sha": "f96c61d886e8597d",
                                                     "profile": "profiles/alt_fwd_dense_n1024_b1_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_gen_fwd_mfma"): {"bytes_per_call": 10.384e9, "sha": "b10c97f2c19018c5",
+    ("idbf", 1024, 32, "f64", "k_gen_fwd_mfma"): {"bytes_per_call": 13.502e9, "sha": "7ccc70389dfe7f70",
                                                    "profile": "profiles/alt_fwd_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_ops_mfma"): {"bytes_per_call": 40.401e9, "sha": "b10c97f2c19018c5",
+    ("idbf", 1024, 32, "f64", "k_ops_mfma"): {"bytes_per_call": 4.346e9, "sha": "7ccc70389dfe7f70",
                                                "profile": "profiles/alt_fwd_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 1, "f64", "k_ops"): {"bytes_per_call": 5.113e9, "sha": "b10c97f2c19018c5",
+    ("idbf", 1024, 1, "f64", "k_ops"): {"bytes_per_call": 0.1472e9, "sha": "7ccc70389dfe7f70",
                                          "profile": "profiles/alt_fwd_idbf_n1024_b1_f64.md"},
-    ("idbf", 1024, 1, "f64", "k_gen_fwd"): {"bytes_per_call": 0.5512e9, "sha": "b10c97f2c19018c5",
+    ("idbf", 1024, 1, "f64", "k_gen_fwd"): {"bytes_per_call": 0.8093e9, "sha": "7ccc70389dfe7f70",
                                              "profile": "profiles/alt_fwd_idbf_n1024_b1_f64.md"},
 }
 
@@ -183,13 +183,14 @@ def roofline(method, N, batch, dtype, stats, kern, reps):
     right-hand sides, s bytes per stored value and vector entry):
       plain form (k_dense_fwd_*): flops = 2 R N^2 (2N + 1), every entry of
         every half matrix once per right-hand side (regeneration not counted);
-      regenerated blocks (k_gen_fwd*): flops = 2 R (regenerated entries);
+      regenerated blocks (k_gen_fwd*): flops = (2 R + 6) (regenerated entries):
+        the product, and the two-step recurrence and scaling of each entry;
       op stages (k_ops*, one launch per program stage): bytes = stored values
         s + index bytes + (gathered rows + written rows) R s, the rows that the
         level-by-level schedule moves through HBM.
-    With matrix cores (R >= 16) the regenerated blocks are the single largest
-    kernel (MFMA bound); with few right-hand sides the op stages are (HBM
-    bound).  "launch" = every launch of that kernel family per call."""
+    The dominant family (`roofline`) is the one with the larger measured time
+    per call; the other is `roofline_other`.  "launch" = every launch of that
+    kernel family per call."""
     R = 4 * batch
     sb = 8 if dtype == "f64" else 4
     if method == "dense":
@@ -209,7 +210,7 @@ def roofline(method, N, batch, dtype, stats, kern, reps):
     files = ["idbf_kernels.hip", "idbf_pack.cpp"]
     gl, gms = _kernel_sum(kern, [gen_name])
     gper = gms / reps / 1e3
-    gflops = 2.0 * R * float(prog.get("generated_entries", 0))
+    gflops = (2.0 * R + 6.0) * float(prog.get("generated_entries", 0))
     gen = _roof("mfma" if mf else "alu", gflops, gper, TFLOPS)
     rc_valu = 4 if R <= 4 else 8 if R <= 8 else 16
     gen.update({"kernel": gen_name, "launches_per_call": gl / reps, "kernel_ms_per_call": gper * 1e3,
@@ -224,11 +225,9 @@ def roofline(method, N, batch, dtype, stats, kern, reps):
                 "dispatches_per_call": ol / reps,
                 "kernel_ms_per_call": oper * 1e3, "algorithmic_bytes_per_call": obytes,
                 "algorithmic_flops_per_call": 2.0 * R * float(prog.get("stored_entries", 0))})
-    if mf:
-        return _traffic(gen, method, N, batch, dtype, gen_name, files), _traffic(ops, method, N, batch, dtype,
-                                                                                   ops_name, files)
-    return _traffic(ops, method, N, batch, dtype, ops_name, files), _traffic(gen, method, N, batch, dtype,
-                                                                               gen_name, files)
+    gen = _traffic(gen, method, N, batch, dtype, gen_name, files)
+    ops = _traffic(ops, method, N, batch, dtype, ops_name, files)
+    return (gen, ops) if not (oper > gper) else (ops, gen)
 
 
 def _traffic(r, method, N, batch, dtype, name, files):

@@ -99,7 +99,10 @@ typedef struct sht_plan_opts {
                           largest entry (paper: 1e-10; default 1e-12) */
     int n0;            /* partition: split turning-point blocks while
                           max(rows, cols) > n0 (paper: 512; default 256) */
-    int leaf;          /* IDBF leaf size (default 32) */
+    int leaf;          /* IDBF leaf size; 0 (default): by size, 32 up to
+                          N = 256, 128 up to N = 1024, 64 above (the measured
+                          crossover between applying butterflies and
+                          regenerating dense blocks on MI355X) */
     int rk;            /* adaptive rank cap r_k of each ID (paper: 150) */
     int oversample;    /* ID row oversampling t (default 2) */
     int rsvd_r;        /* randomized-SVD rank r (paper: 30) */

@@ -133,7 +133,7 @@ void sht_plan_opts_default(sht_plan_opts *o) {
     std::memset(o, 0, sizeof *o);
     o->eps = 1e-12;
     o->n0 = 256;
-    o->leaf = 32;
+    o->leaf = 0;  // by size (see the builder)
     o->rk = 150;
     o->oversample = 2;
     o->rsvd_r = 30;

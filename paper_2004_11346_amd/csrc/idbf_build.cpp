@@ -149,8 +149,10 @@ ID column_id(const View &K, int lo, int hi, const std::vector<int> &cand, Ctx &c
         for (int j = 0; j < n; ++j)
             for (int i = 0; i < ns; ++i) M[i + (size_t)j * ns] = K(s[i], cand[j]);
         std::vector<int> perm;
-        int k = la::pivoted_qr(ns, n, M.data(), ns, cx.tol, std::min(n, cx.o->rk), perm);
+        const int kmax = std::min(n, cx.o->rk);
+        int k = la::pivoted_qr(ns, n, M.data(), ns, cx.tol, kmax, perm);
         ID id;
+        id.capped = k == kmax && k < n;
         id.skel.assign(perm.begin(), perm.begin() + k);
         id.red.assign(perm.begin() + k, perm.end());
         const int nred = n - k;
@@ -255,6 +257,12 @@ bool build_butterfly(const View &K, int r0, int r1, int c0, int c1, Ctx &cx, But
             for (int i = 0; i < ri.k(); ++i)
                 for (int j = 0; j < ci.k(); ++j) S[(size_t)i * ci.k() + j] = K(ri.skel_glob[i], ci.skel_glob[j]);
         }
+    // a butterfly with an ID cut at the rank cap does not compress its block
+    // to the tolerance: leave the block to the dense (regenerated) path
+    for (const auto *ids : {&bf.col, &bf.row})
+        for (const auto &lv : *ids)
+            for (const ID &id : lv)
+                if (id.capped) return false;
     return true;
 }
 
@@ -716,8 +724,17 @@ void build_task(int N, const LegendreTables &lt, const sht_plan_opts &o, int a, 
 
 }  // namespace
 
-int build_all(int N, const sht_plan_opts &opts, HostPlanData &out) {
+// Leaf size when the options leave it to the builder.  It sets the smallest
+// block given a butterfly (4 leaves); below it blocks are regenerated dense
+// blocks.  The values are the measured optima on MI355X (FP64, 8-32 fields):
+// at N = 1024 applying butterflies to blocks under 512 columns costs more than
+// regenerating them, at N = 4096 butterflies pay from 256 columns.
+int auto_leaf(int N) { return N <= 256 ? 32 : N <= 1024 ? 128 : 64; }
+
+int build_all(int N, const sht_plan_opts &opts_in, HostPlanData &out) {
     auto t0 = std::chrono::steady_clock::now();
+    sht_plan_opts opts = opts_in;
+    if (opts.leaf <= 0) opts.leaf = auto_leaf(N);
     out.N = N;
     out.opts = opts;
     build_legendre_tables(N, out.lt);

@@ -21,6 +21,7 @@ struct ID {
     std::vector<int> skel, red;   // positions in cand
     std::vector<double> T;        // k x nred, row-major
     std::vector<int> skel_glob;   // cand[skel]
+    bool capped = false;          // stopped at the rank cap with columns left (tolerance not shown)
     int k() const { return (int)skel.size(); }
 };
 

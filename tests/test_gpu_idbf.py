@@ -91,12 +91,15 @@ def test_idbf_f32(N, batch):
         assert rel_l2(bi[b], oracle.sht_inverse(N, grid[b].astype(np.complex128))) <= 2e-6
 
 
-def test_idbf_n1024_sampled():
-    """Full-size fast path at N = 1024 (grid 2048 x 4095, default partition):
-    the ALT at sampled orders, forward and inverse, against the oracle."""
+@pytest.mark.parametrize("leaf", [32, 0])
+def test_idbf_n1024_sampled(leaf):
+    """Full-size fast path at N = 1024 (grid 2048 x 4095): the ALT at sampled
+    orders, forward and inverse, against the oracle; leaf 32 gives every block
+    from 128 columns a butterfly, leaf 0 is the size-chosen default (mostly
+    regenerated blocks at this size)."""
     N = 1024
-    print("idbf N=1024 sampled (plan build)", flush=True)
-    p = _plan(N, 1)
+    print(f"idbf N=1024 sampled leaf={leaf} (plan build)", flush=True)
+    p = _plan(N, 1, leaf=leaf)
     print("plan stats", p.stats(), flush=True)
     beta = inputs.make_beta(N, 1, 2, dist="decay")
     M = 4 * N - 1

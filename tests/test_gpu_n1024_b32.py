@@ -18,13 +18,13 @@ def rel_l2(a, b):
     return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / max(np.linalg.norm(np.asarray(b).ravel()), 1e-300))
 
 
-@pytest.mark.parametrize("method,tol", [("dense", 1e-12), ("idbf", 1e-11)])
-def test_n1024_32_fields_sampled_orders(method, tol):
+@pytest.mark.parametrize("method,tol,kw", [("dense", 1e-12, {}), ("idbf", 1e-11, {}), ("idbf", 1e-11, {"leaf": 32})])
+def test_n1024_32_fields_sampled_orders(method, tol, kw):
     from paper_2004_11346_amd.sht import Plan
     N, batch = 1024, 32
     M = 4 * N - 1
-    print(f"{method} N=1024 batch 32 sampled (plan build)", flush=True)
-    p = Plan(N, batch, dtype=torch.complex128, method=method)
+    print(f"{method} {kw} N=1024 batch 32 sampled (plan build)", flush=True)
+    p = Plan(N, batch, dtype=torch.complex128, method=method, **kw)
     beta = inputs.make_beta(N, batch, 2, dist="decay")
     absm = sorted({0, 1, N // 2, N, 3 * N // 2, 2 * N - 1} | {int(a) for a in inputs.sample_indices(2 * N, 6, 21)})
     fields = (0, 17, 31)
