@@ -135,17 +135,17 @@ TRAFFIC = {
     # HBM bytes per forward ALT call of each kernel family: rocprofv3 FETCH_SIZE
     # and WRITE_SIZE runs (two calls each), scaled by what the counters read
     # for a 1 GiB copy in the same run; valid for the kernel sources of "sha"
-    ("dense", 1024, 32, "f64", "k_dense_fwd_mfma"): {"bytes_per_call": 24.068e9, "sha": "f96c61d886e8597d",
+    ("dense", 1024, 32, "f64", "k_dense_fwd_mfma"): {"bytes_per_call": 24.079e9, "sha": "3e8f855adf40a47d",
                                                      "profile": "profiles/alt_fwd_dense_n1024_b32_f64.md"},
-    ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7480e9, "sha": "f96c61d886e8597d",
+    ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7507e9, "sha": "3e8f855adf40a47d",
                                                     "profile": "profiles/alt_fwd_dense_n1024_b1_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_gen_fwd_mfma"): {"bytes_per_call": 13.502e9, "sha": "7ccc70389dfe7f70",
+    ("idbf", 1024, 32, "f64", "k_gen_fwd_mfma"): {"bytes_per_call": 15.365e9, "sha": "49ca4d116af01dd6",
                                                    "profile": "profiles/alt_fwd_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_ops_mfma"): {"bytes_per_call": 4.346e9, "sha": "7ccc70389dfe7f70",
+    ("idbf", 1024, 32, "f64", "k_ops_mfma"): {"bytes_per_call": 4.346e9, "sha": "49ca4d116af01dd6",
                                                "profile": "profiles/alt_fwd_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 1, "f64", "k_ops"): {"bytes_per_call": 0.1472e9, "sha": "7ccc70389dfe7f70",
+    ("idbf", 1024, 1, "f64", "k_ops"): {"bytes_per_call": 0.1472e9, "sha": "49ca4d116af01dd6",
                                          "profile": "profiles/alt_fwd_idbf_n1024_b1_f64.md"},
-    ("idbf", 1024, 1, "f64", "k_gen_fwd"): {"bytes_per_call": 0.8093e9, "sha": "7ccc70389dfe7f70",
+    ("idbf", 1024, 1, "f64", "k_gen_fwd"): {"bytes_per_call": 0.8085e9, "sha": "49ca4d116af01dd6",
                                              "profile": "profiles/alt_fwd_idbf_n1024_b1_f64.md"},
 }
 

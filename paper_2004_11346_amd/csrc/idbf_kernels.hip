@@ -550,8 +550,11 @@ __global__ __launch_bounds__(64) void k_gen_fwd(const GenItem *__restrict__ item
 // A = values[16 rows][4 columns], B = X[4 columns][16 columns].  The B
 // fragments of the next tile are loaded while the current one is generated
 // and multiplied; the recurrence coefficients are wave-uniform loads.
+// Three waves per SIMD (at most 170 registers, no spills) run faster than the
+// compiler's own choice of two.
 template <typename T, int CBP>
-__global__ __launch_bounds__(64) void k_gen_fwd_mfma(const GenItem *__restrict__ items, int n_items, int xc, int item0,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8)))
+void k_gen_fwd_mfma(const GenItem *__restrict__ items, int n_items, int xc, int item0,
                                                      const GenSeg *__restrict__ segs, const double *__restrict__ ck,
                                                      const int32_t *__restrict__ ckexp,
                                                      const double *__restrict__ xh, const double *__restrict__ coef2,
