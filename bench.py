@@ -428,13 +428,7 @@ def main():
     N, batch = args.N, args.batch
     cdt = torch.complex128 if args.dtype == "f64" else torch.complex64
     M = 4 * N - 1
-    method = args.method
-    if method is None:
-        method = "idbf"
-        try:
-            S.Plan(4, 1, method="idbf").close()
-        except Exception:  # noqa: BLE001  (fast form not built: measure the plain one)
-            method = "dense"
+    method = args.method or "idbf"
     timer = Timer()
 
     beta_np = inputs.make_beta(N, batch, 2, dist="decay")
