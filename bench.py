@@ -9,7 +9,7 @@ The headline workload is N = 1024 (grid 2048 x 4095), FP64, 32 fields, with
 the fast (IDBF) ALT; the plain (dense) ALT and batch 1 are measured beside it
 and reported under "details".
 
-Prints ONE JSON line.  `--gpus` above 1 is refused: this build runs on one GPU.
+Prints ONE JSON line.  `--gpus` above 1 is refused: the transform runs on one GPU.
 """
 from __future__ import annotations
 
@@ -401,8 +401,8 @@ def fp32_legs(S, inputs, timer, N, batch, beta_np, no_check):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding by order is described in DESIGN.md)"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1 (the path would shard by order across "
+                                   "GPUs; only one GPU's share is implemented)"}))
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("one GPU only: launch without torch.distributed", file=sys.stderr)
