@@ -311,6 +311,9 @@ def n4096_orders(args):
             acc += 0.5 * (ys[i] + ys[i + 1]) * (xs[i + 1] - xs[i]) / W
         return acc + ys[-1]
     est = {k: total(k) for k in ("fast_fwd_ms", "fast_inv_ms", "plain_fwd_ms", "plain_inv_ms")}
+    del g, bo
+    torch.cuda.empty_cache()
+    fp32 = n4096_fp32_windows(S, N, B, W)
     coefs = B * 4 * N * N
     print(json.dumps({"metric": "ALT Gcoef/s at N=4096, fast vs plain, FP64, 8 fields (estimated from windows)",
                       "unit": "Gcoef/s", "n_gpus": 1, "data": "synthetic", "dtype": "f64",
@@ -319,7 +322,50 @@ def n4096_orders(args):
                       "estimated_full_ms": est,
                       "alt_gcoef_per_s": {k.replace("_ms", ""): coefs / (v / 1e3) / 1e9 for k, v in est.items()},
                       "fast_over_plain": {"fwd": est["plain_fwd_ms"] / est["fast_fwd_ms"],
-                                          "inv": est["plain_inv_ms"] / est["fast_inv_ms"]}}), flush=True)
+                                          "inv": est["plain_inv_ms"] / est["fast_inv_ms"]},
+                      "fp32_windows": fp32}), flush=True)
+
+
+def n4096_fp32_windows(S, N, B, W):
+    """FP32 fast-form plans on two 64-order windows at N = 4096 (8 fields):
+    split-BF16 with six products and FP32 storage on the FP64 matrix cores,
+    timed, with the forward ALT error against the FP64 oracle at three orders
+    of the window (fields 0 and 7)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2004_11346_amd import inputs
+    from paper_2004_11346_amd import lib as L
+    M = 4 * N - 1
+    timer = Timer()
+    beta_np = inputs.make_beta(N, B, 3, dist="decay").astype(np.complex64)
+    beta = torch.from_numpy(beta_np).cuda()
+    g = torch.zeros((B, 2 * N, M), dtype=torch.complex64, device="cuda")
+    bo = torch.zeros_like(beta)
+    out = []
+    for a0 in (0, 4096):
+        lo, hi = a0, a0 + W - 1
+        absm = [lo, lo + W // 2, hi]
+        refs = {b: oracle.alt_forward_orders(N, beta_np[b].astype(np.complex128), absm) for b in (0, B - 1)}
+        for name, mode in (("split_bf16x6", L.SHT_F32_SPLIT_BF16_6), ("f32_storage_fp64_mfma", L.SHT_F32_VALU)):
+            p = S.Plan(N, B, dtype=torch.complex64, method="idbf", m_lo=lo, m_hi=hi, f32_mode=mode)
+            r = {"orders": [lo, hi], "form": name,
+                 "fwd_ms": 1e3 * timer.time(lambda: p.alt(lo, hi, "fwd", beta, g), reps=3),
+                 "inv_ms": 1e3 * timer.time(lambda: p.alt(lo, hi, "inv", g, bo), reps=3)}
+            p.alt(lo, hi, "fwd", beta, g)
+            errs = []
+            for b in (0, B - 1):
+                cols = [c for a in absm for c in (a % M, (-a) % M)]
+                gh = g[b][:, cols].cpu().numpy().astype(np.complex128)
+                got = np.stack([np.stack([gh[:, 2 * i], gh[:, 2 * i + 1]]) for i in range(len(absm))])
+                errs.append(rel_l2(got, refs[b]))
+            r["alt_fwd_sampled_orders_rel_l2"] = max(errs)
+            out.append(r)
+            print(json.dumps({"fp32_window": r}), flush=True)
+            p.close()
+            torch.cuda.empty_cache()
+    return out
 
 
 def uneven(args):
