@@ -135,17 +135,17 @@ TRAFFIC = {
     # HBM bytes per forward ALT call of each kernel family: rocprofv3 FETCH_SIZE
     # and WRITE_SIZE runs (two calls each), scaled by what the counters read
     # for a 1 GiB copy in the same run; valid for the kernel sources of "sha"
-    ("dense", 1024, 32, "f64", "k_dense_fwd_mfma"): {"bytes_per_call": 24.079e9, "sha": "3e8f855adf40a47d",
+    ("dense", 1024, 32, "f64", "k_dense_fwd_mfma"): {"bytes_per_call": 24.06e9, "sha": "21a5dbab89ebbe02",
                                                      "profile": "profiles/alt_fwd_dense_n1024_b32_f64.md"},
-    ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7507e9, "sha": "3e8f855adf40a47d",
+    ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7513e9, "sha": "21a5dbab89ebbe02",
                                                     "profile": "profiles/alt_fwd_dense_n1024_b1_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_gen_fwd_mfma"): {"bytes_per_call": 15.365e9, "sha": "49ca4d116af01dd6",
+    ("idbf", 1024, 32, "f64", "k_gen_fwd_mfma"): {"bytes_per_call": 15.37e9, "sha": "d9dc951b5db97d43",
                                                    "profile": "profiles/alt_fwd_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_ops_mfma"): {"bytes_per_call": 4.346e9, "sha": "49ca4d116af01dd6",
+    ("idbf", 1024, 32, "f64", "k_ops_mfma"): {"bytes_per_call": 4.346e9, "sha": "d9dc951b5db97d43",
                                                "profile": "profiles/alt_fwd_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 1, "f64", "k_ops"): {"bytes_per_call": 0.1472e9, "sha": "49ca4d116af01dd6",
+    ("idbf", 1024, 1, "f64", "k_ops"): {"bytes_per_call": 0.1472e9, "sha": "d9dc951b5db97d43",
                                          "profile": "profiles/alt_fwd_idbf_n1024_b1_f64.md"},
-    ("idbf", 1024, 1, "f64", "k_gen_fwd"): {"bytes_per_call": 0.8085e9, "sha": "49ca4d116af01dd6",
+    ("idbf", 1024, 1, "f64", "k_gen_fwd"): {"bytes_per_call": 0.811e9, "sha": "d9dc951b5db97d43",
                                              "profile": "profiles/alt_fwd_idbf_n1024_b1_f64.md"},
 }
 

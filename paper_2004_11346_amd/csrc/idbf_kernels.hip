@@ -671,7 +671,10 @@ void k_gen_fwd_mfma(const GenItem *__restrict__ items, int n_items, int xc, int 
 // registers (B = H[4 rows][16 right-hand sides], rows 4 ks + l/16), and for
 // each 16-column group of the tile the lanes (rows) step the recurrence into
 // an LDS tile that is read back transposed as A = values[16 columns][4 rows];
-// v_mfma_f64_16x16x4f64 sums over the 64 rows.
+// v_mfma_f64_16x16x4f64 sums over the 64 rows.  With two blocks of right-hand
+// sides, three waves per SIMD (168 registers, four of them spilled) run faster
+// than the compiler's own choice of two; with one, its own choice (four) is
+// kept.
 struct GenItemA {
     int32_t task, col0, seg_begin, seg_end;
 };
@@ -680,7 +683,7 @@ struct GenSegA {
 };
 
 template <typename T, int CBP>
-__global__ __launch_bounds__(64) void k_gen_adj(const GenItemA *__restrict__ items, int n_items, int xc, int item0,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(CBP == 1 ? 1 : 3, 8))) void k_gen_adj(const GenItemA *__restrict__ items, int n_items, int xc, int item0,
                                                 const GenSegA *__restrict__ segs, const double *__restrict__ ck,
                                                 const int32_t *__restrict__ ckexp, const double *__restrict__ xh,
                                                 const double *__restrict__ coef2, int N,
@@ -710,20 +713,32 @@ __global__ __launch_bounds__(64) void k_gen_adj(const GenItemA *__restrict__ ite
         double p0 = ck[2 * ((int64_t)sg.ck + lane)], p1 = ck[2 * ((int64_t)sg.ck + lane) + 1];
         int ex = ckexp[sg.ck + lane];
         const double *cs = cfo + 6 * (int64_t)sg.c0;
+        // Loads without branches or selects, so that the compiler waits for the
+        // early ones alone and the H fragments stay in flight while the first
+        // column group is generated: coefficients past the segment's columns
+        // are never read (the index is clamped to a valid one), rows past N
+        // read row N - 1 and right-hand sides past R read R - 1.  Rows outside
+        // the block have zero recurrence states, so their values are 0 and
+        // their (finite) fragments add nothing; right-hand sides past R are
+        // not stored.
         double cv[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const int e = lane + 64 * i;
-            cv[i] = e < 3 * sg.ncol ? cs[6 * (e / 3) + e % 3] : 0.0;
+            const int ee = e < 3 * sg.ncol ? e : 0;
+            cv[i] = cs[6 * (ee / 3) + ee % 3];
         }
+        __builtin_amdgcn_sched_barrier(0);
+        const bool full = sg.row0 + 64 <= N;  // wave-uniform
         double B[16][CBP];
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks) {
-            const T *hg = Ht + (int64_t)(sg.row0 + 4 * ks) * R;  // wave-uniform base
+            const int rr = sg.row0 + 4 * ks + jl;
+            const T *hg = Ht + (int64_t)(full ? rr : min(rr, N - 1)) * R;
 #pragma unroll
             for (int cb = 0; cb < CBP; ++cb) {
-                const int rr = sg.row0 + 4 * ks + jl, col = rhs0 + 16 * cb + cl;
-                B[ks][cb] = (rr < N && col < R) ? (double)hg[jl * (int)R + col] : 0.0;
+                const int col = rhs0 + 16 * cb + cl;
+                B[ks][cb] = (double)hg[col < R ? col : (int)R - 1];
             }
         }
         double sc = scale_of(ex);
@@ -737,7 +752,16 @@ __global__ __launch_bounds__(64) void k_gen_adj(const GenItemA *__restrict__ ite
             if (gc0 + 16 <= sg.c0 || gc0 >= sg.c0 + sg.ncol) continue;
             if (gc0 > sg.c0 && gc0 + 16 <= sg.c0 + sg.ncol) {
                 gen_run<16>(s_c + 3 * (gc0 - sg.c0), x2, p0, p1, ex, sc, tile + lane, PAD);
+            } else if (CBP > 1 && gc0 == sg.c0 && 16 <= sg.ncol) {
+                // the segment's first column is the stored state itself (two
+                // 16-column blocks only: with one the extra code costs a wave
+                // per SIMD)
+                tile[lane] = p1 * sc;
+                gen_run<14>(s_c + 3, x2, p0, p1, ex, sc, tile + PAD + lane, PAD);
+                gen_2step(s_c + 3 * 15, x2, p0, p1, ex, sc);
+                tile[15 * PAD + lane] = p1 * sc;
             } else {
+#pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int t = gc0 + j - sg.c0;  // column index in the segment
                     double v = 0.0;

@@ -55,7 +55,20 @@ __global__ __launch_bounds__(64) void k_group_fwd(const GTrans *__restrict__ tr,
     }
 }
 
-// 4 waves, four nodes per lane (N <= 1024), one field per pass
+// One field pair (or a last odd field) of one order: the recurrence is walked
+// once for both fields of a pair.
+template <typename T, int NR>
+__device__ __forceinline__ void group_adj_order(const GTrans &d, int a, const T *g, T *beta, double *red) {
+    int b0 = 0;
+    for (; b0 + 2 <= d.fields; b0 += 2)
+        dense_adj_order<T, 2, NR>(d.N, d.M, d.fields, b0, a, 4, d.xh, d.wh, d.dmant, d.dexp, d.coef, g, beta, red);
+    if (b0 < d.fields)
+        dense_adj_order<T, 1, NR>(d.N, d.M, d.fields, b0, a, 4, d.xh, d.wh, d.dmant, d.dexp, d.coef, g, beta, red);
+}
+
+// 4 waves; NR = 1, 2 or 4 nodes per lane, the fewest that cover N <= 1024
+// nodes, so that every wave owns nodes from N = 256 up (below that, lanes past
+// the last node form zero products).
 template <typename T>
 __global__ __launch_bounds__(256) void k_group_adj(const GTrans *__restrict__ tr, const GItem *__restrict__ items,
                                                    int nitems, int *counter) {
@@ -68,9 +81,12 @@ __global__ __launch_bounds__(256) void k_group_adj(const GTrans *__restrict__ tr
         const GTrans &d = tr[w.t];
         const T *g = (const T *)d.g;
         T *beta = (T *)d.beta;
-        for (int b0 = 0; b0 < d.fields; ++b0)
-            dense_adj_order<T, 1, 4>(d.N, d.M, d.fields, b0, w.a, 4, d.xh, d.wh, d.dmant, d.dexp, d.coef, g, beta,
-                                     red);
+        if (d.N <= 256)
+            group_adj_order<T, 1>(d, w.a, g, beta, red);
+        else if (d.N <= 512)
+            group_adj_order<T, 2>(d, w.a, g, beta, red);
+        else
+            group_adj_order<T, 4>(d, w.a, g, beta, red);
     }
 }
 
