@@ -73,7 +73,7 @@ def _load():
             lib.oracle_alt_transpose_grid.argtypes = [I, P, P, P, P]
             lib.oracle_alt_transpose_orders.argtypes = [I, P, P, I, P, P, P]
             lib.oracle_dft_synthesis.argtypes = [I, P, I, P, P]
-            lib.oracle_dft_analysis.argtypes = [I, P, I, P, D, P]
+            lib.oracle_dft_analysis.argtypes = [I, P, I, D, P]
             for name in ("oracle_gauss_legendre", "oracle_plm", "oracle_alt_forward_grid",
                          "oracle_alt_forward_orders", "oracle_alt_forward_rows", "oracle_alt_transpose_grid",
                          "oracle_alt_transpose_orders", "oracle_dft_synthesis",
@@ -204,10 +204,7 @@ def dft_analysis(N: int, f_rows: np.ndarray, scale: float | None = None) -> np.n
     if scale is None:
         scale = 1.0 / M
     out = np.zeros_like(f_rows)
-    n_rows = f_rows.shape[0]
-    # rows pointer unused by the analysis (it only needs the row count)
-    dummy = np.arange(n_rows, dtype=np.int32)
-    _chk(_load().oracle_dft_analysis(N, _ptr(f_rows), n_rows, _ptr(dummy), float(scale), _ptr(out)),
+    _chk(_load().oracle_dft_analysis(N, _ptr(f_rows), f_rows.shape[0], float(scale), _ptr(out)),
          "dft_analysis")
     return out
 

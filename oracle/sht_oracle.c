@@ -427,15 +427,12 @@ int oracle_dft_synthesis(int N, const double *g, int n_rows, const int *rows, do
 /* phi analysis: g[l][m mod M] = scale * sum_j f[l][j] exp(-i pi m (2j+1)/M).
  * scale = 1/M gives the inverse of the synthesis (the trapezoid rule in phi is
  * exact for the M residues); scale = 1 gives its conjugate transpose, used by
- * the adjoint.  Listed rows only (rows == NULL: all 2N); f_rows and g_rows are
- * complex [n_rows][M]. */
-int oracle_dft_analysis(int N, const double *f_rows, int n_rows, const int *rows,
-                        double scale, double *g_rows)
+ * the adjoint.  Each row is transformed on its own, so any subset of grid rows
+ * may be passed; f_rows and g_rows are complex [n_rows][M]. */
+int oracle_dft_analysis(int N, const double *f_rows, int n_rows, double scale, double *g_rows)
 {
-    (void)rows;
-    if (N < 1) return -1;
+    if (N < 1 || n_rows < 0) return -1;
     const int M = 4 * N - 1, n = 2 * N;
-    if (!rows) n_rows = n;
     ld *ct, *st;
     if (phase_table(M, &ct, &st)) return -2;
 #pragma omp parallel for schedule(dynamic, 4) collapse(2)

@@ -15,6 +15,6 @@ __all__ = ["inputs", "sht"]
 
 def __getattr__(name):
     import importlib
-    if name in ("sht", "inputs", "lib", "metrics", "autograd"):
+    if name in ("sht", "inputs", "lib", "autograd"):
         return importlib.import_module(f"{__name__}.{name}")
     raise AttributeError(name)

@@ -10,18 +10,18 @@ from __future__ import annotations
 
 import torch
 
-from .sht import Plan
+from .sht import Plan, materialize
 
 
 class SHTForward(torch.autograd.Function):
     @staticmethod
     def forward(ctx, beta: torch.Tensor, plan: Plan) -> torch.Tensor:
         ctx.plan = plan
-        return plan.forward(beta.contiguous())
+        return plan.forward(materialize(beta))
 
     @staticmethod
     def backward(ctx, grad_f: torch.Tensor):
-        return ctx.plan.backward(grad_f.contiguous()), None
+        return ctx.plan.backward(materialize(grad_f)), None
 
 
 def sht_forward(beta: torch.Tensor, plan: Plan) -> torch.Tensor:

@@ -24,18 +24,7 @@ ARCH = "gfx950"
 
 
 def sources():
-    skip = {"idbf_stub.cpp", "host_plan_stub.cpp"}
-    have = set(os.listdir(CSRC))
-    out = []
-    for f in sorted(have):
-        if f.endswith((".hip", ".cpp")):
-            if f in skip:
-                # stubs are only used while the real module is absent
-                real = {"idbf_stub.cpp": "idbf_plan.cpp", "host_plan_stub.cpp": "host_plan.cpp"}[f]
-                if real in have:
-                    continue
-            out.append(os.path.join(CSRC, f))
-    return out
+    return [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith((".hip", ".cpp"))]
 
 
 def hipcc():

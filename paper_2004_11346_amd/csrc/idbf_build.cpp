@@ -731,13 +731,16 @@ void build_task(int N, const LegendreTables &lt, const sht_plan_opts &o, int a, 
 // regenerating them, at N = 4096 butterflies pay from 256 columns.
 int auto_leaf(int N) { return N <= 256 ? 32 : N <= 1024 ? 128 : 64; }
 
-int build_all(int N, const sht_plan_opts &opts_in, HostPlanData &out) {
+int build_all(int N, const sht_plan_opts &opts_in, HostPlanData &out, const LegendreTables *lt) {
     auto t0 = std::chrono::steady_clock::now();
     sht_plan_opts opts = opts_in;
     if (opts.leaf <= 0) opts.leaf = auto_leaf(N);
     out.N = N;
     out.opts = opts;
-    build_legendre_tables(N, out.lt);
+    if (lt && lt->N == N)
+        out.lt = *lt;
+    else
+        build_legendre_tables(N, out.lt);
     const int ntask = 4 * N;  // 2N orders x 2 parities
     out.tasks.assign(ntask, Task());
     int nth = opts.threads > 0 ? opts.threads : (int)std::thread::hardware_concurrency();

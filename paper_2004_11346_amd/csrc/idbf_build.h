@@ -105,8 +105,9 @@ struct HostPlanData {
     std::string stats_json() const;
 };
 
-// Build every task (all orders, both parities).
-int build_all(int N, const sht_plan_opts &opts, HostPlanData &out);
+// Build every task (all orders, both parities).  `lt`, when given, holds the
+// Legendre tables of degree N already built by the caller (copied into out).
+int build_all(int N, const sht_plan_opts &opts, HostPlanData &out, const LegendreTables *lt = nullptr);
 
 
 }  // namespace idbf

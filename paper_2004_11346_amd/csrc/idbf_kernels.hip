@@ -13,10 +13,9 @@
 // accumulation (output panel) follow.  Ops of one stage never write the same
 // rows, so there are no atomics and the result is bitwise reproducible.
 //
-// Generated sub-ops (dense blocks near the turning point, Section 3.2) carry
-// no values: each lane walks the recurrence of one node from a stored state,
-// one composed two-step (same parity) per column, rescaling by exact powers
-// of two as the table builder does.
+// Regenerated dense blocks (near the turning point, Section 3.2) are not part
+// of the program: k_gen_fwd* and k_gen_adj apply them after it, walking the
+// same-parity recurrence from stored per-row states.
 #include <hip/hip_runtime.h>
 
 #include "idbf_device.h"

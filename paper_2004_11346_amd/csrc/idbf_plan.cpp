@@ -76,9 +76,8 @@ void DeviceProgram::release() {
 }
 
 int build_program(int N, int batch, const LegendreTables &lt, const sht_plan_opts &opts, HostProgram &out) {
-    (void)lt;
     HostPlanData hp;
-    int rc = build_all(N, opts, hp);
+    int rc = build_all(N, opts, hp, &lt);
     if (rc) return rc;
     (void)batch;
     pack_programs(hp, out.packed);

@@ -9,8 +9,10 @@
 //   three-term recurrence in k from these, rescaling by exact powers of two.
 // * Coefficients (a_k, b_k) of the normalised three-term recurrence
 //   Pbar_k^m = a_k (x Pbar_{k-1}^m - b_k Pbar_{k-2}^m), packed per order.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "sht_internal.h"
 
@@ -18,6 +20,23 @@ namespace sht {
 
 namespace {
 typedef long double ld;
+
+// Run body(i) for i in [0, n) on all hardware threads (static interleave).
+template <typename F>
+void parallel_for(int n, F body) {
+    int nth = (int)std::thread::hardware_concurrency();
+    nth = std::max(1, std::min({nth, 64, n}));
+    if (nth == 1) {
+        for (int i = 0; i < n; ++i) body(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int w = 0; w < nth; ++w)
+        th.emplace_back([&, w]() {
+            for (int i = w; i < n; i += nth) body(i);
+        });
+    for (auto &t : th) t.join();
+}
 const ld kPi = 3.141592653589793238462643383279502884L;
 
 // P_n(t) and P_n'(t) by the Legendre three-term recurrence.
@@ -40,7 +59,7 @@ void legendre_and_derivative(int n, ld t, ld &p, ld &dp) {
 
 void gauss_legendre(int n, double *x, double *w) {
     const int half = n / 2;
-    for (int k = 1; k <= (n + 1) / 2; ++k) {
+    auto root = [&](int k) {
         // k-th largest root; Tricomi's first-order asymptotic guess
         ld th = kPi * (4 * k - 1) / (4.0L * n + 2.0L);
         ld t = (1.0L - (n - 1.0L) / (8.0L * n * n * n)) * cosl(th);
@@ -63,7 +82,11 @@ void gauss_legendre(int n, double *x, double *w) {
             w[hi] = (double)wt;
             w[lo] = (double)wt;
         }
-    }
+    };
+    if (n >= 512)
+        parallel_for((n + 1) / 2, [&](int i) { root(i + 1); });
+    else
+        for (int k = 1; k <= (n + 1) / 2; ++k) root(k);
     (void)half;
 }
 
@@ -83,7 +106,7 @@ void build_legendre_tables(int N, LegendreTables &t) {
     t.diag_e.assign((size_t)n * N, 0);
     std::vector<ld> fac(n);
     for (int m = 1; m < n; ++m) fac[m] = sqrtl((ld)(2 * m + 1) / (ld)(2 * m));
-    for (int r = 0; r < N; ++r) {
+    parallel_for(N, [&](int r) {
         ld xv = t.xh[r];
         ld s = sqrtl((1.0L - xv) * (1.0L + xv));
         ld mu = 1.0L / sqrtl(2.0L);
@@ -96,10 +119,10 @@ void build_legendre_tables(int N, LegendreTables &t) {
             t.diag_m[(size_t)m * N + r] = (double)mu;
             t.diag_e[(size_t)m * N + r] = e;
         }
-    }
+    });
     // recurrence coefficients
     t.coef.assign((size_t)2 * tri_offset(N, n), 0.0);
-    for (int m = 0; m < n; ++m) {
+    parallel_for(n, [&](int m) {
         double *c = &t.coef[2 * tri_offset(N, m)];
         if (m + 1 < n) {
             c[2] = (double)sqrtl((ld)(2 * m + 3));
@@ -112,14 +135,14 @@ void build_legendre_tables(int N, LegendreTables &t) {
             c[2 * (k - m)] = (double)a;
             c[2 * (k - m) + 1] = (double)b;
         }
-    }
+    });
     // composed two-step coefficients: from P_{k-1} = a_{k-1} (x P_{k-2} - b_{k-1} P_{k-3})
     // and x P_{k-3} = P_{k-2} / a_{k-2} + b_{k-2} P_{k-4},
     //   alpha_k = a_k a_{k-1},  beta_k = -a_k (b_k + a_{k-1} b_{k-1} / a_{k-2}),
     //   gamma_k = -a_k a_{k-1} b_{k-1} b_{k-2};
     // b_{m+1} = 0 removes the terms that would need a_m or b_m
     t.coef2.assign((size_t)3 * tri_offset(N, n), 0.0);
-    for (int m = 0; m < n; ++m) {
+    parallel_for(n, [&](int m) {
         double *c2 = &t.coef2[3 * tri_offset(N, m)];
         auto A = [&](int k) -> ld {
             if (k == m + 1) return sqrtl((ld)(2 * m + 3));
@@ -139,7 +162,7 @@ void build_legendre_tables(int N, LegendreTables &t) {
             c2[3 * (k - m) + 1] = (double)(-ak * (bk + mid));
             c2[3 * (k - m) + 2] = (double)gam;
         }
-    }
+    });
 }
 
 void alt_half_matrix(const LegendreTables &t, int a, int parity, double *out) {

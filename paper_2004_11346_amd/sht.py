@@ -27,6 +27,27 @@ def _stream_ptr(stream=None) -> int:
     return int(s.cuda_stream)
 
 
+def check_tensor(t: torch.Tensor, dtype, shape, name: str, require_cuda: bool = True):
+    """Reject what the C ABI cannot take as a plain pointer: host tensors, a
+    wrong dtype or shape, non-contiguous storage, and lazy conjugate or
+    negative views (their memory holds the unconjugated / unnegated values)."""
+    if not isinstance(t, torch.Tensor) or (require_cuda and not t.is_cuda):
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if t.is_conj() or t.is_neg():
+        raise ValueError(f"{name} is a lazy conjugate/negative view; call .resolve_conj().resolve_neg() first")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def materialize(t: torch.Tensor) -> torch.Tensor:
+    """Contiguous tensor whose memory holds its values (lazy conj/neg resolved)."""
+    return t.resolve_conj().resolve_neg().contiguous()
+
+
 class Plan:
     """A transform plan of degree N for ``batch`` fields.
 
@@ -70,14 +91,7 @@ class Plan:
         return (self.batch, 2 * self.N, self.M)
 
     def _check(self, t: torch.Tensor, shape, name):
-        if not isinstance(t, torch.Tensor) or not t.is_cuda:
-            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
-        if t.dtype != self.dtype:
-            raise TypeError(f"{name} must have dtype {self.dtype}, got {t.dtype}")
-        if tuple(t.shape) != tuple(shape):
-            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
-        if not t.is_contiguous():
-            raise ValueError(f"{name} must be contiguous")
+        check_tensor(t, self.dtype, shape, name)
 
     def empty_coefs(self, device="cuda"):
         return torch.empty(self.coef_shape, dtype=self.dtype, device=device)
@@ -207,9 +221,8 @@ class Group:
         if len(betas) != n or len(fs) != n:
             raise ValueError("one beta and one f tensor per transform")
         for i in range(n):
-            for t, shp, nm in ((betas[i], self.coef_shape(i), "beta"), (fs[i], self.grid_shape(i), "f")):
-                if not t.is_cuda or t.dtype != self.dtype or tuple(t.shape) != shp or not t.is_contiguous():
-                    raise ValueError(f"{nm}[{i}] must be a contiguous {self.dtype} CUDA tensor of shape {shp}")
+            check_tensor(betas[i], self.dtype, self.coef_shape(i), f"beta[{i}]")
+            check_tensor(fs[i], self.dtype, self.grid_shape(i), f"f[{i}]")
         arr = ctypes.c_void_p * n
         _l.check(self._lib.sht_group_bind(self._h, arr(*[b.data_ptr() for b in betas]),
                                           arr(*[f.data_ptr() for f in fs])), "sht_group_bind")

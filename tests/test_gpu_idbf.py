@@ -2,7 +2,9 @@
 C-ABI.  Bar: relative l2 <= 1e-11 in FP64 (the factorization tolerance is
 1e-12 of each task's largest entry; the butterfly levels add their errors),
 <= 2e-6 in FP32.  Small partitions (n0, leaf) are used at small N so that
-butterflies, low-rank and dense blocks all occur."""
+butterflies and dense blocks occur; the cases with a small randomized-SVD
+rank (rsvd_r = 4) also build Algorithm 1 low-rank blocks, which the test
+asserts from the plan statistics."""
 import numpy as np
 import pytest
 import torch
@@ -31,6 +33,9 @@ CASES = [
     (64, 1, dict(n0=32, leaf=8)),
     (64, 2, dict(n0=32, leaf=8, dense_gen=0)),
     (64, 3, dict(n0=32, leaf=8)),
+    (64, 1, dict(n0=32, leaf=8, rsvd_r=4)),
+    (128, 2, dict(n0=64, leaf=8, rsvd_r=4)),
+    (128, 5, dict(n0=64, leaf=8, rsvd_r=4)),
     (100, 2, dict(n0=48, leaf=8)),
     (130, 1, dict()),
     (5, 2, dict()),
@@ -42,6 +47,9 @@ CASES = [
 def test_idbf_forward_inverse_adjoint_vs_oracle(N, batch, kw):
     print(f"idbf N={N} batch={batch} {kw}", flush=True)
     p = _plan(N, batch, **kw)
+    if kw.get("rsvd_r") == 4:
+        st = p.stats()["program"]
+        assert st["blocks_lowrank"] > 0 and st["lowrank_stored"] > 0, st
     beta = inputs.make_beta(N, batch, 1)
     f = p.forward(_dev(beta)).cpu().numpy()
     grid = inputs.make_grid(N, batch, 2)
@@ -146,17 +154,21 @@ def test_idbf_matrix_core_path(N, batch, rcw, monkeypatch):
         assert rel_l2(bi[b], oracle.sht_inverse(N, grid[b])) <= 1e-11
 
 
-@pytest.mark.parametrize("terms", [3, 6])
+@pytest.mark.parametrize("terms", [
+    pytest.param(3, marks=pytest.mark.skip(
+        reason="two BF16 parts per value leave residuals of about 2^-17 per product: relative l2 "
+               "4e-6 at N <= 130 and 2.4e-6 at N = 1024, above the FP32 bar of 2e-6")),
+    6])
 @pytest.mark.parametrize("N,batch,kw", [(64, 1, dict(n0=32, leaf=8)), (64, 8, dict(n0=32, leaf=8)),
-                                        (130, 3, dict()), (48, 12, dict(n0=24, leaf=4))])
+                                        (130, 3, dict()), (48, 12, dict(n0=24, leaf=4)),
+                                        (128, 8, dict(n0=64, leaf=8, rsvd_r=4))])
 def test_idbf_split_bf16(N, batch, kw, terms):
-    """FP32 plans on the BF16 matrix cores with FP32 accumulation.  Three
-    products of two BF16 parts (hi, lo) leave residuals of about 2^-17 of each
-    product, so the relative l2 error is a few 1e-6 (bar 6e-6); six products
-    of three parts drop only terms below 2^-24 and meet the FP32 bar 2e-6."""
+    """FP32 plans on the BF16 matrix cores with FP32 accumulation, held to the
+    FP32 bar 2e-6.  Six products of three BF16 parts drop only terms below
+    2^-24 and meet it; the three-product form does not (skipped)."""
     from paper_2004_11346_amd import lib as L
     mode = L.SHT_F32_SPLIT_BF16 if terms == 3 else L.SHT_F32_SPLIT_BF16_6
-    tol = 6e-6 if terms == 3 else 2e-6
+    tol = 2e-6
     print(f"idbf split-bf16 x{terms} N={N} batch={batch}", flush=True)
     p = _plan(N, batch, dtype=torch.complex64, f32_mode=mode, **kw)
     beta = inputs.make_beta(N, batch, 1).astype(np.complex64)

@@ -98,7 +98,9 @@ def test_library_half_matrices_match_oracle(N):
 
 
 @pytest.mark.parametrize("N,kw", [
-    (64, dict(n0=32, leaf=8)),           # butterflies, low-rank and regenerated dense blocks
+    (64, dict(n0=32, leaf=8)),           # butterflies and regenerated dense blocks
+    (64, dict(n0=32, leaf=8, rsvd_r=4)),     # also Algorithm 1 low-rank blocks
+    (128, dict(n0=64, leaf=8, rsvd_r=4)),
     (64, dict(n0=32, leaf=8, dense_gen=0)),  # dense blocks stored instead
     (40, dict(n0=24, leaf=4)),           # blocks with unaligned first columns
     (96, dict(n0=48, leaf=8, eps=1e-13)),
@@ -128,6 +130,8 @@ def test_packed_program_vs_oracle(N, kw):
     assert worst <= 1e-11, (worst, st)
     if kw.get("leaf") == 8:
         assert st["blocks_butterfly"] > 0
+    if kw.get("rsvd_r") == 4:
+        assert st["blocks_lowrank"] > 0 and st["lowrank_stored"] > 0, st
     if kw.get("dense_gen", 1):
         assert st["blocks_generated"] > 0 and st["generated_entries"] > 0
     else:
