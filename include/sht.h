@@ -155,6 +155,21 @@ int sht_inverse(const sht_plan_t *plan, const void *f, void *beta, void *stream)
  * PyTorch's complex convention. */
 int sht_backward(const sht_plan_t *plan, const void *grad_f, void *grad_beta, void *stream);
 
+/* Allocation-free inverse, for callers that cannot allocate device memory
+ * during the call (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same result as sht_inverse, bit for bit:
+ * the same kernels run, but the phi-analysed grid g (2 x elt x batch x 2N x M
+ * bytes) is staged in a fixed device array of 128 MiB that the library holds
+ * once per GPU until the process ends (its address is looked up when the
+ * first plan is created on that GPU), instead of in the plan's workspace.
+ * Nothing is allocated or freed.  Plans whose grid exceeds 128 MiB (e.g. more
+ * than one FP64 field at N = 1024) are rejected with SHT_ERR_UNSUPPORTED.
+ * Every call on one GPU shares the array: calls that overlap in time on that
+ * GPU (several streams, several host threads) race and must be serialised by
+ * the caller.  Every byte read from the array is written earlier in the same
+ * call, so nothing needs clearing between calls. */
+int sht_inverse_noalloc(const sht_plan_t *plan, const void *f, void *beta, void *stream);
+
 /* ALT only, for the orders with m_lo <= |m| <= m_hi (both signs), no DFT
  * (Section 1, ALT; Section 3.1.1).
  *   dir = SHT_FWD: in = beta [batch][4N^2], out = g [batch][2N][M]; only the

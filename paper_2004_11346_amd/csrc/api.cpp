@@ -190,6 +190,7 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
     sht_plan_opts_default(&p->opts);
     if (opts) p->opts = *opts;
     HIP_TRY(hipGetDevice(&p->device), "hipGetDevice");
+    HIP_TRY((hipError_t)noalloc_scratch_init(p->device), "fixed scratch address");
     if (p->opts.f32_mode != SHT_F32_VALU && p->opts.f32_mode != SHT_F32_SPLIT_BF16 &&
         p->opts.f32_mode != SHT_F32_SPLIT_BF16_6)
         return SHT_ERR_INVALID_ARG;
@@ -472,6 +473,31 @@ int sht_inverse(const sht_plan_t *p, const void *f, void *beta, void *stream) {
 
 int sht_backward(const sht_plan_t *p, const void *grad_f, void *grad_beta, void *stream) {
     return transposed(p, grad_f, grad_beta, stream, false);
+}
+
+int sht_inverse_noalloc(const sht_plan_t *p, const void *f, void *beta, void *stream) {
+    if (!p) return SHT_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = full_transform_ok(p))) return rc;
+    if ((rc = check_ptr(beta, elt_size(p->dtype)))) return rc;
+    if ((rc = check_ptr(f, elt_size(p->dtype)))) return rc;
+    const size_t need = 2 * elt_size(p->dtype) * (size_t)p->batch * 2 * p->N * p->M;
+    if (need > kNoallocScratchBytes) {
+        set_error_detail("sht_inverse_noalloc: the grid of this plan needs " + std::to_string(need) +
+                         " bytes of fixed scratch, more than its " + std::to_string(kNoallocScratchBytes) +
+                         "; use sht_inverse");
+        return SHT_ERR_UNSUPPORTED;
+    }
+    void *g = noalloc_scratch(p->device);
+    if (!g) {
+        set_error_detail("sht_inverse_noalloc: fixed scratch of this device was not looked up");
+        return SHT_ERR_HIP;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    prof::Install inst(p->rec());
+    hipError_t e = dev::dft_analysis(p->dft, p->dtype, p->batch, 1.0 / p->M, f, g, s);
+    if (e != hipSuccess) return hip_fail(e, "DFT analysis");
+    return run_alt(p, 0, 2 * p->N - 1, SHT_INV, g, beta, s);
 }
 
 }  // extern "C"

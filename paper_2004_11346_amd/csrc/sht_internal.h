@@ -20,6 +20,16 @@ namespace sht {
 // ------------------------------------------------------------- errors
 void set_error_detail(const std::string &msg);
 
+// ------------------------------------------------------------- fixed scratch
+// Bytes of the per-GPU device array used by sht_inverse_noalloc for the
+// phi-analysed grid (128 MiB: one FP64 field at N = 1024).
+constexpr size_t kNoallocScratchBytes = (size_t)128 << 20;
+// Looks up the array's device address on `device` (which must be current);
+// once per device, idempotent.  Returns the hipError_t status as an int.
+int noalloc_scratch_init(int device);
+// The address found by the lookup, or nullptr if it has not run.
+void *noalloc_scratch(int device);
+
 // ------------------------------------------------------------- layout
 // Start (complex entries) of order m in the m-major coefficient layout.
 inline int64_t coef_offset(int N, int m) {

@@ -29,7 +29,7 @@ EXPORTED = [
     "sht_strerror", "sht_last_error_detail", "sht_host_plan_create", "sht_host_plan_destroy",
     "sht_host_plan_apply", "sht_host_alt_matrix", "sht_host_plan_stats", "sht_host_gauss_legendre",
     "sht_group_create", "sht_group_destroy", "sht_group_bind", "sht_group_forward", "sht_group_inverse",
-    "sht_group_tune", "sht_group_capture", "sht_group_replay", "sht_group_stats",
+    "sht_group_tune", "sht_group_capture", "sht_group_replay", "sht_group_stats", "sht_inverse_noalloc",
 ]
 
 
@@ -81,7 +81,7 @@ def load():
         lib.sht_plan_create.argtypes = [I, I, I, I, ctypes.POINTER(PlanOpts), PP]
         lib.sht_plan_destroy.argtypes = [P]
         lib.sht_plan_destroy.restype = None
-        for n in ("sht_forward", "sht_inverse", "sht_backward"):
+        for n in ("sht_forward", "sht_inverse", "sht_backward", "sht_inverse_noalloc"):
             getattr(lib, n).argtypes = [P, P, P, P]
         lib.sht_alt_apply.argtypes = [P, I, I, I, P, P, P]
         lib.sht_plan_stats.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]

@@ -118,6 +118,16 @@ class Plan:
                                        ctypes.c_void_p(_stream_ptr(stream))), "sht_inverse")
         return out
 
+    def inverse_noalloc(self, f: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """Inverse SHT that allocates nothing: the phi-analysed grid is staged in
+        the library's fixed per-GPU scratch (at most 128 MiB) instead of the
+        plan's workspace.  `out` must be given."""
+        self._check(f, self.grid_shape, "f")
+        self._check(out, self.coef_shape, "out")
+        _l.check(self._lib.sht_inverse_noalloc(self._h, f.data_ptr(), out.data_ptr(),
+                                               ctypes.c_void_p(_stream_ptr(stream))), "sht_inverse_noalloc")
+        return out
+
     def backward(self, grad_f: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         """Adjoint of forward (conjugate transpose): grad_f -> grad_beta."""
         self._check(grad_f, self.grid_shape, "grad_f")
