@@ -43,10 +43,12 @@ def parse():
     ap.add_argument("--profile-target", action="store_true",
                     help="only a 1 GiB device copy (counter scale) and a few ALT calls, for rocprofv3 runs")
     ap.add_argument("--profile-dirs", default="fwd",
-                    help="ALT directions run by --profile-target (comma separated: fwd, inv)")
-    ap.add_argument("--workload", choices=["default", "n4096-orders", "uneven"], default="default",
+                    help="calls run by --profile-target (comma separated: fwd, inv = ALT only; sht_fwd, "
+                         "sht_inv = full transforms)")
+    ap.add_argument("--workload", choices=["default", "n4096-orders", "uneven", "rank-study"], default="default",
                     help="n4096-orders: N=4096, 8 fields, fast vs plain ALT on 64-order windows across the "
-                         "order range; uneven: the grouped 64-transform workload")
+                         "order range; uneven: the grouped 64-transform workload; rank-study: ID sampling "
+                         "(mock-Chebyshev vs random rows), adaptive rank r_k and tolerance sweeps at m = N")
     return ap.parse_args()
 
 
@@ -84,45 +86,32 @@ class Timer:
 
 
 def cpu_baseline(N: int):
-    """The oracle (plain CPU FP64 definition) on a bounded sample of the same
-    workload, extrapolated to one forward + one inverse SHT of one field."""
+    """The oracle (plain CPU FP64 definition: dense ALT of every order, direct
+    phi sums) timed on one full forward and one full inverse SHT of one field
+    of the same workload (batch 1 of the headline configuration)."""
     import numpy as np
 
     import oracle
     from paper_2004_11346_amd import inputs
 
     beta = inputs.make_beta(N, 1, 2, dist="decay")[0]
-    n = 2 * N
-    step = max(1, n // 512)
-    absm = list(range(0, n, step))
-    rows = list(range(0, n, max(1, n // 128)))
-    work_all = sum(n - a for a in range(n))
-    work_s = sum(n - a for a in absm)
     t0 = time.perf_counter()
-    gfw = oracle.alt_forward_orders(N, beta, absm)
+    f = oracle.sht_forward(N, beta)
     t1 = time.perf_counter()
-    oracle.alt_transpose_orders(N, gfw, absm, weights=True)
+    back = oracle.sht_inverse(N, f)
     t2 = time.perf_counter()
-    g = np.zeros((n, 4 * N - 1), complex)
-    fr = oracle.dft_synthesis(N, g, rows=rows)
-    t3 = time.perf_counter()
-    oracle.dft_analysis(N, fr)
-    t4 = time.perf_counter()
-    scale_alt = work_all / work_s
-    scale_dft = n / len(rows)
-    t_fwd = (t1 - t0) * scale_alt + (t3 - t2) * scale_dft
-    t_inv = (t2 - t1) * scale_alt + (t4 - t3) * scale_dft
     return {
-        "value": 2.0 / (t_fwd + t_inv),
+        "value": 2.0 / (t2 - t0),
         "unit": "SHT/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": (f"N={N}, one field: forward and transposed ALT for {len(absm)} of {n} orders |m| "
-                   f"(both signs), phi synthesis and analysis for {len(rows)} of {n} latitude rows; "
-                   f"measured {t4 - t0:.1f} s, extrapolated by work to full forward+inverse SHTs"),
-        "seconds_measured": t4 - t0,
-        "fwd_s_per_field": t_fwd,
-        "inv_s_per_field": t_inv,
+        "sample": (f"N={N}, one field (batch 1 of the workload): one full forward and one full inverse SHT "
+                   f"(dense ALT of all {4 * N - 1} orders, direct phi sums over all {2 * N} rows), "
+                   f"measured {t2 - t0:.1f} s, not extrapolated"),
+        "seconds_measured": t2 - t0,
+        "fwd_s_per_field": t1 - t0,
+        "inv_s_per_field": t2 - t1,
+        "round_trip_rel_l2": rel_l2(back, beta),
     }
 
 
@@ -159,83 +148,144 @@ def kernel_source_sha(files):
     return h.hexdigest()[:16]
 
 
-def _kernel_sum(kern, names):
-    parts = [v for name, v in kern.items() if any(name == n or name.startswith(n + "[") for n in names)]
-    return (sum(v["launches"] for v in parts) if parts else 0,
-            sum(v["total_ms"] for v in parts) if parts else float("nan"))
-
-
-def _roof(bound, work, per_call_s, unit_peak):
-    unit, peak = unit_peak
-    ach = work / per_call_s / (1e12 if unit == "TFLOP/s" else 1e9)
-    return {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak}
-
-
 TFLOPS = ("TFLOP/s", PEAK_FP64_TFLOPS)
 GBS = ("GB/s", PEAK_HBM_GBS)
 
 
-def roofline(method, N, batch, dtype, stats, kern, reps):
-    """Roofline objects of the forward ALT: the dominant kernel, and (fast
-    form) the other kernel family beside it.
+def family(name):
+    """Kernel family of a recorder label ("k_ops_mfma[L2]" -> "k_ops_mfma")."""
+    return name.split("[", 1)[0]
 
-    Algorithmic work per ALT call (all orders, one batch, R = 4 batch real
-    right-hand sides, s bytes per stored value and vector entry):
-      plain form (k_dense_fwd_*): flops = 2 R N^2 (2N + 1), every entry of
-        every half matrix once per right-hand side (regeneration not counted);
-      regenerated blocks (k_gen_fwd*): flops = (2 R + 6) (regenerated entries):
-        the product, and the two-step recurrence and scaling of each entry;
-      op stages (k_ops*, one launch per program stage): bytes = stored values
-        s + index bytes + (gathered rows + written rows) R s, the rows that the
-        level-by-level schedule moves through HBM.
-    The dominant family (`roofline`) is the one with the larger measured time
-    per call; the other is `roofline_other`.  "launch" = every launch of that
-    kernel family per call."""
+
+def kernel_work(fam, method, N, batch, dtype, prog):
+    """Algorithmic work of one call of a kernel family over all orders of one
+    batch: (bound, work, unit_peak, dispatches per call, what).
+
+    R = 4 batch real right-hand sides, s bytes per stored value and panel
+    entry, E = N^2 (2N + 1) entries of the half matrices of all orders.
+      products with regenerated entries (plain form, regenerated blocks of the
+        fast form): (2 R + 3) flops per entry -- the product with every
+        right-hand side and about 3 flops to generate the entry;
+      op stages (stored factors): values s + index bytes + the vector rows one
+        call must move once (distinct input-panel rows read, output rows
+        written) R s; the rows the level-by-level schedule moves beyond that
+        are reported as "schedule_bytes";
+      panel moves and phi DFTs: one read and one write of the data they move.
+    """
     R = 4 * batch
     sb = 8 if dtype == "f64" else 4
-    if method == "dense":
-        mf = any(n.startswith("k_dense_fwd_mfma") for n in kern)
-        name = "k_dense_fwd_mfma" if mf else "k_dense_fwd_valu"
-        launches, ms = _kernel_sum(kern, [name])
-        per = ms / reps / 1e3
-        flops = 2.0 * R * N * N * (2 * N + 1)
-        prim = _roof("mfma" if mf else "alu", flops, per, TFLOPS)
-        prim.update({"kernel": name, "launches_per_call": launches / reps, "kernel_ms_per_call": per * 1e3,
-                     "dispatches_per_call": launches / reps, "algorithmic_flops_per_call": flops})
-        files = ["kernels_dense.hip", "dense_device.h"]
-        return _traffic(prim, method, N, batch, dtype, name, files), None
-    prog = stats.get("program", {})
-    mf = any(n.startswith("k_ops_mfma") for n in kern)
-    ops_name, gen_name = ("k_ops_mfma", "k_gen_fwd_mfma") if mf else ("k_ops", "k_gen_fwd")
-    files = ["idbf_kernels.hip", "idbf_pack.cpp"]
-    gl, gms = _kernel_sum(kern, [gen_name])
-    gper = gms / reps / 1e3
-    gflops = (2.0 * R + 6.0) * float(prog.get("generated_entries", 0))
-    gen = _roof("mfma" if mf else "alu", gflops, gper, TFLOPS)
-    rc_valu = 4 if R <= 4 else 8 if R <= 8 else 16
-    gen.update({"kernel": gen_name, "launches_per_call": gl / reps, "kernel_ms_per_call": gper * 1e3,
-                "dispatches_per_call": (R + 31) // 32 if mf else (R + rc_valu - 1) // rc_valu,
-                "algorithmic_flops_per_call": gflops})
-    ol, oms = _kernel_sum(kern, [ops_name])
-    oper = oms / reps / 1e3
-    obytes = (float(prog.get("stored_entries", 0)) * sb + float(prog.get("fwd_index_bytes", 0))
-              + (float(prog.get("fwd_gather_rows", 0)) + float(prog.get("fwd_out_rows", 0))) * R * sb)
-    ops = _roof("hbm", obytes, oper, GBS)
-    ops.update({"kernel": ops_name + " (all program stages)", "launches_per_call": ol / reps,
-                "dispatches_per_call": ol / reps,
-                "kernel_ms_per_call": oper * 1e3, "algorithmic_bytes_per_call": obytes,
-                "algorithmic_flops_per_call": 2.0 * R * float(prog.get("stored_entries", 0))})
-    gen = _traffic(gen, method, N, batch, dtype, gen_name, files)
-    ops = _traffic(ops, method, N, batch, dtype, ops_name, files)
-    return (gen, ops) if not (oper > gper) else (ops, gen)
+    E = float(N) * N * (2 * N + 1)
+    grid = 2.0 * N * (4 * N - 1) * batch * 2 * sb  # complex grid bytes
+    coefs = 4.0 * N * N * batch * 2 * sb             # complex coefficient bytes
+    pb = 8 if method == "dense" else sb              # the plain form's panels are FP64
+    xpan = float(N) * (2 * N + 1) * R * pb
+    ypan = 4.0 * N * N * R * pb
+    gen_disp = (R + 31) // 32
+    if fam in ("k_dense_fwd_mfma", "k_dense_adj_ck"):
+        return "mfma", (2.0 * R + 3) * E, TFLOPS, 1, "(2R+3) N^2(2N+1) flops"
+    if fam in ("k_dense_fwd_valu", "k_dense_adj_valu"):
+        return "alu", (2.0 * R + 3) * E, TFLOPS, 1, "(2R+3) N^2(2N+1) flops"
+    if fam == "k_dense_ckpt":
+        return "alu", 3.0 * E, TFLOPS, 1, "3 N^2(2N+1) flops (recurrence walk)"
+    ng = float(prog.get("generated_entries", 0))
+    if fam == "k_gen_fwd_mfma":
+        return "mfma", (2.0 * R + 3) * ng, TFLOPS, gen_disp, "(2R+3) x regenerated entries flops"
+    if fam == "k_gen_fwd":
+        rc = 4 if R <= 4 else 8 if R <= 8 else 16
+        return "alu", (2.0 * R + 3) * ng, TFLOPS, (R + rc - 1) // rc, "(2R+3) x regenerated entries flops"
+    if fam == "k_gen_adj":
+        return "mfma", (2.0 * R + 3) * ng, TFLOPS, 1 if R <= 16 else gen_disp, "(2R+3) x regenerated entries flops"
+    if fam.startswith("k_ops"):
+        d = "adj" if fam.endswith("@inv") else "fwd"
+        vals = float(prog.get(d + "_values", 0)) * sb
+        idx = float(prog.get(d + "_index_bytes", 0))
+        vec = (float(prog.get(d + "_vector_in_rows", 0)) + float(prog.get(d + "_vector_out_rows", 0))) * R * sb
+        return "hbm", vals + idx + vec, GBS, None, "values s + index + distinct vector rows R s"
+    if fam in ("k_pack", "k_scatter"):
+        return "hbm", coefs + xpan, GBS, 1, "coefficients + X panels"
+    if fam in ("k_combine", "k_fold"):
+        return "hbm", grid + ypan, GBS, 1, "grid + Y panels"
+    if fam in ("k_dft_synthesis", "k_dft_analysis"):
+        return "hbm", 2.0 * grid, GBS, 1, "grid read + written"
+    return None
 
 
-def _traffic(r, method, N, batch, dtype, name, files):
+def plan_shape(stats):
+    """How the fast form's work splits: entries stored as IDBF / low-rank /
+    dense factors, entries regenerated by the recurrence, and the share of the
+    dense matrices dropped as negligible (Section 3.3)."""
+    prog = stats.get("program")
+    if not prog:
+        return None
+    dense = float(prog["dense_entries"])
+    keys = ("blocks_butterfly", "blocks_lowrank", "blocks_dense", "blocks_generated", "blocks_dropped",
+            "butterfly_stored", "lowrank_stored", "dense_stored", "stored_entries", "generated_entries",
+            "dense_entries", "leaf", "max_rank")
+    out = {k: prog.get(k) for k in keys}
+    out["stored_over_dense"] = prog["stored_entries"] / dense
+    out["generated_over_dense"] = prog["generated_entries"] / dense
+    osc = prog.get("osc", {})
+    out["oscillatory_area_over_dense"] = osc.get("area", 0) / dense
+    return out
+
+
+def step_roofline(method, N, batch, dtype, prog, kern_fwd, kern_inv, reps):
+    """Per-kernel-family time and roofline fraction over one step (forward +
+    inverse SHT), from HIP events recorded on the launch stream; `roofline`
+    is the family with the largest time per step."""
+    fams = {}
+    for tag, kern in (("fwd", kern_fwd), ("inv", kern_inv)):
+        for name, v in kern.items():
+            fam = family(name)
+            key = fam + ("@inv" if fam.startswith("k_ops") and tag == "inv" else "")
+            f = fams.setdefault(key, {"ms_per_step": 0.0, "launches_per_step": 0.0})
+            f["ms_per_step"] += v["total_ms"] / reps
+            f["launches_per_step"] += v["launches"] / reps
+    rows = {}
+    for key, f in fams.items():
+        w = kernel_work(key, method, N, batch, dtype, prog)
+        r = {"ms_per_step": f["ms_per_step"], "launches_per_step": f["launches_per_step"]}
+        if w:
+            bound, work, (unit, peak), disp, what = w
+            per_call_s = f["ms_per_step"] / f["launches_per_step"] / 1e3
+            ach = work / per_call_s / (1e12 if unit == "TFLOP/s" else 1e9)
+            r.update({"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+                      "work_per_call": work, "work": what})
+            if disp:
+                r["dispatches_per_call"] = disp
+                r["avg_dispatch_ms"] = per_call_s * 1e3 / disp
+        if key.startswith("k_ops"):
+            d = "adj" if key.endswith("@inv") else "fwd"
+            sb = 8 if dtype == "f64" else 4
+            r["schedule_bytes"] = ((float(prog.get(d + "_gather_rows", 0)) + float(prog.get(d + "_out_rows", 0)))
+                                   * 4 * batch * sb)
+        rows[key] = r
+    dom = max((k for k in rows if "frac" in rows[k]), key=lambda k: rows[k]["ms_per_step"])
+    d = rows[dom]
+    roof = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
+            "frac": d["frac"], "kernel": dom, "work": d["work"], "work_per_call": d["work_per_call"],
+            "kernel_ms_per_call": d["ms_per_step"] / d["launches_per_step"],
+            "kernel_share_of_step_kernels": d["ms_per_step"] / sum(r["ms_per_step"] for r in rows.values())}
+    if "dispatches_per_call" in d:
+        roof["dispatches_per_call"] = d["dispatches_per_call"]
+        roof["avg_dispatch_ms"] = d["avg_dispatch_ms"]
+    roof.update(traffic_of(method, N, batch, dtype, dom))
+    return roof, rows
+
+
+def traffic_of(method, N, batch, dtype, fam):
+    """Measured HBM bytes per call of a kernel family (rocprofv3 FETCH_SIZE +
+    WRITE_SIZE, scaled), with the profile it comes from; null when the kernel
+    sources changed since the counters were taken."""
+    files = {"dense": ["kernels_dense.hip", "dense_device.h"],
+             "idbf": ["idbf_kernels.hip", "idbf_pack.cpp"]}[method]
+    if fam.startswith("k_dft"):
+        files = ["kernels_dft.hip", "dft_device.h"]
     sha = kernel_source_sha(files)
-    t = TRAFFIC.get((method, N, batch, dtype, name))
-    r["traffic"] = t["bytes_per_call"] if t and t["sha"] == sha else None
-    r["kernel_src_sha"] = sha
-    return r
+    t = TRAFFIC.get((method, N, batch, dtype, fam))
+    ok = bool(t) and t["sha"] == sha
+    return {"traffic": t["bytes_per_call"] if ok else None,
+            "traffic_profile": t["profile"] if ok else None, "kernel_src_sha": sha}
 
 
 def profile_target(args):
@@ -261,8 +311,14 @@ def profile_target(args):
         for _ in range(args.steps):
             if d == "fwd":
                 plan.alt(0, 2 * N - 1, "fwd", beta, g)
-            else:
+            elif d == "inv":
                 plan.alt(0, 2 * N - 1, "inv", g, bo)
+            elif d == "sht_fwd":
+                plan.forward(beta, out=g)
+            elif d == "sht_inv":
+                plan.inverse(g, out=bo)
+            else:
+                raise SystemExit(f"unknown profile direction {d}")
     torch.cuda.synchronize()
     print(json.dumps({"profile_target": True, "N": N, "batch": batch, "method": method, "dtype": args.dtype,
                       "alt_calls": args.steps, "copy_bytes": 2 * a.numel() * 8}), flush=True)
@@ -370,8 +426,12 @@ def n4096_fp32_windows(S, N, B, W):
 
 def uneven(args):
     """The grouped workload: 64 transforms, N drawn from {128, 256, 512, 1024}
-    and 1-4 fields each (seed 4000), one persistent launch per phase,
-    autotuned, replayed from a hipGraph; FP64 and FP32."""
+    and 1-4 fields each (seed 4000), FP64 and FP32, each direction replayed
+    from a hipGraph: the persistent mode (one persistent launch per phase,
+    grid autotuned) and the batched mode (one plan per degree over all its
+    fields, plain or fast form and leaf chosen by the tuner)."""
+    import tempfile
+
     import numpy as np
     import torch
 
@@ -383,26 +443,111 @@ def uneven(args):
     fields = [int(v) for v in rng.integers(1, 5, size=64)]
     timer = Timer()
     out = {}
+    tmp = tempfile.mkdtemp(prefix="sht_group_")
     for dname, dt in (("f64", torch.complex128), ("f32", torch.complex64)):
-        grp = Group(Ns, fields, dtype=dt)
-        betas = [torch.from_numpy(inputs.make_beta(N, f, 4100 + i)).to(dt).cuda()
-                 for i, (N, f) in enumerate(zip(Ns, fields))]
-        fs = [torch.zeros((f, 2 * N, 4 * N - 1), dtype=dt, device="cuda") for N, f in zip(Ns, fields)]
-        grp.bind(betas, fs)
-        grp.tune()
-        s = torch.cuda.Stream()
-        with torch.cuda.stream(s):
-            grp.capture("fwd", s)
-            grp.capture("inv", s)
-            tf = timer.time(lambda: grp.replay("fwd", s), reps=max(3, args.steps))
-            ti = timer.time(lambda: grp.replay("inv", s), reps=max(3, args.steps))
-        out[dname] = {"fwd_ms": tf * 1e3, "inv_ms": ti * 1e3, "sht_per_s": 2 * sum(fields) / (tf + ti),
-                      "grid": grp.stats()["grid"]}
-        grp.close()
-    print(json.dumps({"metric": "SHT/s, uneven batch of 64 transforms in one persistent launch per phase",
-                      "unit": "SHT/s", "n_gpus": 1, "data": "synthetic",
+        for mode in ("persistent", "batched"):
+            kw = {} if mode == "persistent" else {"tune_file": os.path.join(tmp, f"tune_{dname}.json"),
+                                                  "plan_cache_dir": tmp}
+            grp = Group(Ns, fields, dtype=dt, mode=mode, **kw)
+            betas = [torch.from_numpy(inputs.make_beta(N, f, 4100 + i)).to(dt).cuda()
+                     for i, (N, f) in enumerate(zip(Ns, fields))]
+            fs = [torch.zeros((f, 2 * N, 4 * N - 1), dtype=dt, device="cuda") for N, f in zip(Ns, fields)]
+            grp.bind(betas, fs)
+            t0 = time.perf_counter()
+            grp.tune()
+            t_tune = time.perf_counter() - t0
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                grp.capture("fwd", s)
+                grp.capture("inv", s)
+                tf = timer.time(lambda: grp.replay("fwd", s), reps=max(3, args.steps))
+                ti = timer.time(lambda: grp.replay("inv", s), reps=max(3, args.steps))
+            st = grp.stats()
+            out[f"{dname}_{mode}"] = {"fwd_ms": tf * 1e3, "inv_ms": ti * 1e3,
+                                      "sht_per_s": 2 * sum(fields) / (tf + ti), "tune_s": t_tune,
+                                      "choices": st.get("classes", st.get("grid"))}
+            print(json.dumps({"uneven": {f"{dname}_{mode}": out[f"{dname}_{mode}"]}}), flush=True)
+            grp.close()
+            del betas, fs
+            torch.cuda.empty_cache()
+    print(json.dumps({"metric": "SHT/s, uneven batch of 64 transforms", "unit": "SHT/s", "n_gpus": 1,
+                      "data": "synthetic",
                       "config": {"workload": "64 transforms, N in {128,256,512,1024}, 1-4 fields (seed 4000)",
                                  "fields": sum(fields)}, "results": out}), flush=True)
+
+
+def rank_study(args):
+    """Sampling and rank study (Section 5, Fig. `point`): the forward and
+    inverse ALT of one order (m = N where the partition yields butterflies)
+    with IDs from mock-Chebyshev or random rows and
+    adaptive rank r_k in {50, 100, 150}, IDs as written in Section 2.1 (no
+    verification, truncated butterflies kept), plus a tolerance sweep; errors
+    eps_fwd / eps_inv on 256 sampled rows against the oracle's direct
+    products (Section 5), and on all rows; plan shape and apply time."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2004_11346_amd.sht as S
+    from paper_2004_11346_amd import inputs
+    from paper_2004_11346_amd import lib as L
+    torch.cuda.init()
+    timer = Timer()
+    out = []
+    # (N, m): m = N as in Section 5 where butterflies exist (from N = 2048 with
+    # n0 = 512), and m = N / 2 at N = 1024
+    cases = [(1024, 512), (2048, 2048), (4096, 4096)]
+    variants = []
+    for rk in (50, 100, 150):
+        for smp in ("cheb", "rand"):
+            variants.append({"rk": rk, "sampling": smp, "eps": 1e-10, "id_check": 0})
+    for eps in (1e-6, 1e-8, 1e-12):
+        variants.append({"rk": 150, "sampling": "cheb", "eps": eps, "id_check": 0})
+    for eps in (1e-10, 1e-12):
+        variants.append({"rk": 150, "sampling": "cheb", "eps": eps, "id_check": 1})
+    for N, m in cases:
+        M = 4 * N - 1
+        beta_np = inputs.make_beta(N, 1, 6, dist="half")
+        beta = torch.from_numpy(beta_np).cuda()
+        ref = oracle.alt_forward_orders(N, beta_np[0], [m])
+        rng = np.random.Generator(np.random.PCG64(6000 + N))
+        rows = np.sort(rng.choice(2 * N, size=min(256, 2 * N), replace=False))
+        gin_np = inputs.make_grid(N, 1, 7)[0][:, [m % M, (-m) % M]].T.copy()
+        refi = oracle.alt_transpose_orders(N, gin_np[None], [m], weights=True)[0]
+        kidx = np.sort(rng.choice(2 * N - m, size=min(256, 2 * N - m), replace=False))
+        gin = torch.zeros((1, 2 * N, M), dtype=torch.complex128, device="cuda")
+        gin[0, :, m % M] = torch.from_numpy(gin_np[0]).cuda()
+        gin[0, :, (-m) % M] = torch.from_numpy(gin_np[1]).cuda()
+        for v in variants:
+            smp = L.SHT_SAMPLE_MOCK_CHEB if v["sampling"] == "cheb" else L.SHT_SAMPLE_RANDOM
+            t0 = time.perf_counter()
+            p = S.Plan(N, 1, method="idbf", m_lo=m, m_hi=m, eps=v["eps"], rk=v["rk"], sampling=smp,
+                       id_check=v["id_check"], leaf=32, n0=512)
+            tb = time.perf_counter() - t0
+            g = torch.zeros((1, 2 * N, M), dtype=torch.complex128, device="cuda")
+            bo = torch.zeros((1, 4 * N * N), dtype=torch.complex128, device="cuda")
+            tf = timer.time(lambda: p.alt(m, m, "fwd", beta, g), reps=3)
+            ti = timer.time(lambda: p.alt(m, m, "inv", gin, bo), reps=3)
+            gh = g[0].cpu().numpy()
+            got = np.stack([gh[:, m % M], gh[:, (-m) % M]])
+            k_of, m_of = inputs.layout(N)
+            boh = bo[0].cpu().numpy()
+            goti = np.stack([boh[m_of == m], boh[m_of == -m]])
+            st = p.stats()["program"]
+            r = dict(v, N=N, m=m, plan_build_s=tb, alt_fwd_ms=tf * 1e3, alt_inv_ms=ti * 1e3,
+                     eps_fwd_256=rel_l2(got[:, rows], ref[0][:, rows]), eps_fwd_all=rel_l2(got, ref[0]),
+                     eps_inv_256=rel_l2(goti[:, kidx], refi[:, kidx]),
+                     eps_inv_all=rel_l2(goti, refi[:, : 2 * N - m]),
+                     stored_entries=st["stored_entries"], generated_entries=st["generated_entries"],
+                     dense_entries=st["dense_entries"], blocks_butterfly=st["blocks_butterfly"],
+                     max_rank=st["max_rank"])
+            out.append(r)
+            print(json.dumps({"rank_study": r}), flush=True)
+            p.close()
+    print(json.dumps({"metric": "ALT error vs ID sampling, adaptive rank and tolerance",
+                      "unit": "relative l2", "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": "single order, leaf 32, n0 512, IDs as in Section 2.1",
+                                 "cases": cases}, "results": out}), flush=True)
 
 
 def fp32_legs(S, inputs, timer, N, batch, beta_np, no_check):
@@ -463,6 +608,9 @@ def main():
     if args.workload == "uneven":
         uneven(args)
         return
+    if args.workload == "rank-study":
+        rank_study(args)
+        return
 
     import numpy as np
     import torch
@@ -502,19 +650,25 @@ def main():
     ms_per_step = e0.elapsed_time(e1) / args.steps
     value = 2.0 * batch / (ms_per_step / 1e3)
 
-    # dominant kernel: timed alone, per launch, with HIP events that the
-    # library records on the stream the kernel runs on
+    # ALT rates, then the kernels of one step (forward SHT, then inverse SHT),
+    # each bracketed by HIP events that the library records on the stream the
+    # kernel is launched on
     g = plan.empty_grid()
-    t_alt_fwd = timer.time(lambda: plan.alt(0, 2 * N - 1, "fwd", beta, g), reps=max(3, args.steps))
-    t_alt_inv = timer.time(lambda: plan.alt(0, 2 * N - 1, "inv", g, bout), reps=max(3, args.steps))
     reps = max(3, args.steps)
+    t_alt_fwd = timer.time(lambda: plan.alt(0, 2 * N - 1, "fwd", beta, g), reps=reps)
+    t_alt_inv = timer.time(lambda: plan.alt(0, 2 * N - 1, "inv", g, bout), reps=reps)
     plan.profile(True)
     for _ in range(reps):
-        plan.alt(0, 2 * N - 1, "fwd", beta, g)
-    kern = plan.profile_report()
+        plan.forward(beta, out=f)
+    kern_fwd = plan.profile_report()
+    plan.profile(True)
+    for _ in range(reps):
+        plan.inverse(f, out=bout)
+    kern_inv = plan.profile_report()
     plan.profile(False)
     stats = plan.stats()
-    roof, roof2 = roofline(method, N, batch, args.dtype, stats, kern, reps)
+    roof, step_kern = step_roofline(method, N, batch, args.dtype, stats.get("program", {}), kern_fwd, kern_inv,
+                                    reps)
 
     out = {
         "metric": "SHT/s + ALT Gcoef/s at N=1024/4096, IDBF vs dense, FP64 & FP32, vs FP64 oracle",
@@ -536,8 +690,8 @@ def main():
         "alt_gcoef_per_s_inv": batch * 4 * N * N / t_alt_inv / 1e9,
         "plan_build_s": t_build,
         "roofline": roof,
-        "roofline_other": roof2,
-        "alt_kernels_fwd": kern,
+        "step_kernels": step_kern,
+        "plan_shape": plan_shape(stats),
     }
 
     if not args.no_check:
@@ -584,6 +738,20 @@ def main():
                 for d in ("fwd", "inv"):
                     det[f"idbf_speedup_alt_{d}_b{bb}"] = (det[f"dense_b{bb}"][f"alt_{d}_ms"] /
                                                           det[f"idbf_b{bb}"][f"alt_{d}_ms"])
+        if method == "idbf":
+            # butterflies from 128 columns (leaf 32, the paper's placement at
+            # this size) beside the size-chosen default plan
+            t0 = time.perf_counter()
+            p = S.Plan(N, batch, dtype=cdt, method="idbf", leaf=32)
+            tb = time.perf_counter() - t0
+            ga = p.empty_grid()
+            ob = p.empty_coefs()
+            taf = timer.time(lambda: p.alt(0, 2 * N - 1, "fwd", beta, ga), reps=3)
+            tai = timer.time(lambda: p.alt(0, 2 * N - 1, "inv", ga, ob), reps=3)
+            det[f"idbf_leaf32_b{batch}"] = {"alt_fwd_ms": taf * 1e3, "alt_inv_ms": tai * 1e3, "plan_build_s": tb,
+                                            "plan_shape": plan_shape(p.stats())}
+            p.close()
+            torch.cuda.empty_cache()
         if args.dtype == "f64" and method == "idbf":
             det.update(fp32_legs(S, inputs, timer, N, batch, beta_np, args.no_check))
         out["details"] = det

@@ -34,9 +34,11 @@
  *              the work has completed.
  *
  * Ownership: a plan owns every device array it allocates (factor streams,
- * tables, workspace).  A plan is immutable after creation; calls that use the
- * same plan on different streams at the same time race on its workspace and
- * must be serialised by the caller.
+ * tables, workspace).  Its factors are immutable after creation.  A plan may
+ * be used from several host threads and streams: calls on one plan are
+ * ordered by the plan (a call enqueued on stream B after a call on stream A
+ * first makes B wait for A's work on the plan), because they share the plan's
+ * workspace.  Independent plans run concurrently.
  *
  * Errors: every int-returning call returns SHT_OK (0) or a negative SHT_ERR_*
  * code; no exception crosses the ABI.  Kernels never abort: NaN and Inf in the
@@ -60,7 +62,10 @@ extern "C" {
 #define SHT_ERR_OOM (-3)          /* host or device allocation failed */
 #define SHT_ERR_HIP (-4)          /* a HIP runtime call failed (detail kept) */
 #define SHT_ERR_PLAN (-5)         /* plan construction failed numerically */
-#define SHT_ERR_MISALIGNED (-6)   /* buffer not aligned to its element size */
+#define SHT_ERR_PLAN_CORRUPT (-7) /* a cached plan file failed its header or
+                                     checksum test (see cache_dir) */
+#define SHT_ERR_MISALIGNED (-6)   /* buffer not aligned to its complex element
+                                     (16 bytes FP64, 8 bytes FP32) */
 
 /* element types of beta / f / g */
 #define SHT_F64 0
@@ -85,6 +90,12 @@ extern "C" {
                                 relative) */
 #define SHT_F32_SPLIT_BF16_6 2 /* six products of three BF16 parts per value
                                   (FP32 accuracy on the BF16 matrix cores) */
+
+/* phi DFT schedule (sht_plan_opts.dft_schedule) */
+#define SHT_DFT_AUTO 0      /* by length and type (below) */
+#define SHT_DFT_ROWS 1      /* one row per workgroup in LDS, mixed-radix passes */
+#define SHT_DFT_RADER 2     /* prime M: Rader's length-(M-1) convolution in LDS */
+#define SHT_DFT_FOUR_STEP 3 /* M = M1 M2: two kernels through a grid-sized buffer */
 
 /* ID row sampling (Section 2.1) */
 #define SHT_SAMPLE_MOCK_CHEB 0
@@ -123,6 +134,29 @@ typedef struct sht_plan_opts {
                           factors (default 0 and -1 = all).  A plan restricted
                           to a range serves sht_alt_apply inside it (one GPU's
                           share of the orders); the full transforms need all. */
+    int dft_schedule;  /* SHT_DFT_AUTO (default): rows in LDS when the row fits
+                          and M is not a prime above 13; Rader when M is prime
+                          and M - 1 fits; else four-step.  The others force a
+                          schedule (plan creation fails with UNSUPPORTED where
+                          it does not apply); the results agree to rounding. */
+    int id_check;      /* 1 (default): every ID samples at least n + 8 rows, is
+                          verified on other rows (recomputed from all rows if
+                          the check fails), and a butterfly with an ID cut at
+                          r_k becomes a regenerated dense block.  0: the IDs
+                          of Section 2.1 as written (t min(n, r_k) sampled
+                          rows, no check, truncated butterflies kept), for
+                          the sampling and rank study of Section 5. */
+    const char *cache_dir; /* NULL (default): no plan cache.  Else a directory
+                          where fast-form plans are stored after their first
+                          build and reloaded by later plans with the same N and
+                          factor options (eps, n0, leaf, rk, oversample,
+                          rsvd_r, rsvd_q, sampling, seed, f32_mode, min_idbf,
+                          dense_gen, m_lo, m_hi, id_check; batch, dtype and the DFT
+                          schedule do not enter).  A file that fails its
+                          header or checksum test (SHT_ERR_PLAN_CORRUPT from
+                          sht_plan_cache_verify) is rebuilt and rewritten; the
+                          plan statistics report "plan_cache": "hit", "miss",
+                          "corrupt_rebuilt" or "off". */
 } sht_plan_opts;
 
 void sht_plan_opts_default(sht_plan_opts *opts);
@@ -137,6 +171,28 @@ int sht_plan_create(int N, int batch, int dtype, int method,
                     const sht_plan_opts *opts, sht_plan_t **out);
 
 void sht_plan_destroy(sht_plan_t *plan);
+
+/* Check a cached plan file (see sht_plan_opts.cache_dir): SHT_OK,
+ * SHT_ERR_PLAN_CORRUPT (bad magic or format version, truncated, checksum
+ * mismatch) or SHT_ERR_INVALID_ARG (cannot be read). */
+int sht_plan_cache_verify(const char *path);
+
+/* File name of the cached plan of degree N with these options under
+ * opts->cache_dir (NUL-terminated, at most `cap` bytes); returns the length
+ * needed including the NUL, or a negative error. */
+int sht_plan_cache_path(int N, const sht_plan_opts *opts, char *path, size_t cap);
+
+/* Graph mode (Section 1: the steady-state forward, inverse and adjoint calls
+ * of a plan).  With enable = 1, each sht_forward / sht_inverse /
+ * sht_backward call is served from a hipGraph: the first call with a given
+ * (direction, input, output) triple records the call's kernels into a graph
+ * (captured on a stream of the plan, so any caller stream, including the
+ * default one, works) and every call launches the instantiated graph on the
+ * caller's stream.  Results equal the eager calls bit for bit.  Graphs are
+ * kept per buffer triple (at most 16 per plan, least recently used dropped
+ * first); enable = 0 drops them.  Kernel timing (sht_profile) does not see
+ * kernels inside graphs. */
+int sht_set_graph_capture(sht_plan_t *plan, int enable);
 
 /* Forward SHT (Section 1): beta [batch][4N^2] -> f [batch][2N][M].
  * ALT for every order, parity split (Section 3.1.2), then the phi synthesis
@@ -169,6 +225,24 @@ int sht_backward(const sht_plan_t *plan, const void *grad_f, void *grad_beta, vo
  * the caller.  Every byte read from the array is written earlier in the same
  * call, so nothing needs clearing between calls. */
 int sht_inverse_noalloc(const sht_plan_t *plan, const void *f, void *beta, void *stream);
+
+/* Real fields (Section 1, the expansion of f with real values).  A real f
+ * has beta_{k,-m} = conj(beta_{k,m}) (the same Pbar_k^{|m|} serves both signs
+ * of m), so only the orders m >= 0 are stored:
+ *   beta_half  [nreal][N (2N + 1)] complex: orders m = 0 .. 2N-1, inside an
+ *              order the degrees k = m .. 2N-1 (order m starts at
+ *              2N m - m (m - 1) / 2); the imaginary parts at m = 0 are
+ *              ignored by the forward transform and returned as 0;
+ *   f          [nreal][2N][M] real (double or float as the plan's dtype).
+ * Fields 2p and 2p + 1 are carried as one complex field z = f1 + i f2, so a
+ * plan of `batch` complex fields transforms up to 2 batch real fields at the
+ * cost of `batch` complex ones: the ALT has 2 real right-hand sides per real
+ * field instead of 4, and one complex phi DFT serves two real rows.
+ * 1 <= nreal <= 2 batch (the ALT always runs over all `batch` pairs).
+ * Buffers aligned to the element type.  sht_inverse_real is the exact left
+ * inverse of sht_forward_real on real band-limited grids. */
+int sht_forward_real(const sht_plan_t *plan, int nreal, const void *beta_half, void *f, void *stream);
+int sht_inverse_real(const sht_plan_t *plan, int nreal, const void *f, void *beta_half, void *stream);
 
 /* ALT only, for the orders with m_lo <= |m| <= m_hi (both signs), no DFT
  * (Section 1, ALT; Section 3.1.1).
@@ -220,6 +294,29 @@ const char *sht_last_error_detail(void);
 typedef struct sht_group sht_group_t;
 
 int sht_group_create(int n, const int *Ns, const int *fields, int dtype, sht_group_t **out);
+
+/* Group execution modes.
+ *   SHT_GROUP_PERSISTENT: the persistent kernels above (plain ALT).
+ *   SHT_GROUP_BATCHED: the transforms of each distinct degree N form one
+ *     batch of sum(fields) fields applied by one plan (plain or fast form),
+ *     so many fields share the matrix-core paths of the per-plan kernels;
+ *     each transform's fields are copied into and out of per-degree staging
+ *     buffers (a degree with a single transform uses its buffers directly).
+ *     sht_group_tune times, per degree, the plain form and fast-form plans
+ *     with several leaf sizes (Section 2.2; the smallest block given a
+ *     butterfly) on the bound buffers and keeps the fastest; choices are
+ *     cached in tune_file (one JSON entry per (arch, N, R = 4 fields, dtype))
+ *     and read back when a group is created.  1 <= N <= 8192, fields >= 1. */
+#define SHT_GROUP_PERSISTENT 0
+#define SHT_GROUP_BATCHED 1
+typedef struct sht_group_opts {
+    int mode;                   /* SHT_GROUP_PERSISTENT (default) or SHT_GROUP_BATCHED */
+    const char *tune_file;      /* batched: JSON file of tuned choices (read at create, written by tune); NULL: none */
+    const char *plan_cache_dir; /* batched: plan cache directory (sht_plan_opts.cache_dir) of its plans */
+} sht_group_opts;
+void sht_group_opts_default(sht_group_opts *opts);
+int sht_group_create_ex(int n, const int *Ns, const int *fields, int dtype, const sht_group_opts *opts,
+                        sht_group_t **out);
 void sht_group_destroy(sht_group_t *grp);
 
 /* Bind device buffers: beta[i] [fields_i][4 N_i^2] and f[i] [fields_i][2 N_i][4 N_i - 1]

@@ -19,6 +19,11 @@ writes out:
   phi_j = 2 pi (j + 1/2)/(4N - 1)).
 * ``sht_forward`` / ``sht_inverse`` / ``sht_adjoint`` -- compositions of the
   above (Section 1; Section 3.1.1).
+* ``real_to_full`` / ``full_to_real`` / ``sht_forward_real`` /
+  ``sht_inverse_real`` -- real fields: in the expansion of f (Section 1) the
+  same Pbar_k^{|m|} multiplies e^{i m phi} and e^{-i m phi}, so f is real
+  exactly when beta_{k,-m} = conj(beta_{k,m}) (and beta_{k,0} is real); the
+  real transforms are the complex ones on coefficients extended that way.
 
 Parity status of each function is recorded in the tests that pin it
 (``tests/test_oracle_pins.py``); every function above is pinned there against
@@ -207,6 +212,51 @@ def dft_analysis(N: int, f_rows: np.ndarray, scale: float | None = None) -> np.n
     _chk(_load().oracle_dft_analysis(N, _ptr(f_rows), f_rows.shape[0], float(scale), _ptr(out)),
          "dft_analysis")
     return out
+
+
+def real_to_full(N: int, beta_half: np.ndarray) -> np.ndarray:
+    """Coefficients of orders m >= 0 (orders 0..2N-1, degrees k = m..2N-1 inside
+    each) -> the full m-major coefficients of the real field they describe:
+    beta_{k,-m} = conj(beta_{k,m}), beta_{k,0} real (its imaginary part
+    dropped)."""
+    n = 2 * N
+    beta_half = _c128(beta_half)
+    assert beta_half.shape == (N * (2 * N + 1),)
+    full = np.zeros(4 * N * N, dtype=np.complex128)
+    h = 0
+    for m in range(n):
+        seg = beta_half[h:h + n - m]
+        h += n - m
+        o = coef_offset(N, m)
+        if m == 0:
+            full[o:o + n] = seg.real
+        else:
+            full[o:o + n - m] = seg
+            o2 = coef_offset(N, -m)
+            full[o2:o2 + n - m] = np.conj(seg)
+    return full
+
+
+def full_to_real(N: int, beta: np.ndarray) -> np.ndarray:
+    """The orders m >= 0 of full m-major coefficients, in the half layout."""
+    n = 2 * N
+    beta = _c128(beta)
+    out = []
+    for m in range(n):
+        o = coef_offset(N, m)
+        out.append(beta[o:o + n - m])
+    return np.concatenate(out)
+
+
+def sht_forward_real(N: int, beta_half: np.ndarray) -> np.ndarray:
+    """Forward SHT of a real field given by its orders m >= 0: real f[2N, M]
+    (the real part; the imaginary part of the complex transform is rounding)."""
+    return sht_forward(N, real_to_full(N, beta_half)).real
+
+
+def sht_inverse_real(N: int, f: np.ndarray) -> np.ndarray:
+    """Inverse SHT of a real grid f[2N, M]: its coefficients of orders m >= 0."""
+    return full_to_real(N, sht_inverse(N, np.asarray(f, dtype=np.float64).astype(np.complex128)))
 
 
 def sht_forward(N: int, beta: np.ndarray) -> np.ndarray:

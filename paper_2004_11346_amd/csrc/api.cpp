@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -18,6 +19,7 @@
 
 #include "idbf.h"
 #include "kernels.h"
+#include "plan_cache.h"
 #include "prof.h"
 #include "sht_internal.h"
 
@@ -38,13 +40,16 @@ struct sht_plan {
     // device tables
     double *d_xh = nullptr, *d_wh = nullptr, *d_dmant = nullptr, *d_coef = nullptr, *d_coef2 = nullptr;
     int *d_dexp = nullptr;
-    double *d_tw2 = nullptr;
-    float *d_tw2f = nullptr;
-    int *d_src_pos = nullptr;
+    // phi DFT tables and the four-step intermediate rows
+    double *d_tab = nullptr, *d_ctab = nullptr, *d_bspec = nullptr;
+    float *d_tabf = nullptr, *d_ctabf = nullptr, *d_bspecf = nullptr;
+    int *d_src_pos = nullptr, *d_src_pos2 = nullptr, *d_inslot = nullptr, *d_outslot = nullptr;
+    void *d_dft_scr = nullptr;
     dev::DenseTables dense;
     dev::DftPlan dft;
     // workspace
     void *d_g = nullptr;         // [batch][2N][M] complex (dtype)
+    void *d_bz = nullptr;        // [batch][4N^2] complex: coefficients of real-field pairs
     void *d_X = nullptr;         // dense path FP64 panels
     void *d_Y = nullptr;
     int64_t *d_x_off = nullptr;
@@ -60,24 +65,53 @@ struct sht_plan {
     bool profiling = false;
     mutable prof::Recorder recorder;
     prof::Recorder *rec() const { return profiling ? &recorder : nullptr; }
+    // calls on one plan are ordered: the mutex serialises host threads, the
+    // event makes a call on another stream wait for the previous call's work
+    mutable std::mutex mu;
+    mutable hipEvent_t last_done = nullptr;
+    mutable hipStream_t last_stream = nullptr;
+    mutable bool has_last = false;
+    // graph mode: instantiated graphs per (direction, input, output)
+    struct GraphEntry {
+        int dir;
+        const void *in;
+        void *out;
+        hipGraphExec_t exec;
+        uint64_t used;
+    };
+    bool graph_mode = false;
+    hipStream_t cap_stream = nullptr;
+    mutable std::vector<GraphEntry> graphs;
+    mutable uint64_t tick = 0;
+    void drop_graphs() const;
     ~sht_plan();
 };
+
+void sht_plan::drop_graphs() const {
+    for (GraphEntry &g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+}
 
 static void dfree(void *p) {
     if (p) (void)hipFree(p);
 }
 
 sht_plan::~sht_plan() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (last_done) (void)hipEventDestroy(last_done);
     dfree(d_xh);
     dfree(d_wh);
     dfree(d_dmant);
     dfree(d_coef);
     dfree(d_coef2);
     dfree(d_dexp);
-    dfree(d_tw2);
-    dfree(d_tw2f);
-    dfree(d_src_pos);
+    for (void *q : {(void *)d_tab, (void *)d_ctab, (void *)d_bspec, (void *)d_tabf, (void *)d_ctabf,
+                    (void *)d_bspecf, (void *)d_src_pos, (void *)d_src_pos2, (void *)d_inslot,
+                    (void *)d_outslot, d_dft_scr})
+        dfree(q);
     dfree(d_g);
+    dfree(d_bz);
     dfree(d_X);
     dfree(d_Y);
     dfree(d_x_off);
@@ -116,7 +150,7 @@ int check_ptr(const void *p, size_t align) {
         return SHT_ERR_INVALID_ARG;
     }
     if (reinterpret_cast<uintptr_t>(p) % align) {
-        set_error_detail("buffer not aligned to its element size");
+        set_error_detail("buffer not aligned to its complex element (16 bytes FP64, 8 bytes FP32)");
         return SHT_ERR_MISALIGNED;
     }
     return SHT_OK;
@@ -146,6 +180,8 @@ void sht_plan_opts_default(sht_plan_opts *o) {
     o->dense_gen = 1;
     o->m_lo = 0;
     o->m_hi = -1;
+    o->dft_schedule = SHT_DFT_AUTO;
+    o->id_check = 1;
 }
 
 const char *sht_strerror(int code) {
@@ -157,6 +193,7 @@ const char *sht_strerror(int code) {
         case SHT_ERR_HIP: return "HIP runtime error";
         case SHT_ERR_PLAN: return "plan construction failed";
         case SHT_ERR_MISALIGNED: return "misaligned buffer";
+        case SHT_ERR_PLAN_CORRUPT: return "corrupt plan file";
         default: return "unknown error";
     }
 }
@@ -191,6 +228,8 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
     if (opts) p->opts = *opts;
     HIP_TRY(hipGetDevice(&p->device), "hipGetDevice");
     HIP_TRY((hipError_t)noalloc_scratch_init(p->device), "fixed scratch address");
+    HIP_TRY(dev::dft_init(), "DFT kernel attributes");
+    HIP_TRY(hipEventCreateWithFlags(&p->last_done, hipEventDisableTiming), "plan event");
     if (p->opts.f32_mode != SHT_F32_VALU && p->opts.f32_mode != SHT_F32_SPLIT_BF16 &&
         p->opts.f32_mode != SHT_F32_SPLIT_BF16_6)
         return SHT_ERR_INVALID_ARG;
@@ -207,8 +246,6 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
         set_error_detail("order ranges apply to the fast form (the plain form stores no per-order data)");
         return SHT_ERR_UNSUPPORTED;
     }
-    // the phi DFT holds a row in LDS; without it the plan serves sht_alt_apply only
-    p->dft_ok = dev::dft_supported(p->M, dtype);
 
     LegendreTables lt;
     try {
@@ -236,38 +273,69 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
     p->dense.coef = p->d_coef;
     p->dense.coef2 = p->d_coef2;
 
-    // phi DFT: radices and the e^{i pi r / M} table (long double, rounded)
+    // phi DFT: schedule and tables for this length and type
     {
-        std::vector<int> f, bl, sp;
-        dev::dft_passes(p->M, f, bl, sp);
-        p->dft.N = N;
-        p->dft.M = p->M;
-        p->dft.nrad = (int)f.size();
-        for (size_t i = 0; i < f.size(); ++i) {
-            p->dft.radix[i] = f[i];
-            p->dft.blen[i] = bl[i];
+        dev::DftHost dh;
+        if (p->opts.dft_schedule < SHT_DFT_AUTO || p->opts.dft_schedule > SHT_DFT_FOUR_STEP) {
+            set_error_detail("unknown phi DFT schedule");
+            return SHT_ERR_INVALID_ARG;
         }
-        if ((rc = upload(sp, &p->d_src_pos, "upload DFT positions"))) return rc;
-        p->dft.src_pos = p->d_src_pos;
-        std::vector<double> tw(4 * (size_t)p->M);
-        std::vector<float> twf(4 * (size_t)p->M);
-        const long double pi = 3.141592653589793238462643383279502884L;
-        for (int r = 0; r < 2 * p->M; ++r) {
-            long double ph = pi * r / p->M;
-            tw[2 * r] = (double)cosl(ph);
-            tw[2 * r + 1] = (double)sinl(ph);
-            twf[2 * r] = (float)cosl(ph);
-            twf[2 * r + 1] = (float)sinl(ph);
+        dev::dft_build(p->M, dtype, dh, p->opts.dft_schedule);
+        if (p->opts.dft_schedule != SHT_DFT_AUTO && dh.kind == dev::kDftNone) {
+            set_error_detail("the requested phi DFT schedule does not apply to this length and type");
+            return SHT_ERR_UNSUPPORTED;
         }
-        if ((rc = upload(tw, &p->d_tw2, "upload twiddles"))) return rc;
-        if ((rc = upload(twf, &p->d_tw2f, "upload twiddles"))) return rc;
-        p->dft.tw2 = p->d_tw2;
-        p->dft.tw2f = p->d_tw2f;
+        dev::DftPlan &d = p->dft;
+        d.N = N;
+        d.M = p->M;
+        d.kind = dh.kind;
+        p->dft_ok = dh.kind != dev::kDftNone;
+        if (dh.radix.size() > 24 || dh.radix2.size() > 24) return SHT_ERR_UNSUPPORTED;
+        d.nrad = (int)dh.radix.size();
+        for (int i = 0; i < d.nrad; ++i) {
+            d.radix[i] = dh.radix[i];
+            d.blen[i] = dh.blen[i];
+        }
+        d.nrad2 = (int)dh.radix2.size();
+        for (int i = 0; i < d.nrad2; ++i) {
+            d.radix2[i] = dh.radix2[i];
+            d.blen2[i] = dh.blen2[i];
+        }
+        d.M1 = dh.M1;
+        d.M2 = dh.M2;
+        d.chunk1 = dh.chunk1;
+        d.chunk2 = dh.chunk2;
+        if ((rc = upload(dh.tab, &p->d_tab, "upload DFT table"))) return rc;
+        if ((rc = upload(dh.tabf, &p->d_tabf, "upload DFT table"))) return rc;
+        if ((rc = upload(dh.ctab, &p->d_ctab, "upload DFT table"))) return rc;
+        if ((rc = upload(dh.ctabf, &p->d_ctabf, "upload DFT table"))) return rc;
+        if ((rc = upload(dh.src_pos, &p->d_src_pos, "upload DFT positions"))) return rc;
+        if ((rc = upload(dh.src_pos2, &p->d_src_pos2, "upload DFT positions"))) return rc;
+        if ((rc = upload(dh.inslot, &p->d_inslot, "upload DFT slots"))) return rc;
+        if ((rc = upload(dh.outslot, &p->d_outslot, "upload DFT slots"))) return rc;
+        if ((rc = upload(dh.bspec, &p->d_bspec, "upload DFT spectrum"))) return rc;
+        if ((rc = upload(dh.bspecf, &p->d_bspecf, "upload DFT spectrum"))) return rc;
+        d.tab = p->d_tab;
+        d.tabf = p->d_tabf;
+        d.ctab = p->d_ctab;
+        d.ctabf = p->d_ctabf;
+        d.src_pos = p->d_src_pos;
+        d.src_pos2 = p->d_src_pos2;
+        d.inslot = p->d_inslot;
+        d.outslot = p->d_outslot;
+        d.bspec = p->d_bspec;
+        d.bspecf = p->d_bspecf;
+        if (dh.kind == dev::kDftFourStep) {
+            HIP_TRY(hipMalloc(&p->d_dft_scr, 2 * elt_size(dtype) * (size_t)batch * 2 * N * p->M),
+                    "DFT intermediate rows");
+            d.scratch = p->d_dft_scr;
+        }
     }
 
     // workspace
     const size_t gbytes = 2 * elt_size(dtype) * (size_t)batch * 2 * N * p->M;
     HIP_TRY(hipMalloc(&p->d_g, gbytes), "workspace g");
+    HIP_TRY(hipMalloc(&p->d_bz, 2 * elt_size(dtype) * (size_t)batch * 4 * N * N), "workspace real-field coefficients");
     if (method == SHT_DENSE) {
         // FP64 panels: X [sum of half-matrix columns][R], Y [4N^2][R]
         std::vector<int64_t> xo(4 * (size_t)N + 1, 0);
@@ -328,6 +396,7 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
         if (brc) return brc;
         p->stats = hp.stats_json;
     }
+    p->opts.cache_dir = nullptr;  // the caller's string is not kept
     p->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     HIP_TRY(hipDeviceSynchronize(), "plan upload");
     *out = p.release();
@@ -371,7 +440,8 @@ int sht_plan_stats(const sht_plan_t *p, char *json, size_t cap) {
 
 static int full_transform_ok(const sht_plan_t *p) {
     if (!p->dft_ok) {
-        set_error_detail("the phi DFT row does not fit in LDS for this N and dtype; use sht_alt_apply");
+        set_error_detail("no phi DFT schedule for this N and dtype (a prime 4N-1 whose row exceeds LDS, or a "
+                         "length without a four-step split); use sht_alt_apply");
         return SHT_ERR_UNSUPPORTED;
     }
     if (p->opts.m_lo != 0 || p->opts.m_hi != 2 * p->N - 1) {
@@ -419,6 +489,90 @@ static int run_alt(const sht_plan_t *p, int a_lo, int a_hi, int dir, const void 
     return SHT_OK;
 }
 
+}  // extern "C"
+
+// Enqueue one call's work on stream s in the plan's order (see sht.h,
+// Ownership): under the plan's lock, wait for the previous call's work if it
+// ran on another stream, enqueue, record.  A stream that the caller is
+// capturing into a graph is left alone (the caller orders its captures).
+template <typename F>
+static int ordered(const sht_plan_t *p, hipStream_t s, F &&enqueue) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cs), "stream capture status");
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    if (!capturing && p->has_last && p->last_stream != s)
+        HIP_TRY(hipStreamWaitEvent(s, p->last_done, 0), "order after the previous call");
+    const int rc = enqueue(s);
+    if (!capturing) {
+        HIP_TRY(hipEventRecord(p->last_done, s), "record call end");
+        p->last_stream = s;
+        p->has_last = true;
+    }
+    return rc;
+}
+
+// Graph mode: run `enqueue` from an instantiated graph keyed by (dir, in,
+// out), capturing it on the plan's own stream the first time.  Called under
+// the plan's lock (inside ordered()).
+template <typename F>
+static int via_graph(const sht_plan_t *p, int dir, const void *in, void *out, hipStream_t s, F &&enqueue) {
+    sht_plan::GraphEntry *hit = nullptr;
+    for (sht_plan::GraphEntry &g : p->graphs)
+        if (g.dir == dir && g.in == in && g.out == out) hit = &g;
+    if (!hit) {
+        if (p->graphs.size() >= 16) {
+            auto lru = std::min_element(p->graphs.begin(), p->graphs.end(),
+                                        [](const sht_plan::GraphEntry &a, const sht_plan::GraphEntry &b) {
+                                            return a.used < b.used;
+                                        });
+            (void)hipGraphExecDestroy(lru->exec);
+            p->graphs.erase(lru);
+        }
+        prof::Install none(nullptr);  // no timing events inside a graph
+        HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        const int rc = enqueue(p->cap_stream);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return hip_fail(ei, "instantiate graph");
+        p->graphs.push_back({dir, in, out, exec, 0});
+        hit = &p->graphs.back();
+    }
+    hit->used = ++p->tick;
+    HIP_TRY(hipGraphLaunch(hit->exec, s), "launch graph");
+    return SHT_OK;
+}
+
+extern "C" {
+
+int sht_set_graph_capture(sht_plan_t *p, int enable) {
+    if (!p) return SHT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->drop_graphs();
+    p->graph_mode = enable != 0;
+    if (p->graph_mode && !p->cap_stream)
+        HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "capture stream");
+    return SHT_OK;
+}
+
+int sht_plan_cache_verify(const char *path) {
+    if (!path) return SHT_ERR_INVALID_ARG;
+    return idbf::cache_verify(path);
+}
+
+int sht_plan_cache_path(int N, const sht_plan_opts *opts, char *path, size_t cap) {
+    if (!opts || !opts->cache_dir || N < 1) return SHT_ERR_INVALID_ARG;
+    return copy_json(idbf::cache_path(opts->cache_dir, idbf::cache_key(N, *opts)), path, cap);
+}
+
 int sht_alt_apply(const sht_plan_t *p, int m_lo, int m_hi, int dir, const void *in, void *out,
                   void *stream) {
     if (!p) return SHT_ERR_INVALID_ARG;
@@ -431,22 +585,14 @@ int sht_alt_apply(const sht_plan_t *p, int m_lo, int m_hi, int dir, const void *
         return SHT_ERR_INVALID_ARG;
     }
     int rc;
-    if ((rc = check_ptr(in, elt_size(p->dtype)))) return rc;
-    if ((rc = check_ptr(out, elt_size(p->dtype)))) return rc;
-    return run_alt(p, m_lo, m_hi, dir, in, out, (hipStream_t)stream);
+    if ((rc = check_ptr(in, 2 * elt_size(p->dtype)))) return rc;
+    if ((rc = check_ptr(out, 2 * elt_size(p->dtype)))) return rc;
+    return ordered(p, (hipStream_t)stream,
+                   [&](hipStream_t s) { return run_alt(p, m_lo, m_hi, dir, in, out, s); });
 }
 
-int sht_forward(const sht_plan_t *p, const void *beta, void *f, void *stream) {
-    if (!p) return SHT_ERR_INVALID_ARG;
+static int forward_work(const sht_plan_t *p, const void *beta, void *f, hipStream_t s) {
     int rc;
-    if ((rc = check_ptr(beta, elt_size(p->dtype)))) return rc;
-    if ((rc = check_ptr(f, elt_size(p->dtype)))) return rc;
-    if (beta == f) {
-        set_error_detail("f may not alias beta");
-        return SHT_ERR_INVALID_ARG;
-    }
-    if ((rc = full_transform_ok(p))) return rc;
-    hipStream_t s = (hipStream_t)stream;
     if ((rc = run_alt(p, 0, 2 * p->N - 1, SHT_FWD, beta, f, s))) return rc;
     prof::Install inst(p->rec());
     hipError_t e = dev::dft_synthesis(p->dft, p->dtype, p->batch, f, s);
@@ -454,17 +600,39 @@ int sht_forward(const sht_plan_t *p, const void *beta, void *f, void *stream) {
     return SHT_OK;
 }
 
+static int transposed_work(const sht_plan_t *p, const void *f, void *beta, void *g, bool inverse, hipStream_t s) {
+    prof::Install inst(p->rec());
+    hipError_t e = dev::dft_analysis(p->dft, p->dtype, p->batch, inverse ? 1.0 / p->M : 1.0, f, g, s);
+    if (e != hipSuccess) return hip_fail(e, "DFT analysis");
+    return run_alt(p, 0, 2 * p->N - 1, inverse ? SHT_INV : SHT_ADJ, g, beta, s);
+}
+
+int sht_forward(const sht_plan_t *p, const void *beta, void *f, void *stream) {
+    if (!p) return SHT_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_ptr(beta, 2 * elt_size(p->dtype)))) return rc;
+    if ((rc = check_ptr(f, 2 * elt_size(p->dtype)))) return rc;
+    if (beta == f) {
+        set_error_detail("f may not alias beta");
+        return SHT_ERR_INVALID_ARG;
+    }
+    if ((rc = full_transform_ok(p))) return rc;
+    return ordered(p, (hipStream_t)stream, [&](hipStream_t s) {
+        auto work = [&](hipStream_t w) { return forward_work(p, beta, f, w); };
+        return p->graph_mode ? via_graph(p, SHT_FWD, beta, f, s, work) : work(s);
+    });
+}
+
 static int transposed(const sht_plan_t *p, const void *f, void *beta, void *stream, bool inverse) {
     if (!p) return SHT_ERR_INVALID_ARG;
     int rc;
     if ((rc = full_transform_ok(p))) return rc;
-    if ((rc = check_ptr(beta, elt_size(p->dtype)))) return rc;
-    if ((rc = check_ptr(f, elt_size(p->dtype)))) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    prof::Install inst(p->rec());
-    hipError_t e = dev::dft_analysis(p->dft, p->dtype, p->batch, inverse ? 1.0 / p->M : 1.0, f, p->d_g, s);
-    if (e != hipSuccess) return hip_fail(e, "DFT analysis");
-    return run_alt(p, 0, 2 * p->N - 1, inverse ? SHT_INV : SHT_ADJ, p->d_g, beta, s);
+    if ((rc = check_ptr(beta, 2 * elt_size(p->dtype)))) return rc;
+    if ((rc = check_ptr(f, 2 * elt_size(p->dtype)))) return rc;
+    return ordered(p, (hipStream_t)stream, [&](hipStream_t s) {
+        auto work = [&](hipStream_t w) { return transposed_work(p, f, beta, p->d_g, inverse, w); };
+        return p->graph_mode ? via_graph(p, inverse ? SHT_INV : SHT_ADJ, f, beta, s, work) : work(s);
+    });
 }
 
 int sht_inverse(const sht_plan_t *p, const void *f, void *beta, void *stream) {
@@ -475,12 +643,56 @@ int sht_backward(const sht_plan_t *p, const void *grad_f, void *grad_beta, void 
     return transposed(p, grad_f, grad_beta, stream, false);
 }
 
+static int real_args(const sht_plan_t *p, int nreal, const void *a, const void *b) {
+    if (!p) return SHT_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = full_transform_ok(p))) return rc;
+    if (nreal < 1 || nreal > 2 * p->batch) {
+        set_error_detail("nreal must be in [1, 2 batch]");
+        return SHT_ERR_INVALID_ARG;
+    }
+    if ((rc = check_ptr(a, elt_size(p->dtype)))) return rc;
+    return check_ptr(b, elt_size(p->dtype));
+}
+
+int sht_forward_real(const sht_plan_t *p, int nreal, const void *beta_half, void *f, void *stream) {
+    int rc;
+    if ((rc = real_args(p, nreal, beta_half, f))) return rc;
+    return ordered(p, (hipStream_t)stream, [&](hipStream_t s) {
+        prof::Install inst(p->rec());
+        hipError_t e = dev::real_pack(p->dtype, p->N, p->batch, nreal, beta_half, p->d_bz, s);
+        if (e != hipSuccess) return hip_fail(e, "real-field coefficients");
+        int r = run_alt(p, 0, 2 * p->N - 1, SHT_FWD, p->d_bz, p->d_g, s);
+        if (r) return r;
+        prof::Install inst2(p->rec());
+        e = dev::dft_synthesis_real(p->dft, p->dtype, p->batch, nreal, p->d_g, f, s);
+        if (e != hipSuccess) return hip_fail(e, "DFT synthesis");
+        return SHT_OK;
+    });
+}
+
+int sht_inverse_real(const sht_plan_t *p, int nreal, const void *f, void *beta_half, void *stream) {
+    int rc;
+    if ((rc = real_args(p, nreal, f, beta_half))) return rc;
+    return ordered(p, (hipStream_t)stream, [&](hipStream_t s) {
+        prof::Install inst(p->rec());
+        hipError_t e = dev::dft_analysis_real(p->dft, p->dtype, p->batch, nreal, 1.0 / p->M, f, p->d_g, s);
+        if (e != hipSuccess) return hip_fail(e, "DFT analysis");
+        int r = run_alt(p, 0, 2 * p->N - 1, SHT_INV, p->d_g, p->d_bz, s);
+        if (r) return r;
+        prof::Install inst2(p->rec());
+        e = dev::real_unpack(p->dtype, p->N, p->batch, nreal, p->d_bz, beta_half, s);
+        if (e != hipSuccess) return hip_fail(e, "real-field coefficients");
+        return SHT_OK;
+    });
+}
+
 int sht_inverse_noalloc(const sht_plan_t *p, const void *f, void *beta, void *stream) {
     if (!p) return SHT_ERR_INVALID_ARG;
     int rc;
     if ((rc = full_transform_ok(p))) return rc;
-    if ((rc = check_ptr(beta, elt_size(p->dtype)))) return rc;
-    if ((rc = check_ptr(f, elt_size(p->dtype)))) return rc;
+    if ((rc = check_ptr(beta, 2 * elt_size(p->dtype)))) return rc;
+    if ((rc = check_ptr(f, 2 * elt_size(p->dtype)))) return rc;
     const size_t need = 2 * elt_size(p->dtype) * (size_t)p->batch * 2 * p->N * p->M;
     if (need > kNoallocScratchBytes) {
         set_error_detail("sht_inverse_noalloc: the grid of this plan needs " + std::to_string(need) +
@@ -493,11 +705,8 @@ int sht_inverse_noalloc(const sht_plan_t *p, const void *f, void *beta, void *st
         set_error_detail("sht_inverse_noalloc: fixed scratch of this device was not looked up");
         return SHT_ERR_HIP;
     }
-    hipStream_t s = (hipStream_t)stream;
-    prof::Install inst(p->rec());
-    hipError_t e = dev::dft_analysis(p->dft, p->dtype, p->batch, 1.0 / p->M, f, g, s);
-    if (e != hipSuccess) return hip_fail(e, "DFT analysis");
-    return run_alt(p, 0, 2 * p->N - 1, SHT_INV, g, beta, s);
+    return ordered(p, (hipStream_t)stream,
+                   [&](hipStream_t s) { return transposed_work(p, f, beta, g, true, s); });
 }
 
 }  // extern "C"

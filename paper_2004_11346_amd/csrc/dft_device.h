@@ -1,5 +1,20 @@
-// Device body of the length-M phi DFT of one grid row (shared by the per-plan
-// kernel and the grouped persistent kernel).  Included by .hip files only.
+// Device bodies of the length-M phi DFT (Section 1, the phi sums of eq.
+// `sht_fft`), shared by the per-plan kernels and the grouped persistent
+// kernel.  Included by .hip files only.
+//
+// Building blocks:
+//  * a two-level phase table in LDS: e^{i pi r / Mt} = lo[r mod 64] * hi[r / 64]
+//    for r in [0, 2 Mt), 64 + ceil(2 Mt / 64) complex entries (a few KB), filled
+//    from a global table rounded from long double on the host;
+//  * mixed-radix decimation-in-frequency passes over a buffer of `total`
+//    elements made of independent segments of length L0 (a whole row, or the
+//    sub-rows of a four-step pass): a pass of radix R over blocks of length L
+//    splits each block into R interleaved sub-blocks of length L/R with
+//      y[n1 + (L/R) k2] = w_L^{n1 k2} sum_{n2} x[n1 + (L/R) n2] w_R^{n2 k2};
+//    radices up to 13 run as register butterflies, larger primes as R-term
+//    sums; after the passes every segment is in digit-reversed order;
+//  * global loads and stores issued in unrolled groups, so that a thread's
+//    accesses are in flight together.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,34 +35,52 @@ struct Passes {
     int L[24];  // block length before the pass
 };
 
+constexpr int kUnroll = 8;  // global accesses in flight per thread and group
+
 template <typename C>
 __device__ __forceinline__ typename V2<C>::t cmul(typename V2<C>::t a, typename V2<C>::t b) {
     return typename V2<C>::t{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
-// phase e^{sgn * 2 pi i q / M}: table entry 2q mod 2M, conjugated for sgn < 0
+// entries of the two-level table of base Mt
+__host__ __device__ inline int tab_entries(int Mt) { return 64 + (2 * Mt + 63) / 64; }
+
+// e^{sgn i pi r / Mt}, 0 <= r < 2 Mt, from the table in LDS
 template <typename C>
-__device__ __forceinline__ typename V2<C>::t phase(const C *__restrict__ tw2, int idx2, C sgn) {
-    return typename V2<C>::t{tw2[2 * idx2], sgn * tw2[2 * idx2 + 1]};
+__device__ __forceinline__ typename V2<C>::t tw(const typename V2<C>::t *t, int r, C sgn) {
+    typename V2<C>::t p = cmul<C>(t[r & 63], t[64 + (r >> 6)]);
+    p.y *= sgn;
+    return p;
 }
 
-// register butterflies of radix R over blocks of length L
+// copy a table of base Mt from global memory to LDS
+template <typename C>
+__device__ __forceinline__ void load_tab(const C *__restrict__ g, int Mt, typename V2<C>::t *t) {
+    typedef typename V2<C>::t c2;
+    const int n = tab_entries(Mt);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) t[i] = reinterpret_cast<const c2 *>(g)[i];
+}
+
+// register butterflies of radix R over blocks of length L (table base Mt,
+// L divides Mt), `total` elements
 template <typename C, int R>
-__device__ __forceinline__ void pass_reg(typename V2<C>::t *buf, int M, int L, const C *__restrict__ tw2, C sgn) {
+__device__ __forceinline__ void pass_reg(typename V2<C>::t *buf, int total, int L, const typename V2<C>::t *t,
+                                         int Mt, C sgn) {
     typedef typename V2<C>::t c2;
     const int Ls = L / R;
-    const int twoM = 2 * M;
-    c2 wr[R];  // w_R^q = e^{sgn 2 pi i q / R}
+    const int twoM = 2 * Mt;
+    c2 wr[R];  // w_R^q
 #pragma unroll
-    for (int q = 0; q < R; ++q) wr[q] = phase<C>(tw2, (2 * q * (M / R)) % twoM, sgn);
-    const int unitL = 2 * (M / L);  // table step of w_L
-    for (int t = threadIdx.x; t < M / R; t += blockDim.x) {
-        const int b = t / Ls, n1 = t - b * Ls;
-        const int base = b * L + n1;
+    for (int q = 0; q < R; ++q) wr[q] = tw<C>(t, (2 * q * (Mt / R)) % twoM, sgn);
+    const int unitL = 2 * (Mt / L);
+    const int nb = total / R;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const int blk = b / Ls, n1 = b - blk * Ls;
+        const int base = blk * L + n1;
         c2 x[R];
 #pragma unroll
         for (int n2 = 0; n2 < R; ++n2) x[n2] = buf[base + Ls * n2];
-        const int step = (n1 * unitL) % twoM;
+        const int step = n1 * unitL;  // < 2 Mt / R
         int ti = 0;
 #pragma unroll
         for (int k2 = 0; k2 < R; ++k2) {
@@ -58,7 +91,7 @@ __device__ __forceinline__ void pass_reg(typename V2<C>::t *buf, int M, int L, c
                 y.x += p.x;
                 y.y += p.y;
             }
-            if (k2 > 0) y = cmul<C>(y, phase<C>(tw2, ti, sgn));
+            if (k2 > 0) y = cmul<C>(y, tw<C>(t, ti, sgn));
             buf[base + Ls * k2] = y;
             ti += step;
             if (ti >= twoM) ti -= twoM;
@@ -66,23 +99,20 @@ __device__ __forceinline__ void pass_reg(typename V2<C>::t *buf, int M, int L, c
     }
 }
 
-// any radix: every output is an R-term sum; results held in registers until all
+// any radix: every output is an R-term sum held in registers until all
 // threads have read the pass's inputs.  At most MAXO outputs per thread.
 template <typename C, int MAXO>
-__device__ __forceinline__ void pass_sum(typename V2<C>::t *buf, int M, int R, int L, const C *__restrict__ tw2,
-                                         C sgn) {
+__device__ __forceinline__ void pass_sum(typename V2<C>::t *buf, int total, int R, int L, const typename V2<C>::t *t,
+                                         int Mt, C sgn) {
     typedef typename V2<C>::t c2;
     const int Ls = L / R;
-    const int twoM = 2 * M;
-    const int unitR = 2 * (M / R), unitL = 2 * (M / L);
+    const int twoM = 2 * Mt;
+    const int unitR = 2 * (Mt / R), unitL = 2 * (Mt / L);
     c2 out[MAXO];
-    int pos[MAXO];
 #pragma unroll
     for (int j = 0; j < MAXO; ++j) {
         const int o = threadIdx.x + j * blockDim.x;
-        pos[j] = -1;
-        if (o >= M) continue;
-        // o = base + Ls k2 within block b
+        if (o >= total) continue;
         const int b = o / L, rem = o - b * L;
         const int k2 = rem / Ls, n1 = rem - k2 * Ls;
         const int base = b * L + n1;
@@ -90,71 +120,246 @@ __device__ __forceinline__ void pass_sum(typename V2<C>::t *buf, int M, int R, i
         c2 y = c2{(C)0, (C)0};
         int ti = 0;
         for (int n2 = 0; n2 < R; ++n2) {
-            const c2 p = cmul<C>(buf[base + Ls * n2], phase<C>(tw2, ti, sgn));
+            const c2 p = cmul<C>(buf[base + Ls * n2], tw<C>(t, ti, sgn));
             y.x += p.x;
             y.y += p.y;
             ti += step;
             if (ti >= twoM) ti -= twoM;
         }
         const int tl = (int)(((long long)n1 * k2 * unitL) % twoM);
-        out[j] = cmul<C>(y, phase<C>(tw2, tl, sgn));
-        pos[j] = o;
+        out[j] = cmul<C>(y, tw<C>(t, tl, sgn));
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < MAXO; ++j)
-        if (pos[j] >= 0) buf[pos[j]] = out[j];
+    for (int j = 0; j < MAXO; ++j) {
+        const int o = threadIdx.x + j * blockDim.x;
+        if (o < total) buf[o] = out[j];
+    }
 }
 
-// mode 0: synthesis (pre-twiddle e^{+i pi m/M}, sign +1)
-// mode 1: analysis  (sign -1, post-twiddle scale * e^{-i pi m/M})
-// One row by one workgroup: src and dst point at the row (may alias), buf is
-// M complex values of LDS.  MAXO: outputs per thread of the generic pass
-// (radices above 13); 0 when every radix has a register butterfly, which
-// keeps the register budget low enough for two 512-thread rows per CU.
-template <typename C, typename T, int MAXO>
-__device__ __forceinline__ void dft_row(int N, int M, const Passes &ps, const C *__restrict__ tw2,
-                                        const int *__restrict__ src_pos, int mode, C scale, const T *src, T *dst,
-                                        typename V2<C>::t *buf) {
-    typedef typename V2<C>::t c2;
-    const int twoM = 2 * M;
-    const C sgn = mode == 0 ? (C)1 : (C)-1;
-    for (int c = threadIdx.x; c < M; c += blockDim.x) {
-        c2 v = c2{(C)src[2 * c], (C)src[2 * c + 1]};
-        if (mode == 0) {
-            const int m = c <= 2 * N - 1 ? c : c - M;  // signed order
-            v = cmul<C>(v, c2{tw2[2 * (m < 0 ? m + twoM : m)], tw2[2 * (m < 0 ? m + twoM : m) + 1]});
-        }
-        buf[c] = v;
-    }
-    __syncthreads();
+// all passes of `ps` over `total` elements (segments of length ps.L[0]);
+// ends with a barrier
+template <typename C, int MAXO>
+__device__ __forceinline__ void run_passes(typename V2<C>::t *buf, int total, const Passes &ps,
+                                           const typename V2<C>::t *t, int Mt, C sgn) {
     for (int p = 0; p < ps.n; ++p) {
         const int R = ps.R[p], L = ps.L[p];
         switch (R) {
-            case 2: pass_reg<C, 2>(buf, M, L, tw2, sgn); break;
-            case 3: pass_reg<C, 3>(buf, M, L, tw2, sgn); break;
-            case 5: pass_reg<C, 5>(buf, M, L, tw2, sgn); break;
-            case 7: pass_reg<C, 7>(buf, M, L, tw2, sgn); break;
-            case 11: pass_reg<C, 11>(buf, M, L, tw2, sgn); break;
-            case 13: pass_reg<C, 13>(buf, M, L, tw2, sgn); break;
+            case 2: pass_reg<C, 2>(buf, total, L, t, Mt, sgn); break;
+            case 3: pass_reg<C, 3>(buf, total, L, t, Mt, sgn); break;
+            case 5: pass_reg<C, 5>(buf, total, L, t, Mt, sgn); break;
+            case 7: pass_reg<C, 7>(buf, total, L, t, Mt, sgn); break;
+            case 11: pass_reg<C, 11>(buf, total, L, t, Mt, sgn); break;
+            case 13: pass_reg<C, 13>(buf, total, L, t, Mt, sgn); break;
             default:
-                if constexpr (MAXO > 0) pass_sum<C, MAXO>(buf, M, R, L, tw2, sgn);
+                if constexpr (MAXO > 0) pass_sum<C, MAXO>(buf, total, R, L, t, Mt, sgn);
                 break;
         }
         __syncthreads();
     }
-    for (int c = threadIdx.x; c < M; c += blockDim.x) {
-        c2 v = buf[src_pos[c]];
-        if (mode == 1) {
-            const int m = c <= 2 * N - 1 ? c : c - M;
-            int q = m < 0 ? -m : twoM - m;  // e^{-i pi m / M}
-            if (q == twoM) q = 0;
-            v = cmul<C>(v, c2{tw2[2 * q], tw2[2 * q + 1]});
-            v.x *= scale;
-            v.y *= scale;
+}
+
+// Inverse of a register pass up to the factor R: for each butterfly the
+// outputs are first multiplied by the conjugate twiddles w_L^{-n1 k2}, then an
+// R-point DFT of the opposite sign gives R times the pass's inputs.  Run over
+// the passes in reverse order (run_passes_inv), it takes a digit-reversed
+// spectrum back to natural order: M times the inverse transform.
+template <typename C, int R>
+__device__ __forceinline__ void pass_reg_inv(typename V2<C>::t *buf, int total, int L, const typename V2<C>::t *t,
+                                             int Mt, C sgn) {
+    typedef typename V2<C>::t c2;
+    const int Ls = L / R;
+    const int twoM = 2 * Mt;
+    c2 wr[R];  // w_R^{-q}
+#pragma unroll
+    for (int q = 0; q < R; ++q) wr[q] = tw<C>(t, (2 * q * (Mt / R)) % twoM, -sgn);
+    const int unitL = 2 * (Mt / L);
+    const int nb = total / R;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const int blk = b / Ls, n1 = b - blk * Ls;
+        const int base = blk * L + n1;
+        const int step = n1 * unitL;
+        c2 y[R];
+        int ti = 0;
+#pragma unroll
+        for (int k2 = 0; k2 < R; ++k2) {
+            y[k2] = buf[base + Ls * k2];
+            if (k2 > 0) y[k2] = cmul<C>(y[k2], tw<C>(t, ti, -sgn));
+            ti += step;
+            if (ti >= twoM) ti -= twoM;
         }
-        dst[2 * c] = (T)v.x;
-        dst[2 * c + 1] = (T)v.y;
+#pragma unroll
+        for (int n2 = 0; n2 < R; ++n2) {
+            c2 x = y[0];
+#pragma unroll
+            for (int k2 = 1; k2 < R; ++k2) {
+                const c2 p = cmul<C>(y[k2], wr[(n2 * k2) % R]);
+                x.x += p.x;
+                x.y += p.y;
+            }
+            buf[base + Ls * n2] = x;
+        }
+    }
+}
+
+// generic-radix form of pass_reg_inv (MAXO inputs per thread)
+template <typename C, int MAXO>
+__device__ __forceinline__ void pass_sum_inv(typename V2<C>::t *buf, int total, int R, int L,
+                                             const typename V2<C>::t *t, int Mt, C sgn) {
+    typedef typename V2<C>::t c2;
+    const int Ls = L / R;
+    const int twoM = 2 * Mt;
+    const int unitR = 2 * (Mt / R), unitL = 2 * (Mt / L);
+    c2 out[MAXO];
+#pragma unroll
+    for (int j = 0; j < MAXO; ++j) {
+        const int o = threadIdx.x + j * blockDim.x;
+        if (o >= total) continue;
+        const int b = o / L, rem = o - b * L;
+        const int n2 = rem / Ls, n1 = rem - n2 * Ls;
+        const int base = b * L + n1;
+        // x[n2] = sum_k2 w_R^{-n2 k2} w_L^{-n1 k2} y[k2]
+        const int step = (int)(((long long)n2 * unitR + (long long)n1 * unitL) % twoM);
+        c2 x = c2{(C)0, (C)0};
+        int ti = 0;
+        for (int k2 = 0; k2 < R; ++k2) {
+            const c2 p = cmul<C>(buf[base + Ls * k2], tw<C>(t, ti, -sgn));
+            x.x += p.x;
+            x.y += p.y;
+            ti += step;
+            if (ti >= twoM) ti -= twoM;
+        }
+        out[j] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < MAXO; ++j) {
+        const int o = threadIdx.x + j * blockDim.x;
+        if (o < total) buf[o] = out[j];
+    }
+}
+
+// reverse passes: digit-reversed spectrum (of run_passes with sign sgn) ->
+// natural order, times the segment length; ends with a barrier
+template <typename C, int MAXO>
+__device__ __forceinline__ void run_passes_inv(typename V2<C>::t *buf, int total, const Passes &ps,
+                                               const typename V2<C>::t *t, int Mt, C sgn) {
+    for (int p = ps.n - 1; p >= 0; --p) {
+        const int R = ps.R[p], L = ps.L[p];
+        switch (R) {
+            case 2: pass_reg_inv<C, 2>(buf, total, L, t, Mt, sgn); break;
+            case 3: pass_reg_inv<C, 3>(buf, total, L, t, Mt, sgn); break;
+            case 5: pass_reg_inv<C, 5>(buf, total, L, t, Mt, sgn); break;
+            case 7: pass_reg_inv<C, 7>(buf, total, L, t, Mt, sgn); break;
+            case 11: pass_reg_inv<C, 11>(buf, total, L, t, Mt, sgn); break;
+            case 13: pass_reg_inv<C, 13>(buf, total, L, t, Mt, sgn); break;
+            default:
+                if constexpr (MAXO > 0) pass_sum_inv<C, MAXO>(buf, total, R, L, t, Mt, sgn);
+                break;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename C, typename T>
+__device__ __forceinline__ typename V2<C>::t ld(const T *p) {
+    const typename V2<T>::t v = *reinterpret_cast<const typename V2<T>::t *>(p);
+    return typename V2<C>::t{(C)v.x, (C)v.y};
+}
+
+template <typename C, typename T>
+__device__ __forceinline__ void st(T *p, typename V2<C>::t v) {
+    *reinterpret_cast<typename V2<T>::t *>(p) = typename V2<T>::t{(T)v.x, (T)v.y};
+}
+
+// Row input/output of the real-field transforms: a complex row z = f1 + i f2
+// carries two real rows f1, f2 (two fields of real data; the second may be
+// absent, then it reads as zero and is not written).
+//   IO = 0: complex rows in and out;
+//   IO = 1: complex row in, the real and imaginary parts stored to two real
+//           rows (synthesis of two real fields);
+//   IO = 2: two real rows in as one complex row, complex row out (analysis).
+template <typename C, typename T, int IO>
+__device__ __forceinline__ typename V2<C>::t ld_in(const T *src, const T *src2, int c) {
+    if constexpr (IO == 2) return typename V2<C>::t{(C)src[c], src2 ? (C)src2[c] : (C)0};
+    else return ld<C, T>(src + 2 * c);
+}
+
+template <typename C, typename T, int IO>
+__device__ __forceinline__ void st_out(T *dst, T *dst2, int c, typename V2<C>::t v) {
+    if constexpr (IO == 1) {
+        dst[c] = (T)v.x;
+        if (dst2) dst2[c] = (T)v.y;
+    } else {
+        st<C, T>(dst + 2 * c, v);
+    }
+}
+
+// signed order of grid column c: 0..2N-1, then -(2N-1)..-1
+__device__ __forceinline__ int signed_order(int c, int N, int M) { return c <= 2 * N - 1 ? c : c - M; }
+
+// mode 0: synthesis, f[j] = sum_m g[m mod M] e^{i m phi_j}: pre-twiddle
+//         e^{+i pi m / M}, sign +1, no scaling;
+// mode 1: analysis, g[m mod M] = scale sum_j f[j] e^{-i m phi_j}: sign -1,
+//         post-twiddle scale e^{-i pi m / M}.
+// One row by one workgroup: src and dst point at the row (may alias), buf is
+// M complex values of LDS followed by the phase table (base M).  MAXO:
+// outputs per thread of the generic pass (radices above 13); 0 when every
+// radix has a register butterfly.
+template <typename C, typename T, int MAXO, int IO = 0>
+__device__ __forceinline__ void dft_row(int N, int M, const Passes &ps, const C *__restrict__ gtab,
+                                        const int *__restrict__ src_pos, int mode, C scale, const T *src,
+                                        const T *src2, T *dst, T *dst2, typename V2<C>::t *buf) {
+    typedef typename V2<C>::t c2;
+    c2 *t = buf + M;
+    load_tab<C>(gtab, M, t);
+    const int twoM = 2 * M;
+    const C sgn = mode == 0 ? (C)1 : (C)-1;
+    const int bd = blockDim.x;
+    c2 v[kUnroll];
+    __syncthreads();  // table
+    for (int c0 = 0; c0 < M; c0 += kUnroll * bd) {
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int c = c0 + threadIdx.x + j * bd;
+            if (c < M) v[j] = ld_in<C, T, IO>(src, src2, c);
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int c = c0 + threadIdx.x + j * bd;
+            if (c >= M) continue;
+            c2 x = v[j];
+            if (mode == 0) {
+                const int m = signed_order(c, N, M);
+                x = cmul<C>(x, tw<C>(t, m < 0 ? m + twoM : m, (C)1));
+            }
+            buf[c] = x;
+        }
+    }
+    __syncthreads();
+    run_passes<C, MAXO>(buf, M, ps, t, M, sgn);
+    for (int c0 = 0; c0 < M; c0 += kUnroll * bd) {
+        int sp[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int c = c0 + threadIdx.x + j * bd;
+            sp[j] = c < M ? src_pos[c] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int c = c0 + threadIdx.x + j * bd;
+            if (c >= M) continue;
+            c2 x = buf[sp[j]];
+            if (mode == 1) {
+                const int m = signed_order(c, N, M);
+                int q = m < 0 ? -m : twoM - m;  // e^{-i pi m / M}
+                if (q == twoM) q = 0;
+                x = cmul<C>(x, tw<C>(t, q, (C)1));
+                x.x *= scale;
+                x.y *= scale;
+            }
+            st_out<C, T, IO>(dst, dst2, c, x);
+        }
     }
 }
 

@@ -18,8 +18,8 @@ struct GTrans {
     int N, M, fields, pad;
     const double *xh, *wh, *dmant, *coef;
     const int *dexp;
-    const double *tw2;
-    const float *tw2f;
+    const double *tab;  // phi DFT phase table (two-level, base M)
+    const float *tabf;
     const int *src_pos;
     int npass;
     int R[kMaxPass], L[kMaxPass];
@@ -34,6 +34,15 @@ struct GItem {
 };
 
 enum Phase { kFwdAlt = 0, kAdjAlt = 1, kDftSyn = 2, kDftAna = 3 };
+
+// batched mode: a copy between a transform's buffer (ext) and its place in
+// a per-degree staging buffer, in 8-byte words
+struct CopySeg {
+    void *ext;
+    void *stage;
+    int64_t units;
+};
+hipError_t launch_copy_segs(const CopySeg *segs, int nseg, int64_t max_units, int to_stage, hipStream_t s);
 
 hipError_t launch_reset(int *counters, int n, hipStream_t s);
 // grid: number of persistent workgroups

@@ -11,6 +11,7 @@
 
 #include "idbf_build.h"
 #include "idbf_pack.h"
+#include "plan_cache.h"
 #include "sht.h"
 #include "sht_internal.h"
 
@@ -18,7 +19,8 @@ using namespace sht;
 
 struct sht_host_plan {
     int method = SHT_DENSE;
-    idbf::HostPlanData data;
+    int cache = idbf::kCacheOff;  // plan cache outcome (fast form)
+    idbf::HostPlanData data;      // tasks are empty when the plan came from the cache
     idbf::PackedPlan packed;
 };
 
@@ -37,16 +39,35 @@ int sht_host_plan_create(int N, int method, const sht_plan_opts *opts, sht_host_
     hp->method = method;
     try {
         if (method == SHT_IDBF) {
-            int rc = idbf::build_all(N, o, hp->data);
-            if (rc) {
-                delete hp;
-                return rc;
+            std::string key, path;
+            bool loaded = false;
+            if (o.cache_dir && o.cache_dir[0]) {
+                key = idbf::cache_key(N, o);
+                path = idbf::cache_path(o.cache_dir, key);
+                const int lrc = idbf::cache_load(path, key, hp->packed, hp->data.stats);
+                loaded = lrc == SHT_OK;
+                hp->cache = loaded ? idbf::kCacheHit : lrc == SHT_ERR_PLAN_CORRUPT ? idbf::kCacheRebuilt
+                                                                                   : idbf::kCacheMiss;
             }
-            auto tp = std::chrono::steady_clock::now();
-            idbf::pack_programs(hp->data, hp->packed);
-            if (std::getenv("SHT_VERBOSE"))
-                std::fprintf(stderr, "[sht] factors %.2fs, packing %.2fs\n", hp->data.stats.seconds,
-                             std::chrono::duration<double>(std::chrono::steady_clock::now() - tp).count());
+            if (loaded) {
+                hp->data.N = N;
+                hp->data.opts = o;
+                build_legendre_tables(N, hp->data.lt);
+            } else {
+                int rc = idbf::build_all(N, o, hp->data);
+                if (rc) {
+                    delete hp;
+                    return rc;
+                }
+                auto tp = std::chrono::steady_clock::now();
+                idbf::pack_programs(hp->data, hp->packed);
+                if (std::getenv("SHT_VERBOSE"))
+                    std::fprintf(stderr, "[sht] factors %.2fs, packing %.2fs\n", hp->data.stats.seconds,
+                                 std::chrono::duration<double>(std::chrono::steady_clock::now() - tp).count());
+                if (hp->cache != idbf::kCacheOff && idbf::cache_store(path, key, hp->packed, hp->data.stats) != SHT_OK)
+                    hp->cache = idbf::kCacheOff;
+            }
+            hp->data.opts.cache_dir = nullptr;  // the caller's string is not kept
         } else {
             hp->data.N = N;
             hp->data.opts = o;
@@ -70,8 +91,8 @@ int sht_host_plan_apply(const sht_host_plan_t *hp, int absm, int parity, int dir
         return SHT_ERR_INVALID_ARG;
     if (hp->method != SHT_IDBF) return SHT_ERR_UNSUPPORTED;
     const int task = 2 * absm + parity;
-    const idbf::Task &t = hp->data.tasks[task];
-    if (t.cols <= 0) return SHT_OK;
+    const int rows = N, cols = half_cols(N, absm, parity);
+    if (cols <= 0) return SHT_OK;
     // run the packed program on panels that are zero outside this task
     const idbf::PackedPlan &pk = hp->packed;
     const bool fwd = dir == SHT_FWD;
@@ -79,7 +100,7 @@ int sht_host_plan_apply(const sht_host_plan_t *hp, int absm, int parity, int dir
     std::vector<double> pin((size_t)p.in_rows * R, 0.0), pout((size_t)p.out_rows * R, 0.0);
     const int64_t ib = fwd ? pk.x_off[task] : pk.y_off[task];
     const int64_t ob = fwd ? pk.y_off[task] : pk.x_off[task];
-    const int nin = fwd ? t.cols : t.rows, nout = fwd ? t.rows : t.cols;
+    const int nin = fwd ? cols : rows, nout = fwd ? rows : cols;
     std::memcpy(&pin[(size_t)ib * R], in, sizeof(double) * (size_t)nin * R);
     idbf::host_run_program(p, R, pin.data(), pout.data());
     if (fwd)
@@ -107,6 +128,7 @@ int sht_host_plan_stats(const sht_host_plan_t *hp, char *json, size_t cap) {
     if (hp->method == SHT_IDBF) {
         s = hp->data.stats_json();
         s.pop_back();
+        s += std::string(",\"plan_cache\":\"") + idbf::cache_status_name(hp->cache) + "\"";
         const idbf::PackedPlan &pk = hp->packed;
         s += ",\"fwd_stages\":" + std::to_string(pk.fwd.stages.size()) + ",\"fwd_work_stages\":" +
              std::to_string(pk.fwd.n_work_stages) + ",\"fwd_ops\":" + std::to_string(pk.fwd.ops.size()) +

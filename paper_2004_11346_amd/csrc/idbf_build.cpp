@@ -135,11 +135,15 @@ struct Ctx {
 };
 
 // Column ID of K(rows [lo, hi), cand) (Section 2.1): pivoted QR of the sampled
-// rows, truncated at the tolerance; T = R11^{-1} R12.  Verified on a second
-// sample of rows; on failure repeated with every row.
+// rows, truncated at the tolerance; T = R11^{-1} R12.  With id_check (the
+// default) at least n + 8 rows are sampled, the ID is verified on a second
+// sample of rows and on failure repeated with every row; without it the ID is
+// taken from t min(n, r_k) sampled rows as written in Section 2.1.
 ID column_id(const View &K, int lo, int hi, const std::vector<int> &cand, Ctx &cx) {
     const int n = (int)cand.size(), nrows = hi - lo;
-    const int want = std::max(n + 8, cx.o->oversample * std::min(n, cx.o->rk));
+    const bool check = cx.o->id_check != 0;
+    const int want = check ? std::max(n + 8, cx.o->oversample * std::min(n, cx.o->rk))
+                           : std::max(1, cx.o->oversample * std::min(n, cx.o->rk));
     for (int attempt = 0; attempt < 2; ++attempt) {
         std::vector<int> s = attempt == 0 ? (cx.o->sampling == SHT_SAMPLE_RANDOM ? random_sample(lo, hi, want, cx.rng)
                                                                                 : mock_cheb(lo, hi, want))
@@ -165,7 +169,7 @@ ID column_id(const View &K, int lo, int hi, const std::vector<int> &cand, Ctx &c
             // numerically zero block: nothing to keep
         }
         for (int i = 0; i < k; ++i) id.skel_glob.push_back(cand[id.skel[i]]);
-        if (attempt == 1 || ns == nrows || nred == 0) return id;
+        if (!check || attempt == 1 || ns == nrows || nred == 0) return id;
         // verification on rows outside the sample
         std::vector<int> chk = random_sample(lo, hi, std::min(nrows, 48), cx.rng);
         double worst = 0.0;
@@ -259,6 +263,8 @@ bool build_butterfly(const View &K, int r0, int r1, int c0, int c1, Ctx &cx, But
         }
     // a butterfly with an ID cut at the rank cap does not compress its block
     // to the tolerance: leave the block to the dense (regenerated) path
+    // (with id_check; without it the truncated butterfly is kept)
+    if (cx.o->id_check == 0) return true;
     for (const auto *ids : {&bf.col, &bf.row})
         for (const auto &lv : *ids)
             for (const ID &id : lv)
@@ -653,7 +659,10 @@ void build_task(int N, const LegendreTables &lt, const sht_plan_opts &o, int a, 
             if (build_butterfly(K, b.r0, b.r1, b.c0, b.c1, cx, bf)) {
                 blk.type = kButterfly;
                 blk.bf = std::move(bf);
-                if (blk.stored() < dense_sz && butterfly_check(K, blk.bf, cx) <= 50.0 * cx.tol) {
+                // without id_check the truncated butterfly is kept as Section 2.1
+                // builds it (the sampling and rank study measures its error)
+                if (blk.stored() < dense_sz &&
+                    (o.id_check == 0 || butterfly_check(K, blk.bf, cx) <= 50.0 * cx.tol)) {
                     chosen = true;
                 } else {
                     blk.bf = Butterfly();
@@ -784,7 +793,9 @@ int build_all(int N, const sht_plan_opts &opts_in, HostPlanData &out, const Lege
     return SHT_OK;
 }
 
-std::string HostPlanData::stats_json() const {
+std::string HostPlanData::stats_json() const { return idbf::stats_json(stats, opts); }
+
+std::string stats_json(const BuildStats &stats, const sht_plan_opts &opts) {
     std::ostringstream os;
     os << "{\"dense_entries\":" << stats.dense_entries << ",\"stored_entries\":" << stats.stored
        << ",\"compression\":" << (stats.stored ? (double)stats.dense_entries / stats.stored : 0.0)

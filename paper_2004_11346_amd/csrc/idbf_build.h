@@ -105,6 +105,9 @@ struct HostPlanData {
     std::string stats_json() const;
 };
 
+// Statistics of a plan as a JSON object.
+std::string stats_json(const BuildStats &stats, const sht_plan_opts &opts);
+
 // Build every task (all orders, both parities).  `lt`, when given, holds the
 // Legendre tables of degree N already built by the caller (copied into out).
 int build_all(int N, const sht_plan_opts &opts, HostPlanData &out, const LegendreTables *lt = nullptr);

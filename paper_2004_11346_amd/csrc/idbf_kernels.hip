@@ -893,13 +893,17 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
 #undef SHT_OPS_LAUNCH
         }
     }
+    // regenerated blocks: on the FP64 matrix cores from 16 right-hand sides,
+    // also in split-BF16 plans (their entries come from the FP64 recurrence,
+    // so their products keep FP64 accuracy); on the VALU below
+    const bool gen_mfma = p.RCW > 0 && R >= 16;
     if (fwd && p.gen.n_items > 0) {
         const int i0 = p.gen.task_first_h[t_lo], i1 = p.gen.task_first_h[t_hi + 1];
         if (i1 > i0) {
-            prof::Scope ps(s, mfma ? "k_gen_fwd_mfma" : "k_gen_fwd");
+            prof::Scope ps(s, gen_mfma ? "k_gen_fwd_mfma" : "k_gen_fwd");
             const GenItem *gi = (const GenItem *)p.gen.d_items;
             const GenSeg *gs = (const GenSeg *)p.gen.d_segs;
-            if (mfma) {
+            if (gen_mfma) {
                 for (int c0 = 0; c0 < R; c0 += 32)
                     hipLaunchKernelGGL((k_gen_fwd_mfma<T, 2>), dim3(xcd_grid(i1 - i0)), dim3(64), 0, s, gi, i1 - i0,
                                        kXc, i0, gs, p.gen.d_ck, p.gen.d_ckexp, p.d_xh, p.d_coef2, N, p.d_x_off,

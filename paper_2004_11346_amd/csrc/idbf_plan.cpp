@@ -7,6 +7,7 @@
 #include <sstream>
 
 #include "idbf.h"
+#include "plan_cache.h"
 
 namespace sht {
 namespace idbf {
@@ -76,17 +77,32 @@ void DeviceProgram::release() {
 }
 
 int build_program(int N, int batch, const LegendreTables &lt, const sht_plan_opts &opts, HostProgram &out) {
-    HostPlanData hp;
-    int rc = build_all(N, opts, hp, &lt);
-    if (rc) return rc;
     (void)batch;
-    pack_programs(hp, out.packed);
+    int cache = kCacheOff;
+    std::string key, path;
+    bool loaded = false;
+    if (opts.cache_dir && opts.cache_dir[0]) {
+        key = cache_key(N, opts);
+        path = cache_path(opts.cache_dir, key);
+        const int lrc = cache_load(path, key, out.packed, out.stats);
+        loaded = lrc == SHT_OK;
+        cache = loaded ? kCacheHit : lrc == SHT_ERR_PLAN_CORRUPT ? kCacheRebuilt : kCacheMiss;
+    }
+    if (!loaded) {
+        HostPlanData hp;
+        int rc = build_all(N, opts, hp, &lt);
+        if (rc) return rc;
+        pack_programs(hp, out.packed);
+        out.stats = hp.stats;
+        if (cache != kCacheOff && cache_store(path, key, out.packed, out.stats) != SHT_OK)
+            cache = kCacheOff;  // not writable: the plan is still built
+    }
     out.N = N;
     out.f32_mode = opts.f32_mode;
-    out.stats = hp.stats;
     std::ostringstream os;
-    std::string base = hp.stats_json();
+    std::string base = idbf::stats_json(out.stats, opts);
     base.pop_back();  // strip '}'
+    base += std::string(",\"plan_cache\":\"") + cache_status_name(cache) + "\"";
     int64_t idx_bytes = 4 * (int64_t)(out.packed.fwd.idx.size() + out.packed.adj.idx.size()) +
                         (int64_t)(out.packed.fwd.ops.size() + out.packed.adj.ops.size()) * sizeof(Op) +
                         (int64_t)(out.packed.fwd.subs.size() + out.packed.adj.subs.size()) * sizeof(SubOp);
@@ -122,8 +138,40 @@ int build_program(int N, int batch, const LegendreTables &lt, const sht_plan_opt
     int64_t fin = 0, fout = 0, ain = 0, aout = 0;
     rows_moved(pk.fwd, fin, fout);
     rows_moved(pk.adj, ain, aout);
+    // distinct input-panel rows the program reads and output-panel rows its
+    // final stage writes: the vector rows one call must move at least once
+    auto vector_rows = [](const Program &pr, int64_t &in_rows, int64_t &out_rows) {
+        std::vector<unsigned char> seen((size_t)std::max<int64_t>(1, pr.in_rows), 0);
+        in_rows = 0;
+        out_rows = 0;
+        for (const Op &op : pr.ops) {
+            if (op.dst == kOut) out_rows += op.n_out;
+            for (int k = 0; k < op.nsub; ++k) {
+                const SubOp &so = pr.subs[op.sub0 + k];
+                if (so.src != kIn) continue;
+                auto mark = [&](int64_t r) {
+                    if (r >= 0 && r < pr.in_rows && !seen[(size_t)r]) {
+                        seen[(size_t)r] = 1;
+                        ++in_rows;
+                    }
+                };
+                if (so.n_map > 0)
+                    for (int j = 0; j < so.n_in; ++j) mark(pr.idx[(size_t)so.in_off + j]);
+                for (int j = 0; j < so.n_dir; ++j) mark(pr.idx[(size_t)so.dir_off + 2 * j]);
+            }
+        }
+    };
+    int64_t fvi = 0, fvo = 0, avi = 0, avo = 0;
+    vector_rows(pk.fwd, fvi, fvo);
+    vector_rows(pk.adj, avi, avo);
+    const int64_t adj_idx = 4 * (int64_t)pk.adj.idx.size() + (int64_t)pk.adj.ops.size() * sizeof(Op) +
+                            (int64_t)pk.adj.subs.size() * sizeof(SubOp) +
+                            (int64_t)pk.gen_adj.items.size() * sizeof(GenAdjoint::Item) +
+                            (int64_t)pk.gen_adj.segs.size() * sizeof(GenAdjoint::Seg);
     os << ",\"fwd_gather_rows\":" << fin << ",\"fwd_out_rows\":" << fout << ",\"adj_gather_rows\":" << ain
-       << ",\"adj_out_rows\":" << aout;
+       << ",\"adj_out_rows\":" << aout << ",\"fwd_vector_in_rows\":" << fvi << ",\"fwd_vector_out_rows\":" << fvo
+       << ",\"adj_vector_in_rows\":" << avi << ",\"adj_vector_out_rows\":" << avo
+       << ",\"adj_index_bytes\":" << adj_idx;
     os << ",\"fwd_index_bytes\":" << fwd_idx << ",\"fwd_state_bytes\":" << 20 * fwd_states
        << ",\"adj_state_bytes\":" << 20 * adj_states << ",\"gen_fwd_items\":" << pk.gen_fwd.items.size()
        << ",\"gen_adj_items\":" << pk.gen_adj.items.size() << "}";

@@ -62,24 +62,67 @@ hipError_t panel_combine(int dtype, bool panel64, int N, int batch, int a_lo, in
 hipError_t panel_fold(int dtype, bool panel64, int N, int batch, int a_lo, int a_hi, const double *wh,
                       const void *g, void *Y, hipStream_t s);
 
-// Length-M DFT of every grid row (Section 1, phi sums), LDS resident.
-struct DftPlan {
-    int N = 0, M = 0;
-    int nrad = 0;
-    int radix[24] = {0};          // prime factors of M, largest first
-    int blen[24] = {0};           // block length before each pass
-    const double *tw2 = nullptr;  // [2M][2]: exp(i pi r / M), r in [0, 2M)
-    const float *tw2f = nullptr;  // same in float
-    const int *src_pos = nullptr;  // [M]: LDS slot holding output index c
+// Length-M DFT of every grid row (Section 1, the phi sums).  Schedules:
+// rows in LDS, Rader's convolution for prime M, or four-step through a
+// grid-sized buffer for rows larger than LDS (see kernels_dft.hip).
+enum DftKind { kDftNone = -1, kDftRows = 0, kDftRader = 1, kDftFourStep = 2 };
+
+// host tables of one length M (built once per plan or grouped transform)
+struct DftHost {
+    int kind = kDftNone, M = 0;
+    std::vector<int> radix, blen, src_pos;     // rows: passes of M; Rader: of M - 1; four-step: of M1
+    std::vector<int> radix2, blen2, src_pos2;  // four-step: passes of M2
+    std::vector<double> tab;                   // phase table of base M (lo[64], hi[...]), complex
+    std::vector<float> tabf;
+    std::vector<double> ctab;                  // Rader: phase table of base M - 1
+    std::vector<float> ctabf;
+    std::vector<int> inslot, outslot;          // Rader: slot of input n / output k
+    std::vector<double> bspec;                 // Rader: [2][M - 1] complex spectra (synthesis, analysis)
+    std::vector<float> bspecf;
+    int M1 = 0, M2 = 0, chunk1 = 0, chunk2 = 0;  // four-step split and chunks
 };
-bool dft_supported(int M, int dtype);
-// host: radices, block lengths and the output position table for length M
-void dft_passes(int M, std::vector<int> &radix, std::vector<int> &blen, std::vector<int> &src_pos);
+// force: 0 = by length and type, 1 = rows in LDS (generic passes for large
+// primes), 2 = Rader (prime M), 3 = four-step; kind = kDftNone if the schedule
+// does not apply
+void dft_build(int M, int dtype, DftHost &h, int force = 0);
+
+// device view of the tables (arrays owned by the plan or group)
+struct DftPlan {
+    int N = 0, M = 0, kind = kDftNone;
+    int nrad = 0, radix[24] = {0}, blen[24] = {0};
+    int nrad2 = 0, radix2[24] = {0}, blen2[24] = {0};
+    int M1 = 0, M2 = 0, chunk1 = 0, chunk2 = 0;
+    const double *tab = nullptr;
+    const float *tabf = nullptr;
+    const double *ctab = nullptr;
+    const float *ctabf = nullptr;
+    const int *src_pos = nullptr, *src_pos2 = nullptr;
+    const int *inslot = nullptr, *outslot = nullptr;
+    const double *bspec = nullptr;
+    const float *bspecf = nullptr;
+    void *scratch = nullptr;  // four-step: [batch][2N][M] complex of the plan's type
+};
+// kernel attributes of the DFT kernels (once per process, before any capture)
+hipError_t dft_init();
 // synthesis in place on f: f[l][j] = sum_m g[l][m mod M] e^{i m phi_j}
 hipError_t dft_synthesis(const DftPlan &p, int dtype, int batch, void *f, hipStream_t s);
 // analysis f -> g: g[l][m mod M] = scale * sum_j f[l][j] e^{-i m phi_j}
 hipError_t dft_analysis(const DftPlan &p, int dtype, int batch, double scale, const void *f, void *g,
                         hipStream_t s);
+// real fields: complex rows z (pairs fields) -> real rows of fields 2b and
+// 2b + 1 (its real and imaginary part; fields >= nreal are not written)
+hipError_t dft_synthesis_real(const DftPlan &p, int dtype, int pairs, int nreal, const void *z, void *f,
+                              hipStream_t s);
+// real fields: real rows of fields 2b, 2b + 1 (zero past nreal) as one
+// complex row -> analysed complex rows z
+hipError_t dft_analysis_real(const DftPlan &p, int dtype, int pairs, int nreal, double scale, const void *f,
+                             void *z, hipStream_t s);
+
+// Real fields (see kernels_real.hip): half coefficients [nreal][N (2N + 1)]
+// of fields 2p, 2p + 1 <-> full complex coefficients [pairs][4N^2] of
+// z = f1 + i f2 (fields past nreal read as zero / are not written).
+hipError_t real_pack(int dtype, int N, int pairs, int nreal, const void *half, void *full, hipStream_t s);
+hipError_t real_unpack(int dtype, int N, int pairs, int nreal, const void *full, void *half, hipStream_t s);
 
 }  // namespace dev
 }  // namespace sht

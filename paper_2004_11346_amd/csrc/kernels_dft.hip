@@ -1,26 +1,31 @@
-// Length-M (M = 4N - 1) DFT along phi for every grid row (Section 1):
+// Length-M (M = 4N - 1) DFT along phi for every grid row (Section 1, the phi
+// sums of eq. `sht_fft`):
 //   synthesis  f[l][j] = sum_{m=-(2N-1)}^{2N-1} g[l][m mod M] e^{i m phi_j},
 //              phi_j = 2 pi (j + 1/2) / M,
 //   analysis   g[l][m mod M] = scale * sum_j f[l][j] e^{-i m phi_j}.
 // The half-sample shift of phi_j becomes a twiddle e^{+-i pi m / M} on the
 // order side (with the signed order m), leaving a plain length-M DFT.
 //
-// One workgroup owns one row, held once in LDS.  The DFT is an in-place
-// mixed-radix decimation in frequency over the prime factors of M (largest
-// first): a pass of radix R over blocks of length L splits each block into R
-// interleaved sub-blocks of length L/R with
-//   y[n1 + (L/R) k2] = w_L^{n1 k2} sum_{n2} x[n1 + (L/R) n2] w_R^{n2 k2}.
-// Small radices run as register butterflies (each thread owns whole
-// butterflies, so a pass needs no barrier between its reads and writes);
-// large primes (e.g. 89 in 2047 = 23 * 89, 127 in 16383) compute every output
-// of the pass as an R-term sum into registers, then write after a barrier.
-// After the last pass the spectrum sits in digit-reversed order; a position
-// table maps each output index to its LDS slot so the row is written back
-// with coalesced stores.  Every phase is looked up in one table of
-// e^{i pi r / M}, r in [0, 2M), with indices reduced exactly in integers.
+// Three schedules, chosen per M and element type when the plan is built:
+//  * rows in LDS: one workgroup per row, the row held once in LDS, mixed-radix
+//    passes over the prime factors of M (largest first), the digit-reversed
+//    result written back through a position table;
+//  * Rader (prime M): with a primitive root g of M, the outputs X_k, k != 0,
+//    are x_0 plus a cyclic convolution of length M - 1 of the inputs taken in
+//    the order x_{g^q} with the phases w^{g^{-q}}; the convolution runs in LDS
+//    as a forward mixed-radix transform of length M - 1, a product with the
+//    phases' precomputed spectrum and the reverse passes back to natural
+//    order, so a prime row costs O(M log M) instead of M^2 products;
+//  * four-step (rows larger than LDS): M = M1 M2, n = M2 n1 + n2,
+//    k = k1 + M1 k2: a first kernel takes the length-M1 transforms over n1 for
+//    a chunk of n2 and multiplies by w_M^{n2 k1}, a second the length-M2
+//    transforms over n2 for a chunk of k1; the intermediate rows go through a
+//    grid-sized buffer of the plan.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <vector>
 
 #include "dft_device.h"
 #include "kernels.h"
@@ -33,102 +38,623 @@ namespace {
 
 using namespace dft;
 
-template <typename C, typename T, int MAXO>
-__global__ __launch_bounds__(512) void k_dft_rows(int N, int M, Passes ps, const C *__restrict__ tw2,
-                                                  const int *__restrict__ src_pos, int mode, C scale, const T *in,
-                                                  T *out) {
+constexpr int kThreads = 512;
+constexpr size_t kLds = 160 * 1024;
+constexpr int kRaderMaxo = 24;  // generic-pass outputs per thread (M - 1 <= 12288)
+constexpr int kSegMaxo = 16;    // four-step: at most 8192 elements per workgroup
+
+// Row pointers of grid row l of field (or field pair) b for the I/O mode of
+// dft_row: complex rows at [b][l]; real rows of fields 2b and 2b + 1 (the
+// second absent when 2b + 1 >= nreal).
+template <typename T, int IO>
+struct RowPtrs {
+    const T *src = nullptr, *src2 = nullptr;
+    T *dst = nullptr, *dst2 = nullptr;
+    __device__ RowPtrs(int N, int M, int b, int l, int nreal, const T *in, T *out) {
+        const int64_t crow = 2 * (((int64_t)b * 2 * N + l) * M);
+        const int64_t r1 = ((int64_t)(2 * b) * 2 * N + l) * M, r2 = r1 + (int64_t)2 * N * M;
+        const bool two = 2 * b + 1 < nreal;
+        if constexpr (IO == 2) {
+            src = in + r1;
+            src2 = two ? in + r2 : nullptr;
+        } else {
+            src = in + crow;
+        }
+        if constexpr (IO == 1) {
+            dst = out + r1;
+            dst2 = two ? out + r2 : nullptr;
+        } else {
+            dst = out + crow;
+        }
+    }
+};
+
+template <typename C, typename T, int MAXO, int IO>
+__global__ __launch_bounds__(kThreads) void k_dft_rows(int N, int M, Passes ps, const C *__restrict__ tab,
+                                                       const int *__restrict__ src_pos, int mode, C scale,
+                                                       const T *in, T *out, int nreal) {
     extern __shared__ unsigned char smem_raw[];
     typename V2<C>::t *buf = reinterpret_cast<typename V2<C>::t *>(smem_raw);
-    const int64_t base = 2 * ((int64_t)blockIdx.y * 2 * N * M + (int64_t)blockIdx.x * M);
-    dft_row<C, T, MAXO>(N, M, ps, tw2, src_pos, mode, scale, in + base, out + base, buf);
+    const RowPtrs<T, IO> r(N, M, blockIdx.y, blockIdx.x, nreal, in, out);
+    dft_row<C, T, MAXO, IO>(N, M, ps, tab, src_pos, mode, scale, r.src, r.src2, r.dst, r.dst2, buf);
 }
 
-template <typename C, typename T>
-hipError_t launch_rows(const DftPlan &p, int batch, int mode, double scale, const void *in, void *out,
-                       hipStream_t s) {
-    Passes ps;
-    ps.n = p.nrad;
-    for (int i = 0; i < 24; ++i) {
-        ps.R[i] = p.radix[i];
-        ps.L[i] = p.blen[i];
-    }
-    const size_t lds = sizeof(typename V2<C>::t) * (size_t)p.M;
-    static bool attr_set = false;
-    if (!attr_set) {
-        for (const void *fn : {(const void *)&k_dft_rows<C, T, 0>, (const void *)&k_dft_rows<C, T, 8>,
-                               (const void *)&k_dft_rows<C, T, 32>}) {
-            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            if (e != hipSuccess) return e;
+// prime M by Rader's convolution
+template <typename C, typename T, int IO>
+__global__ __launch_bounds__(kThreads) void k_dft_rader(int N, int M, Passes pc, const C *__restrict__ tab,
+                                                        const C *__restrict__ ctab, const int *__restrict__ inslot,
+                                                        const int *__restrict__ outslot, const C *__restrict__ bspec,
+                                                        int mode, C scale, const T *in, T *out, int nreal) {
+    typedef typename V2<C>::t c2;
+    extern __shared__ unsigned char smem_raw[];
+    c2 *buf = reinterpret_cast<c2 *>(smem_raw);
+    const int L = M - 1;
+    c2 *t = buf + L;
+    c2 *tc = t + tab_entries(M);
+    c2 *red = tc + tab_entries(L);  // [kThreads / 64 + 1]
+    const RowPtrs<T, IO> r(N, M, blockIdx.y, blockIdx.x, nreal, in, out);
+    load_tab<C>(tab, M, t);
+    load_tab<C>(ctab, L, tc);
+    __syncthreads();
+    const int twoM = 2 * M;
+    const int bd = blockDim.x;
+    // inputs: x_n to slot q with g^q = n (n >= 1); x_0 kept aside; total sum
+    c2 sum = c2{(C)0, (C)0};
+    for (int c0 = 0; c0 < M; c0 += kUnroll * bd) {
+        c2 v[kUnroll];
+        int q[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int c = c0 + threadIdx.x + j * bd;
+            if (c < M) {
+                v[j] = ld_in<C, T, IO>(r.src, r.src2, c);
+                q[j] = inslot[c];
+            }
         }
-        attr_set = true;
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int c = c0 + threadIdx.x + j * bd;
+            if (c >= M) continue;
+            c2 x = v[j];
+            if (mode == 0) {
+                const int m = signed_order(c, N, M);
+                x = cmul<C>(x, tw<C>(t, m < 0 ? m + twoM : m, (C)1));
+            }
+            sum.x += x.x;
+            sum.y += x.y;
+            if (c == 0)
+                red[kThreads / 64] = x;
+            else
+                buf[q[j]] = x;
+        }
     }
-    const C *tw = sizeof(C) == 8 ? (const C *)p.tw2 : (const C *)p.tw2f;
-    int maxr = 0;
-    for (int i = 0; i < p.nrad; ++i) maxr = std::max(maxr, p.radix[i]);
+    // X_0 = sum of all inputs
+    for (int o = 32; o > 0; o >>= 1) {
+        sum.x += __shfl_xor(sum.x, o);
+        sum.y += __shfl_xor(sum.y, o);
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    // cyclic convolution: forward transform (sign -1), spectrum product,
+    // reverse passes (the 1/(M-1) is folded into the spectrum)
+    run_passes<C, kRaderMaxo>(buf, L, pc, tc, L, (C)-1);
+    const C *bs = bspec + (size_t)(mode == 0 ? 0 : 2 * L);
+    for (int c0 = 0; c0 < L; c0 += kUnroll * bd) {
+        c2 b[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int c = c0 + threadIdx.x + j * bd;
+            if (c < L) b[j] = reinterpret_cast<const c2 *>(bs)[c];
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int c = c0 + threadIdx.x + j * bd;
+            if (c < L) buf[c] = cmul<C>(buf[c], b[j]);
+        }
+    }
+    __syncthreads();
+    run_passes_inv<C, kRaderMaxo>(buf, L, pc, tc, L, (C)-1);
+    c2 x0 = red[kThreads / 64];
+    c2 X0 = c2{(C)0, (C)0};
+    for (int w = 0; w < kThreads / 64; ++w) {
+        X0.x += red[w].x;
+        X0.y += red[w].y;
+    }
+    for (int c0 = 0; c0 < M; c0 += kUnroll * bd) {
+        int sp[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int c = c0 + threadIdx.x + j * bd;
+            sp[j] = (c < M && c > 0) ? outslot[c] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int c = c0 + threadIdx.x + j * bd;
+            if (c >= M) continue;
+            c2 x;
+            if (c == 0) {
+                x = X0;
+            } else {
+                x = buf[sp[j]];
+                x.x += x0.x;
+                x.y += x0.y;
+            }
+            if (mode == 1) {
+                const int m = signed_order(c, N, M);
+                int qq = m < 0 ? -m : twoM - m;
+                if (qq == twoM) qq = 0;
+                x = cmul<C>(x, tw<C>(t, qq, (C)1));
+                x.x *= scale;
+                x.y *= scale;
+            }
+            st_out<C, T, IO>(r.dst, r.dst2, c, x);
+        }
+    }
+}
+
+// four-step, first kernel: for n2 in [n2_0, n2_0 + cnt), the length-M1
+// transforms over n1 of x[M2 n1 + n2] (pre-twiddled for synthesis), times
+// w_M^{n2 k1}, written to y[k1 M2 + n2]
+template <typename C, typename T, int IO>
+__global__ __launch_bounds__(kThreads) void k_dft_4s_a(int N, int M, int M1, int M2, int chunk, Passes ps,
+                                                       const C *__restrict__ tab, const int *__restrict__ src_pos,
+                                                       int mode, const T *in, T *out, int nreal) {
+    typedef typename V2<C>::t c2;
+    extern __shared__ unsigned char smem_raw[];
+    c2 *buf = reinterpret_cast<c2 *>(smem_raw);
+    const int n2_0 = blockIdx.x * chunk;
+    const int cnt = min(chunk, M2 - n2_0);
+    const int total = cnt * M1;
+    c2 *t = buf + chunk * M1;
+    // input rows in the I/O mode (IO 2: two real rows); output: complex
+    // intermediate rows
+    const RowPtrs<T, IO == 2 ? 2 : 0> r(N, M, blockIdx.z, blockIdx.y, nreal, in, out);
+    const T *src = r.src;
+    T *dst = out + 2 * (((int64_t)blockIdx.z * 2 * N + blockIdx.y) * M);
+    load_tab<C>(tab, M, t);
+    __syncthreads();
+    const int twoM = 2 * M;
+    const C sgn = mode == 0 ? (C)1 : (C)-1;
+    const int bd = blockDim.x;
+    for (int e0 = 0; e0 < total; e0 += kUnroll * bd) {
+        c2 v[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int e = e0 + threadIdx.x + j * bd;
+            if (e < total) {
+                const int n1 = e / cnt, n2l = e - n1 * cnt;
+                v[j] = ld_in<C, T, IO == 2 ? 2 : 0>(src, r.src2, M2 * n1 + n2_0 + n2l);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int e = e0 + threadIdx.x + j * bd;
+            if (e >= total) continue;
+            const int n1 = e / cnt, n2l = e - n1 * cnt;
+            c2 x = v[j];
+            if (mode == 0) {
+                const int m = signed_order(M2 * n1 + n2_0 + n2l, N, M);
+                x = cmul<C>(x, tw<C>(t, m < 0 ? m + twoM : m, (C)1));
+            }
+            buf[n2l * M1 + n1] = x;
+        }
+    }
+    __syncthreads();
+    run_passes<C, kSegMaxo>(buf, total, ps, t, M, sgn);
+    for (int e0 = 0; e0 < total; e0 += kUnroll * bd) {
+        int sp[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int e = e0 + threadIdx.x + j * bd;
+            sp[j] = e < total ? src_pos[e / cnt] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int e = e0 + threadIdx.x + j * bd;
+            if (e >= total) continue;
+            const int k1 = e / cnt, n2l = e - k1 * cnt;
+            const int n2 = n2_0 + n2l;
+            c2 x = buf[n2l * M1 + sp[j]];
+            x = cmul<C>(x, tw<C>(t, (int)((2 * (int64_t)n2 * k1) % twoM), sgn));
+            st<C, T>(dst + 2 * ((int64_t)k1 * M2 + n2), x);
+        }
+    }
+}
+
+// four-step, second kernel: for k1 in [k1_0, k1_0 + cnt), the length-M2
+// transforms over n2 of y[k1 M2 + n2], written to X[k1 + M1 k2]
+// (post-twiddled and scaled for analysis)
+template <typename C, typename T, int IO>
+__global__ __launch_bounds__(kThreads) void k_dft_4s_b(int N, int M, int M1, int M2, int chunk, Passes ps,
+                                                       const C *__restrict__ tab, const int *__restrict__ src_pos,
+                                                       int mode, C scale, const T *in, T *out, int nreal) {
+    typedef typename V2<C>::t c2;
+    extern __shared__ unsigned char smem_raw[];
+    c2 *buf = reinterpret_cast<c2 *>(smem_raw);
+    const int k1_0 = blockIdx.x * chunk;
+    const int cnt = min(chunk, M1 - k1_0);
+    const int total = cnt * M2;
+    c2 *t = buf + chunk * M2;
+    // input: complex intermediate rows; output rows in the I/O mode (IO 1:
+    // two real rows)
+    const T *src = in + 2 * (((int64_t)blockIdx.z * 2 * N + blockIdx.y) * M) + 2 * (int64_t)k1_0 * M2;
+    const RowPtrs<T, IO == 1 ? 1 : 0> r(N, M, blockIdx.z, blockIdx.y, nreal, in, out);
+    load_tab<C>(tab, M, t);
+    const int twoM = 2 * M;
+    const C sgn = mode == 0 ? (C)1 : (C)-1;
+    const int bd = blockDim.x;
+    for (int e0 = 0; e0 < total; e0 += kUnroll * bd) {
+        c2 v[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int e = e0 + threadIdx.x + j * bd;
+            if (e < total) v[j] = ld<C, T>(src + 2 * (int64_t)e);
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int e = e0 + threadIdx.x + j * bd;
+            if (e < total) buf[e] = v[j];
+        }
+    }
+    __syncthreads();
+    run_passes<C, kSegMaxo>(buf, total, ps, t, M, sgn);
+    for (int e0 = 0; e0 < total; e0 += kUnroll * bd) {
+        int sp[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int e = e0 + threadIdx.x + j * bd;
+            sp[j] = e < total ? src_pos[e / cnt] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int e = e0 + threadIdx.x + j * bd;
+            if (e >= total) continue;
+            const int k2 = e / cnt, k1l = e - k2 * cnt;
+            const int k = k1_0 + k1l + M1 * k2;
+            c2 x = buf[k1l * M2 + sp[j]];
+            if (mode == 1) {
+                const int m = signed_order(k, N, M);
+                int q = m < 0 ? -m : twoM - m;
+                if (q == twoM) q = 0;
+                x = cmul<C>(x, tw<C>(t, q, (C)1));
+                x.x *= scale;
+                x.y *= scale;
+            }
+            st_out<C, T, IO == 1 ? 1 : 0>(r.dst, r.dst2, k, x);
+        }
+    }
+}
+
+Passes to_passes(int n, const int *R, const int *L) {
+    Passes ps;
+    ps.n = n;
+    for (int i = 0; i < 24; ++i) {
+        ps.R[i] = i < n ? R[i] : 0;
+        ps.L[i] = i < n ? L[i] : 0;
+    }
+    return ps;
+}
+
+int max_radix(int n, const int *R) {
+    int m = 0;
+    for (int i = 0; i < n; ++i) m = std::max(m, R[i]);
+    return m;
+}
+
+template <typename C, int IO>
+hipError_t set_attrs_io() {
+    const void *fns[] = {(const void *)&k_dft_rows<C, C, 0, IO>,  (const void *)&k_dft_rows<C, C, 8, IO>,
+                         (const void *)&k_dft_rows<C, C, 16, IO>, (const void *)&k_dft_rows<C, C, 32, IO>,
+                         (const void *)&k_dft_rader<C, C, IO>,    (const void *)&k_dft_4s_a<C, C, IO>,
+                         (const void *)&k_dft_4s_b<C, C, IO>};
+    for (const void *fn : fns) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename C>
+hipError_t set_attrs() {
+    static bool done = false;
+    if (done) return hipSuccess;
+    hipError_t e;
+    if ((e = set_attrs_io<C, 0>()) != hipSuccess) return e;
+    if ((e = set_attrs_io<C, 1>()) != hipSuccess) return e;
+    if ((e = set_attrs_io<C, 2>()) != hipSuccess) return e;
+    done = true;
+    return hipSuccess;
+}
+
+// IO: 0 complex rows; 1 synthesis into real field pairs; 2 analysis of real
+// field pairs (see dft_row).  nreal: real fields (IO 1 and 2).
+template <typename C, typename T, int IO>
+hipError_t launch(const DftPlan &p, int batch, int mode, double scale, const void *in, void *out, int nreal,
+                  hipStream_t s) {
+    typedef typename V2<C>::t c2;
+    hipError_t e = set_attrs<C>();
+    if (e != hipSuccess) return e;
+    const bool f64 = sizeof(C) == 8;
+    const C *tab = f64 ? (const C *)p.tab : (const C *)p.tabf;
+    const int M = p.M;
     prof::Scope sc(s, mode == 0 ? "k_dft_synthesis" : "k_dft_analysis");
-    if (maxr <= 13)
-        hipLaunchKernelGGL((k_dft_rows<C, T, 0>), dim3(2 * p.N, batch), dim3(512), lds, s, p.N, p.M, ps, tw,
-                           p.src_pos, mode, (C)scale, (const T *)in, (T *)out);
-    else if (p.M <= 8 * 512)
-        hipLaunchKernelGGL((k_dft_rows<C, T, 8>), dim3(2 * p.N, batch), dim3(512), lds, s, p.N, p.M, ps, tw,
-                           p.src_pos, mode, (C)scale, (const T *)in, (T *)out);
-    else
-        hipLaunchKernelGGL((k_dft_rows<C, T, 32>), dim3(2 * p.N, batch), dim3(512), lds, s, p.N, p.M, ps, tw,
-                           p.src_pos, mode, (C)scale, (const T *)in, (T *)out);
-    return hipGetLastError();
+    if (p.kind == kDftRows) {
+        const Passes ps = to_passes(p.nrad, p.radix, p.blen);
+        const size_t lds = sizeof(c2) * ((size_t)M + tab_entries(M));
+        const int maxr = max_radix(p.nrad, p.radix);
+        const dim3 grid(2 * p.N, batch);
+#define SHT_ROWS(MX)                                                                                        \
+    hipLaunchKernelGGL((k_dft_rows<C, T, MX, IO>), grid, dim3(kThreads), lds, s, p.N, M, ps, tab, p.src_pos, \
+                       mode, (C)scale, (const T *)in, (T *)out, nreal)
+        if (maxr <= 13)
+            SHT_ROWS(0);
+        else if (M <= 8 * kThreads)
+            SHT_ROWS(8);
+        else if (M <= 16 * kThreads)
+            SHT_ROWS(16);
+        else
+            SHT_ROWS(32);
+#undef SHT_ROWS
+        return hipGetLastError();
+    }
+    if (p.kind == kDftRader) {
+        const Passes pc = to_passes(p.nrad, p.radix, p.blen);
+        const size_t lds = sizeof(c2) * ((size_t)(M - 1) + tab_entries(M) + tab_entries(M - 1) + kThreads / 64 + 1);
+        hipLaunchKernelGGL((k_dft_rader<C, T, IO>), dim3(2 * p.N, batch), dim3(kThreads), lds, s, p.N, M, pc, tab,
+                           f64 ? (const C *)p.ctab : (const C *)p.ctabf, p.inslot, p.outslot,
+                           f64 ? (const C *)p.bspec : (const C *)p.bspecf, mode, (C)scale, (const T *)in, (T *)out,
+                           nreal);
+        return hipGetLastError();
+    }
+    if (p.kind == kDftFourStep) {
+        if (!p.scratch) return hipErrorInvalidValue;
+        const Passes pa = to_passes(p.nrad, p.radix, p.blen);
+        const Passes pb = to_passes(p.nrad2, p.radix2, p.blen2);
+        const size_t la = sizeof(c2) * ((size_t)p.chunk1 * p.M1 + tab_entries(M));
+        const size_t lb = sizeof(c2) * ((size_t)p.chunk2 * p.M2 + tab_entries(M));
+        T *scr = (T *)p.scratch;
+        hipLaunchKernelGGL((k_dft_4s_a<C, T, IO>), dim3((p.M2 + p.chunk1 - 1) / p.chunk1, 2 * p.N, batch),
+                           dim3(kThreads), la, s, p.N, M, p.M1, p.M2, p.chunk1, pa, tab, p.src_pos, mode,
+                           (const T *)in, scr, nreal);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_dft_4s_b<C, T, IO>), dim3((p.M1 + p.chunk2 - 1) / p.chunk2, 2 * p.N, batch),
+                           dim3(kThreads), lb, s, p.N, M, p.M1, p.M2, p.chunk2, pb, tab, p.src_pos2, mode, (C)scale,
+                           (const T *)scr, (T *)out, nreal);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
 }
 
-}  // namespace
+// ------------------------------------------------------------- host tables
 
-bool dft_supported(int M, int dtype) {
-    const size_t elt = dtype == 0 ? 16 : 8;
-    // one row in LDS; the generic pass holds at most 32 outputs per thread
-    return elt * (size_t)M <= 160 * 1024 && M <= 32 * 512;
-}
-
-void dft_passes(int M, std::vector<int> &radix, std::vector<int> &blen, std::vector<int> &src_pos) {
-    radix.clear();
-    int m = M;
+std::vector<int> prime_factors(int m) {
+    std::vector<int> f;
     for (int p = 2; (long long)p * p <= m; ++p)
         while (m % p == 0) {
-            radix.push_back(p);
+            f.push_back(p);
             m /= p;
         }
-    if (m > 1) radix.push_back(m);
+    if (m > 1) f.push_back(m);
+    return f;
+}
+
+// radices (largest first), block lengths and the slot of every output
+// frequency after the DIF passes of length L
+void passes_of(int L, std::vector<int> &radix, std::vector<int> &blen, std::vector<int> &src_pos) {
+    radix = prime_factors(L);
     std::sort(radix.rbegin(), radix.rend());
     blen.clear();
-    int L = M;
+    int len = L;
     for (int R : radix) {
-        blen.push_back(L);
-        L /= R;
+        blen.push_back(len);
+        len /= R;
     }
-    // output frequency of every LDS slot after the passes (digit reversal)
-    std::vector<int> freq(M);
+    std::vector<int> freq(L);
     struct Rec {
-        static void go(std::vector<int> &f, const std::vector<int> &rs, size_t d, int pos0, int L, int mult,
+        static void go(std::vector<int> &f, const std::vector<int> &rs, size_t d, int pos0, int len, int mult,
                        int fb) {
             if (d == rs.size()) {
                 f[pos0] = fb;
                 return;
             }
-            const int R = rs[d], Ls = L / R;
+            const int R = rs[d], Ls = len / R;
             for (int k2 = 0; k2 < R; ++k2) go(f, rs, d + 1, pos0 + Ls * k2, Ls, mult * R, fb + k2 * mult);
         }
     };
-    Rec::go(freq, radix, 0, 0, M, 1, 0);
-    src_pos.assign(M, 0);
-    for (int i = 0; i < M; ++i) src_pos[freq[i]] = i;
+    Rec::go(freq, radix, 0, 0, L, 1, 0);
+    src_pos.assign(L, 0);
+    for (int i = 0; i < L; ++i) src_pos[freq[i]] = i;
+}
+
+// two-level table of e^{i pi r / Mt}: lo[j] = e^{i pi j / Mt} (j < 64),
+// hi[j] = e^{i pi 64 j / Mt}
+void phase_table(int Mt, std::vector<double> &t, std::vector<float> &tf) {
+    const int n = tab_entries(Mt);
+    t.assign(2 * (size_t)n, 0.0);
+    tf.assign(2 * (size_t)n, 0.0f);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < n; ++i) {
+        const long long r = i < 64 ? i : 64LL * (i - 64);
+        const long double ph = pi * (long double)(r % (2LL * Mt)) / Mt;
+        t[2 * i] = (double)cosl(ph);
+        t[2 * i + 1] = (double)sinl(ph);
+        tf[2 * i] = (float)cosl(ph);
+        tf[2 * i + 1] = (float)sinl(ph);
+    }
+}
+
+long long powmod(long long b, long long e, long long m) {
+    long long r = 1 % m;
+    b %= m;
+    while (e > 0) {
+        if (e & 1) r = r * b % m;
+        b = b * b % m;
+        e >>= 1;
+    }
+    return r;
+}
+
+int primitive_root(int M) {
+    const std::vector<int> f = prime_factors(M - 1);
+    for (int g = 2; g < M; ++g) {
+        bool ok = true;
+        for (int p : f)
+            if (powmod(g, (M - 1) / p, M) == 1) {
+                ok = false;
+                break;
+            }
+        if (ok) return g;
+    }
+    return 1;
+}
+
+bool fits_rows(int M, size_t elt) {
+    const std::vector<int> f = prime_factors(M);
+    const int maxp = f.empty() ? 1 : *std::max_element(f.begin(), f.end());
+    return elt * ((size_t)M + tab_entries(M)) <= kLds && (maxp <= 13 || M <= 32 * kThreads);
+}
+
+bool fits_rader(int M, size_t elt) {
+    const std::vector<int> f = prime_factors(M - 1);
+    const int maxp = f.empty() ? 1 : *std::max_element(f.begin(), f.end());
+    return elt * ((size_t)(M - 1) + tab_entries(M) + tab_entries(M - 1) + kThreads / 64 + 1) <= kLds &&
+           (maxp <= 13 || M - 1 <= kRaderMaxo * kThreads);
+}
+
+// four-step split with the smallest larger factor whose segments fit
+bool four_step_split(int M, size_t elt, int &M1, int &M2, int &c1, int &c2) {
+    int best = -1;
+    for (int d = 2; (long long)d * d <= M; ++d) {
+        if (M % d) continue;
+        const int a = d, b = M / d;
+        // each workgroup holds chunk x length <= 8192 elements (the generic
+        // pass holds 16 outputs per thread) plus the table
+        if (b > 16 * kThreads) continue;
+        if (elt * ((size_t)b + tab_entries(M)) > kLds) continue;
+        if (best < 0 || b < M / best) best = a;
+    }
+    if (best < 0) return false;
+    M2 = best;  // length of the second pass's transforms
+    M1 = M / best;
+    // chunks: about 4096 elements (FP64; 8192 FP32) so that two workgroups fit
+    // a CU where possible
+    const int target = elt == 16 ? 4096 : 8192;
+    c1 = std::max(1, std::min(M2, target / M1));
+    c2 = std::max(1, std::min(M1, target / M2));
+    while (c1 > 1 && elt * ((size_t)c1 * M1 + tab_entries(M)) > kLds) --c1;
+    while (c2 > 1 && elt * ((size_t)c2 * M2 + tab_entries(M)) > kLds) --c2;
+    return true;
+}
+
+}  // namespace
+
+void dft_build(int M, int dtype, DftHost &h, int force) {
+    const size_t elt = dtype == 0 ? 16 : 8;
+    h = DftHost();
+    h.M = M;
+    phase_table(M, h.tab, h.tabf);
+    const std::vector<int> pf = prime_factors(M);
+    const bool prime = pf.size() == 1 && M > 13;
+    if (((force == 0 && !prime) || force == 1) && fits_rows(M, elt)) {
+        h.kind = kDftRows;
+        passes_of(M, h.radix, h.blen, h.src_pos);
+        return;
+    }
+    if ((force == 0 || force == 2) && prime && fits_rader(M, elt)) {
+        h.kind = kDftRader;
+        const int L = M - 1;
+        passes_of(L, h.radix, h.blen, h.src_pos);
+        phase_table(L, h.ctab, h.ctabf);
+        const int g = primitive_root(M);
+        h.inslot.assign(M, 0);
+        h.outslot.assign(M, 0);
+        std::vector<int> gpow(L);
+        long long v = 1;
+        for (int q = 0; q < L; ++q) {
+            gpow[q] = (int)v;
+            h.inslot[(int)v] = q;
+            v = v * g % M;
+        }
+        for (int k = 1; k < M; ++k) h.outslot[k] = (L - h.inslot[k]) % L;
+        // spectrum of b_q = e^{sgn 2 pi i g^{-q} / M} under the sign -1
+        // transform of length L, divided by L, in digit-reversed slot order;
+        // sgn = +1 (synthesis) then -1 (analysis)
+        const long double pi = 3.141592653589793238462643383279502884L;
+        std::vector<long double> cr(L), ci(L);
+        for (int j = 0; j < L; ++j) {
+            cr[j] = cosl(2 * pi * j / L);
+            ci[j] = -sinl(2 * pi * j / L);
+        }
+        h.bspec.assign(4 * (size_t)L, 0.0);
+        h.bspecf.assign(4 * (size_t)L, 0.0f);
+        for (int si = 0; si < 2; ++si) {
+            const long double sgn = si == 0 ? 1.0L : -1.0L;
+            std::vector<long double> br(L), bi(L);
+            for (int q = 0; q < L; ++q) {
+                const int e = gpow[(L - q) % L];  // g^{-q}
+                br[q] = cosl(2 * pi * e / M);
+                bi[q] = sgn * sinl(2 * pi * e / M);
+            }
+            for (int j = 0; j < L; ++j) {
+                long double sr = 0, sim = 0;
+                long long idx = 0;
+                for (int q = 0; q < L; ++q) {
+                    sr += br[q] * cr[idx] - bi[q] * ci[idx];
+                    sim += br[q] * ci[idx] + bi[q] * cr[idx];
+                    idx += j;
+                    if (idx >= L) idx -= L;
+                }
+                const size_t o = 2 * ((size_t)si * L + h.src_pos[j]);
+                h.bspec[o] = (double)(sr / L);
+                h.bspec[o + 1] = (double)(sim / L);
+                h.bspecf[o] = (float)(sr / L);
+                h.bspecf[o + 1] = (float)(sim / L);
+            }
+        }
+        return;
+    }
+    int M1 = 0, M2 = 0, c1 = 0, c2 = 0;
+    if ((force == 0 || force == 3) && !prime && four_step_split(M, elt, M1, M2, c1, c2)) {
+        h.kind = kDftFourStep;
+        h.M1 = M1;
+        h.M2 = M2;
+        h.chunk1 = c1;
+        h.chunk2 = c2;
+        passes_of(M1, h.radix, h.blen, h.src_pos);
+        passes_of(M2, h.radix2, h.blen2, h.src_pos2);
+        return;
+    }
+    h.kind = kDftNone;
+}
+
+hipError_t dft_init() {
+    hipError_t e = set_attrs<double>();
+    if (e != hipSuccess) return e;
+    return set_attrs<float>();
 }
 
 hipError_t dft_synthesis(const DftPlan &p, int dtype, int batch, void *f, hipStream_t s) {
-    if (dtype == 0) return launch_rows<double, double>(p, batch, 0, 1.0, f, f, s);
-    return launch_rows<float, float>(p, batch, 0, 1.0, f, f, s);
+    if (dtype == 0) return launch<double, double, 0>(p, batch, 0, 1.0, f, f, 0, s);
+    return launch<float, float, 0>(p, batch, 0, 1.0, f, f, 0, s);
 }
 
 hipError_t dft_analysis(const DftPlan &p, int dtype, int batch, double scale, const void *f, void *g,
                         hipStream_t s) {
-    if (dtype == 0) return launch_rows<double, double>(p, batch, 1, scale, f, g, s);
-    return launch_rows<float, float>(p, batch, 1, scale, f, g, s);
+    if (dtype == 0) return launch<double, double, 0>(p, batch, 1, scale, f, g, 0, s);
+    return launch<float, float, 0>(p, batch, 1, scale, f, g, 0, s);
+}
+
+hipError_t dft_synthesis_real(const DftPlan &p, int dtype, int pairs, int nreal, const void *z, void *f,
+                              hipStream_t s) {
+    if (dtype == 0) return launch<double, double, 1>(p, pairs, 0, 1.0, z, f, nreal, s);
+    return launch<float, float, 1>(p, pairs, 0, 1.0, z, f, nreal, s);
+}
+
+hipError_t dft_analysis_real(const DftPlan &p, int dtype, int pairs, int nreal, double scale, const void *f,
+                             void *z, hipStream_t s) {
+    if (dtype == 0) return launch<double, double, 2>(p, pairs, 1, scale, f, z, nreal, s);
+    return launch<float, float, 2>(p, pairs, 1, scale, f, z, nreal, s);
 }
 
 }  // namespace dev

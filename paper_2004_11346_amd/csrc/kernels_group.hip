@@ -7,6 +7,8 @@
 // start to end, so results do not depend on the schedule.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "dense_device.h"
 #include "dft_device.h"
 #include "group.h"
@@ -112,25 +114,51 @@ __global__ __launch_bounds__(512) void k_group_dft(const GTrans *__restrict__ tr
         }
         __syncthreads();
         const int64_t base = 2 * ((int64_t)w.a * 2 * d.N * d.M + (int64_t)w.b * d.M);
-        const C *tw = sizeof(C) == 8 ? (const C *)d.tw2 : (const C *)d.tw2f;
+        const C *tw = sizeof(C) == 8 ? (const C *)d.tab : (const C *)d.tabf;
         if (mode == 0) {
             T *row = (T *)d.f + base;
-            dev::dft::dft_row<C, T, 8>(d.N, d.M, ps, tw, d.src_pos, 0, (C)1, row, row, buf);
+            dev::dft::dft_row<C, T, 8>(d.N, d.M, ps, tw, d.src_pos, 0, (C)1, row, nullptr, row, nullptr, buf);
         } else {
             dev::dft::dft_row<C, T, 8>(d.N, d.M, ps, tw, d.src_pos, 1, (C)(1.0 / d.M), (const T *)d.f + base,
-                                    (T *)d.g + base, buf);
+                                       nullptr, (T *)d.g + base, nullptr, buf);
         }
         __syncthreads();
     }
 }
 
+// segment copies of the batched mode: segment y copies segs[y].units 8-byte
+// words from (to_stage ? ext : stage) to the other side
+__global__ __launch_bounds__(256) void k_copy_segs(const CopySeg *__restrict__ segs, int to_stage) {
+    const CopySeg sg = segs[blockIdx.y];
+    const uint2 *src = (const uint2 *)(to_stage ? sg.ext : sg.stage);
+    uint2 *dst = (uint2 *)(to_stage ? sg.stage : sg.ext);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < sg.units; i += 4 * stride) {
+        const uint2 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < sg.units; i += stride) dst[i] = src[i];
+}
+
 }  // namespace
+
+hipError_t launch_copy_segs(const CopySeg *segs, int nseg, int64_t max_units, int to_stage, hipStream_t s) {
+    if (nseg <= 0) return hipSuccess;
+    prof::Scope ps(s, to_stage ? "k_copy_segs[gather]" : "k_copy_segs[scatter]");
+    const int64_t blocks = std::min<int64_t>(1024, std::max<int64_t>(1, (max_units + 1023) / 1024));
+    hipLaunchKernelGGL(k_copy_segs, dim3((unsigned)blocks, nseg), dim3(256), 0, s, segs, to_stage);
+    return hipGetLastError();
+}
 
 int fwd_rows_per_tile() { return 64 * kNpl; }
 
 hipError_t init_attributes() {
     for (const void *fn : {(const void *)&k_group_dft<double, double>, (const void *)&k_group_dft<float, float>}) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -164,7 +192,7 @@ hipError_t launch_phase(int phase, int dtype, int grid, const GTrans *tr, const 
         default: {
             const int mode = phase == kDftSyn ? 0 : 1;
             prof::Scope ps(s, mode == 0 ? "k_group_dft_synthesis" : "k_group_dft_analysis");
-            const size_t lds = (dtype == 0 ? 16 : 8) * (size_t)max_M;
+            const size_t lds = (dtype == 0 ? 16 : 8) * ((size_t)max_M + dev::dft::tab_entries(max_M));
             if (dtype == 0)
                 hipLaunchKernelGGL((k_group_dft<double, double>), dim3(grid), dim3(512), lds, s, tr, items, nitems,
                                    counter, mode);

@@ -13,39 +13,46 @@ int pivoted_qr(int m, int n, double *a, int lda, double tol, int kmax, std::vect
                std::vector<double> *tau_out) {
     perm.resize(n);
     std::iota(perm.begin(), perm.end(), 0);
-    std::vector<double> norms(n);
+    // partial column norms: vn1 is kept up to date by downdating with the new
+    // row of R after each step; vn2 is the value at the last exact
+    // computation.  When the downdate has cancelled most of a norm, it is
+    // recomputed exactly (the safeguard of LAPACK's column-pivoted QR).
+    std::vector<double> vn1(n), vn2(n);
+    for (int j = 0; j < n; ++j) {
+        const double *c = a + (size_t)j * lda;
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += c[i] * c[i];
+        vn1[j] = vn2[j] = std::sqrt(s);
+    }
+    const double tol3z = std::sqrt(2.220446049250313e-16);
     std::vector<double> tau;
     const int kk = std::min(std::min(m, n), kmax);
     int rank = 0;
     for (int k = 0; k < kk; ++k) {
-        // exact norms of the remaining parts of the columns
         int p = k;
-        double best = -1.0;
-        for (int j = k; j < n; ++j) {
-            const double *c = a + (size_t)j * lda;
-            double s = 0.0;
-            for (int i = k; i < m; ++i) s += c[i] * c[i];
-            norms[j] = s;
-            if (s > best) {
-                best = s;
-                p = j;
-            }
-        }
-        if (std::sqrt(best) <= tol) break;
+        for (int j = k + 1; j < n; ++j)
+            if (vn1[j] > vn1[p]) p = j;
         if (p != k) {
             std::swap_ranges(a + (size_t)k * lda, a + (size_t)k * lda + m, a + (size_t)p * lda);
             std::swap(perm[k], perm[p]);
+            std::swap(vn1[k], vn1[p]);
+            std::swap(vn2[k], vn2[p]);
         }
-        // Householder reflector for column k, rows k..m-1
+        // exact norm of the pivot column's remaining part
         double *c = a + (size_t)k * lda;
+        double best = 0.0;
+        for (int i = k; i < m; ++i) best += c[i] * c[i];
+        const double xnorm = std::sqrt(best);
+        if (xnorm <= tol) break;
+        // Householder reflector for column k, rows k..m-1
         double alpha = c[k];
-        double xnorm = std::sqrt(best);
         double beta = alpha >= 0 ? -xnorm : xnorm;
         double t = (beta - alpha) / beta;
         double scale = 1.0 / (alpha - beta);
         for (int i = k + 1; i < m; ++i) c[i] *= scale;
         c[k] = beta;
         // apply H = I - t v v^T (v = [1; c[k+1:m]]) to the remaining columns
+        // and downdate their norms by the new entry R(k, j)
         for (int j = k + 1; j < n; ++j) {
             double *d = a + (size_t)j * lda;
             double s = d[k];
@@ -53,6 +60,18 @@ int pivoted_qr(int m, int n, double *a, int lda, double tol, int kmax, std::vect
             s *= t;
             d[k] -= s;
             for (int i = k + 1; i < m; ++i) d[i] -= s * c[i];
+            if (vn1[j] != 0.0) {
+                double r = std::fabs(d[k]) / vn1[j];
+                r = std::max(0.0, (1.0 + r) * (1.0 - r));
+                const double q = vn1[j] / vn2[j];
+                if (r * q * q <= tol3z) {
+                    double e = 0.0;
+                    for (int i = k + 1; i < m; ++i) e += d[i] * d[i];
+                    vn1[j] = vn2[j] = std::sqrt(e);
+                } else {
+                    vn1[j] *= std::sqrt(r);
+                }
+            }
         }
         tau.push_back(t);
         rank = k + 1;

@@ -22,6 +22,9 @@ SHT_DENSE, SHT_IDBF = 0, 1
 SHT_FWD, SHT_INV, SHT_ADJ = 0, 1, 2
 SHT_F32_VALU, SHT_F32_SPLIT_BF16, SHT_F32_SPLIT_BF16_6 = 0, 1, 2
 SHT_SAMPLE_MOCK_CHEB, SHT_SAMPLE_RANDOM = 0, 1
+SHT_DFT_AUTO, SHT_DFT_ROWS, SHT_DFT_RADER, SHT_DFT_FOUR_STEP = 0, 1, 2, 3
+SHT_ERR_INVALID_ARG, SHT_ERR_UNSUPPORTED, SHT_ERR_PLAN_CORRUPT = -1, -2, -7
+SHT_GROUP_PERSISTENT, SHT_GROUP_BATCHED = 0, 1
 
 EXPORTED = [
     "sht_plan_opts_default", "sht_plan_create", "sht_plan_destroy", "sht_forward", "sht_inverse",
@@ -30,6 +33,8 @@ EXPORTED = [
     "sht_host_plan_apply", "sht_host_alt_matrix", "sht_host_plan_stats", "sht_host_gauss_legendre",
     "sht_group_create", "sht_group_destroy", "sht_group_bind", "sht_group_forward", "sht_group_inverse",
     "sht_group_tune", "sht_group_capture", "sht_group_replay", "sht_group_stats", "sht_inverse_noalloc",
+    "sht_set_graph_capture", "sht_plan_cache_verify", "sht_plan_cache_path",
+    "sht_forward_real", "sht_inverse_real", "sht_group_opts_default", "sht_group_create_ex",
 ]
 
 
@@ -56,7 +61,14 @@ class PlanOpts(ctypes.Structure):
         ("dense_gen", ctypes.c_int),
         ("m_lo", ctypes.c_int),
         ("m_hi", ctypes.c_int),
+        ("dft_schedule", ctypes.c_int),
+        ("id_check", ctypes.c_int),
+        ("cache_dir", ctypes.c_char_p),
     ]
+
+
+class GroupOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("tune_file", ctypes.c_char_p), ("plan_cache_dir", ctypes.c_char_p)]
 
 
 _lock = threading.Lock()
@@ -84,6 +96,11 @@ def load():
         for n in ("sht_forward", "sht_inverse", "sht_backward", "sht_inverse_noalloc"):
             getattr(lib, n).argtypes = [P, P, P, P]
         lib.sht_alt_apply.argtypes = [P, I, I, I, P, P, P]
+        lib.sht_set_graph_capture.argtypes = [P, I]
+        lib.sht_forward_real.argtypes = [P, I, P, P, P]
+        lib.sht_inverse_real.argtypes = [P, I, P, P, P]
+        lib.sht_plan_cache_verify.argtypes = [ctypes.c_char_p]
+        lib.sht_plan_cache_path.argtypes = [I, ctypes.POINTER(PlanOpts), ctypes.c_char_p, ctypes.c_size_t]
         lib.sht_plan_stats.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
         lib.sht_profile.argtypes = [P, I]
         lib.sht_profile_report.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
@@ -102,6 +119,9 @@ def load():
         lib.sht_host_plan_stats.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
         lib.sht_host_gauss_legendre.argtypes = [I, P, P]
         lib.sht_group_create.argtypes = [I, P, P, I, PP]
+        lib.sht_group_opts_default.argtypes = [ctypes.POINTER(GroupOpts)]
+        lib.sht_group_opts_default.restype = None
+        lib.sht_group_create_ex.argtypes = [I, P, P, I, ctypes.POINTER(GroupOpts), PP]
         lib.sht_group_destroy.argtypes = [P]
         lib.sht_group_destroy.restype = None
         lib.sht_group_bind.argtypes = [P, P, P]
@@ -138,5 +158,7 @@ def default_opts(**kw) -> PlanOpts:
     for k, v in kw.items():
         if not hasattr(o, k):
             raise TypeError(f"unknown plan option {k}")
+        if k == "cache_dir" and isinstance(v, str):
+            v = v.encode()
         setattr(o, k, v)
     return o

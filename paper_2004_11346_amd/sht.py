@@ -54,7 +54,8 @@ class Plan:
     method: "dense" (plain form) or "idbf" (fast form).
     dtype:  torch.complex128 (FP64) or torch.complex64 (FP32).
     Extra keyword arguments set ``sht_plan_opts`` fields (eps, n0, leaf, rk,
-    oversample, rsvd_r, rsvd_q, sampling, seed, threads, f32_mode, min_idbf).
+    oversample, rsvd_r, rsvd_q, sampling, seed, threads, f32_mode, min_idbf,
+    dense_gen, m_lo, m_hi, dft_schedule, cache_dir).
     """
 
     def __init__(self, N: int, batch: int = 1, dtype=torch.complex128, method: str = "dense", **opts):
@@ -117,6 +118,42 @@ class Plan:
         _l.check(self._lib.sht_inverse(self._h, f.data_ptr(), out.data_ptr(),
                                        ctypes.c_void_p(_stream_ptr(stream))), "sht_inverse")
         return out
+
+    # ------------------------------------------------------------ real fields
+    @property
+    def half_coef_count(self):
+        return self.N * (2 * self.N + 1)
+
+    @property
+    def real_dtype(self):
+        return torch.float64 if self.dtype == torch.complex128 else torch.float32
+
+    def forward_real(self, beta_half: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Forward SHT of real fields: beta_half [nreal, N(2N+1)] complex (orders
+        m >= 0) -> real grid values [nreal, 2N, 4N-1]."""
+        nreal = beta_half.shape[0] if beta_half.dim() == 2 else -1
+        self._check(beta_half, (nreal, self.half_coef_count), "beta_half")
+        out = torch.empty((nreal, 2 * self.N, self.M), dtype=self.real_dtype, device=beta_half.device) \
+            if out is None else out
+        check_tensor(out, self.real_dtype, (nreal, 2 * self.N, self.M), "out")
+        _l.check(self._lib.sht_forward_real(self._h, nreal, beta_half.data_ptr(), out.data_ptr(),
+                                            ctypes.c_void_p(_stream_ptr(stream))), "sht_forward_real")
+        return out
+
+    def inverse_real(self, f: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Inverse SHT of real fields: real grid [nreal, 2N, 4N-1] -> beta_half."""
+        nreal = f.shape[0] if f.dim() == 3 else -1
+        check_tensor(f, self.real_dtype, (nreal, 2 * self.N, self.M), "f")
+        out = torch.empty((nreal, self.half_coef_count), dtype=self.dtype, device=f.device) if out is None else out
+        self._check(out, (nreal, self.half_coef_count), "out")
+        _l.check(self._lib.sht_inverse_real(self._h, nreal, f.data_ptr(), out.data_ptr(),
+                                            ctypes.c_void_p(_stream_ptr(stream))), "sht_inverse_real")
+        return out
+
+    def set_graph_capture(self, enable: bool = True):
+        """Graph mode: forward / inverse / backward calls replay a hipGraph per
+        (direction, input, output) after their first call."""
+        _l.check(self._lib.sht_set_graph_capture(self._h, int(bool(enable))), "sht_set_graph_capture")
 
     def inverse_noalloc(self, f: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
         """Inverse SHT that allocates nothing: the phi-analysed grid is staged in
@@ -187,12 +224,15 @@ def host_gauss_legendre(n: int):
 
 
 class Group:
-    """Many independent transforms of different degrees (``Ns[i]``, 1..1024)
-    and field counts (``fields[i]``, 1..4) applied together by persistent
-    kernels.  Bind the per-transform tensors once, then call ``forward`` /
-    ``inverse`` (or capture them into a hipGraph and ``replay``)."""
+    """Many independent transforms of different degrees (``Ns[i]``) and field
+    counts (``fields[i]``) applied together.  mode "persistent": persistent
+    kernels over a longest-first queue (N <= 1024, 1-4 fields); mode
+    "batched": one tuned plan per distinct degree over all its fields.  Bind
+    the per-transform tensors once, then call ``forward`` / ``inverse`` (or
+    capture them into a hipGraph and ``replay``)."""
 
-    def __init__(self, Ns, fields, dtype=torch.complex128):
+    def __init__(self, Ns, fields, dtype=torch.complex128, mode: str = "persistent", tune_file=None,
+                 plan_cache_dir=None):
         self._lib = _l.load()
         self.Ns = [int(n) for n in Ns]
         self.fields = [int(f) for f in fields]
@@ -202,8 +242,13 @@ class Group:
         n = len(self.Ns)
         arr = ctypes.c_int * n
         h = ctypes.c_void_p()
-        _l.check(self._lib.sht_group_create(n, arr(*self.Ns), arr(*self.fields), _DT[dtype], ctypes.byref(h)),
-                 "sht_group_create")
+        o = _l.GroupOpts()
+        self._lib.sht_group_opts_default(ctypes.byref(o))
+        o.mode = {"persistent": _l.SHT_GROUP_PERSISTENT, "batched": _l.SHT_GROUP_BATCHED}[mode]
+        self._keep = [s.encode() if isinstance(s, str) else s for s in (tune_file, plan_cache_dir)]
+        o.tune_file, o.plan_cache_dir = self._keep
+        _l.check(self._lib.sht_group_create_ex(n, arr(*self.Ns), arr(*self.fields), _DT[dtype], ctypes.byref(o),
+                                               ctypes.byref(h)), "sht_group_create")
         self._h = h
         self._bound = None
 

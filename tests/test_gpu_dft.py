@@ -1,0 +1,144 @@
+"""The three phi DFT schedules (Section 1, eq. `sht_fft`: rows in LDS, Rader's
+convolution for prime M = 4N - 1, four-step through a grid-sized buffer)
+against the oracle, through the C ABI.
+
+* Every schedule is forced at small N, where the oracle computes the whole
+  transform: forward SHT, adjoint and round trip, FP64 and FP32 (plain ALT,
+  so only the DFT schedule changes).
+* At N = 1500 the forced four-step runs with partial chunks in both kernels.
+* At N = 2048 (M = 8191 prime: Rader) and N = 4096 (M = 16383 = 3 43 127:
+  four-step in FP64, rows in FP32), where the full oracle transform takes too
+  long, the forward SHT of coefficients that are non-zero at a few orders only
+  is compared at sampled rows with the oracle's ALT of those orders followed by
+  its direct phi sums; the inverse is checked by round trip and the adjoint by
+  the dot-product identity <S b, y> = <b, S^H y>.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2004_11346_amd import inputs
+from paper_2004_11346_amd import lib as L
+
+pytestmark = pytest.mark.gpu
+
+SCHED = {"rows": L.SHT_DFT_ROWS, "rader": L.SHT_DFT_RADER, "four_step": L.SHT_DFT_FOUR_STEP}
+TOL = {torch.complex128: 1e-12, torch.complex64: 2e-6}
+# large N: the FP64 bar of the whole path (the plain ALT's recurrence over
+# thousands of degrees dominates the error there)
+TOL_LARGE = {torch.complex128: 1e-11, torch.complex64: 2e-6}
+
+
+def rel_l2(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def _cast(a, dtype):
+    return a if dtype == torch.complex128 else a.astype(np.complex64).astype(np.complex128)
+
+
+# (N, schedule): M = 19 (prime), 63 = 3^2 7, 131 (prime), 255 = 3 5 17,
+# 519 = 3 173 (a large prime factor: generic pass / four-step 173 x 3)
+CASES = [(5, "rows"), (5, "rader"), (16, "rows"), (16, "four_step"), (33, "rader"), (33, "rows"),
+         (64, "rows"), (64, "four_step"), (130, "rows"), (130, "four_step")]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("N,sched", CASES)
+def test_forced_schedule_vs_oracle(N, sched, dtype):
+    from paper_2004_11346_amd.sht import Plan
+    print(f"dft schedule {sched} N={N} {dtype}", flush=True)
+    batch = 2
+    p = Plan(N, batch, dtype=dtype, method="dense", dft_schedule=SCHED[sched])
+    beta = _cast(inputs.make_beta(N, batch, 1), dtype)
+    bd = torch.from_numpy(beta).to(dtype).cuda()
+    f = p.forward(bd)
+    back = p.inverse(f)
+    grid = _cast(inputs.make_grid(N, batch, 5), dtype)
+    adj = p.backward(torch.from_numpy(grid).to(dtype).cuda())
+    torch.cuda.synchronize()
+    fh, bh, ah = f.cpu().numpy(), back.cpu().numpy(), adj.cpu().numpy()
+    for b in range(batch):
+        assert rel_l2(fh[b], oracle.sht_forward(N, beta[b])) <= TOL[dtype], b
+        assert rel_l2(ah[b], oracle.sht_adjoint(N, grid[b])) <= TOL[dtype], b
+    assert rel_l2(bh, beta) <= TOL[dtype]
+    p.close()
+
+
+def test_schedule_that_does_not_apply_is_refused():
+    from paper_2004_11346_amd.sht import Plan
+    from paper_2004_11346_amd.lib import ShtError
+    with pytest.raises(ShtError):
+        Plan(16, 1, method="dense", dft_schedule=L.SHT_DFT_RADER)  # M = 63 is not prime
+    with pytest.raises(ShtError):
+        Plan(5, 1, method="dense", dft_schedule=L.SHT_DFT_FOUR_STEP)  # M = 19 has no split
+
+
+def _sparse_beta(N, orders, seed):
+    """Coefficients that are non-zero only at the listed signed orders, with the
+    workloads' variance (k + 1)^-2."""
+    k_of, m_of = inputs.layout(N)
+    beta = inputs.make_beta(N, 1, seed, dist="decay")[0]
+    keep = np.isin(m_of, orders)
+    beta[~keep] = 0
+    return beta
+
+
+def _expected_rows(N, beta, orders, rows):
+    """The oracle's f at the listed rows for coefficients supported on `orders`."""
+    M = 4 * N - 1
+    absm = sorted({abs(m) for m in orders})
+    ga = oracle.alt_forward_orders(N, beta, absm)
+    g = np.zeros((2 * N, M), dtype=np.complex128)
+    for i, a in enumerate(absm):
+        g[:, a % M] = ga[i, 0]
+        if a:
+            g[:, (-a) % M] = ga[i, 1]
+    return oracle.dft_synthesis(N, g, rows=rows)
+
+
+@pytest.mark.parametrize("N,dtype,sched", [(1500, torch.complex128, "four_step"), (2048, torch.complex128, None),
+                                           (4096, torch.complex128, None), (4096, torch.complex64, None),
+                                           (2048, torch.complex64, None)])
+def test_large_rows_vs_oracle(N, dtype, sched):
+    from paper_2004_11346_amd.sht import Plan
+    kw = {} if sched is None else {"dft_schedule": SCHED[sched]}
+    print(f"dft large N={N} {dtype} {sched or 'auto'}", flush=True)
+    p = Plan(N, 1, dtype=dtype, method="dense", **kw)
+    orders = [0, 1, -1, 7, -300, N, -(N + 1), 2 * N - 1, -(2 * N - 1)]
+    beta = _cast(_sparse_beta(N, orders, 11), dtype)
+    f = p.forward(torch.from_numpy(beta[None]).to(dtype).cuda())
+    rows = [0, 1, N - 1, N, 2 * N - 3]
+    got = f[0, rows].cpu().numpy()
+    err = rel_l2(got, _expected_rows(N, beta, orders, rows))
+    # the ALT alone at the same orders and rows, to separate the DFT's share
+    M = 4 * N - 1
+    g = torch.zeros((1, 2 * N, M), dtype=dtype, device="cuda")
+    p.alt(0, 2 * N - 1, "fwd", torch.from_numpy(beta[None]).to(dtype).cuda(), g)
+    absm = sorted({abs(m) for m in orders})
+    ga = oracle.alt_forward_orders(N, beta, absm)
+    cols = [c for a in absm for c in ((a % M, (-a) % M) if a else (0,))]
+    ref_g = np.stack([ga[i, s][rows] for i, a in enumerate(absm) for s in ((0, 1) if a else (0,))])
+    err_alt = rel_l2(g[0][rows][:, cols].cpu().numpy().T, ref_g)
+    print(f"forward at sampled rows: {err:.3e} (ALT alone at those rows and orders: {err_alt:.3e})", flush=True)
+    assert err <= TOL_LARGE[dtype]
+    # round trip on generic coefficients
+    bfull = _cast(inputs.make_beta(N, 1, 12, dist="decay"), dtype)
+    bt = torch.from_numpy(bfull).to(dtype).cuda()
+    back = p.inverse(p.forward(bt))
+    rt = rel_l2(back.cpu().numpy(), bfull)
+    print(f"round trip: {rt:.3e}", flush=True)
+    assert rt <= TOL_LARGE[dtype]
+    # adjoint: <S b, y> = <b, S^H y>
+    y = torch.from_numpy(_cast(inputs.make_grid(N, 1, 13), dtype)).to(dtype).cuda()
+    sb = p.forward(bt)
+    shy = p.backward(y)
+    lhs = torch.vdot(y.reshape(-1).to(torch.complex128), sb.reshape(-1).to(torch.complex128)).item()
+    rhs = torch.vdot(shy.reshape(-1).to(torch.complex128), bt.reshape(-1).to(torch.complex128)).item()
+    rel = abs(lhs - rhs) / abs(lhs)
+    print(f"adjoint identity: {rel:.3e}", flush=True)
+    assert rel <= TOL_LARGE[dtype]
+    p.close()

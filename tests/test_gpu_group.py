@@ -125,3 +125,69 @@ def test_uneven_workload(dtype, tol):
         for i in range(len(Ns)):
             assert torch.equal(fs[i], f_eager[i]), (rep, i)
         _ = torch.randn(1000, device="cuda").sum().item()
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 2e-6)])
+def test_batched_group_vs_oracle(dtype, tol, tmp_path):
+    """Batched mode: degrees shared by several transforms (staging copies) and
+    single ones (direct), against the oracle; tuning (plain vs fast-form plans
+    per degree) keeps the results within the bar, writes its choices to the
+    tune file, and a new group reads them back; graph replays equal eager."""
+    from paper_2004_11346_amd.sht import Group
+    Ns = [16, 64, 16, 33, 64, 5, 64]
+    fields = [1, 2, 3, 2, 1, 4, 2]
+    tune = str(tmp_path / "tune.json")
+    print(f"batched group {dtype}", flush=True)
+    g = Group(Ns, fields, dtype=dtype, mode="batched", tune_file=tune)
+    betas, fs, bnp = _tensors(Ns, fields, dtype, 7300)
+
+    def check_forward():
+        for i, (N, f) in enumerate(zip(Ns, fields)):
+            got = fs[i].cpu().numpy()
+            for b in range(f):
+                assert rel_l2(got[b], oracle.sht_forward(N, bnp[i][b])) <= tol, (i, b)
+
+    g.bind(betas, fs)
+    g.forward()
+    torch.cuda.synchronize()
+    check_forward()
+    grids = []
+    for i, (N, f) in enumerate(zip(Ns, fields)):
+        gr = inputs.make_grid(N, f, 7400 + i)
+        if dtype == torch.complex64:
+            gr = gr.astype(np.complex64).astype(np.complex128)
+        grids.append(gr)
+        fs[i].copy_(torch.from_numpy(gr).to(dtype))
+    g.inverse()
+    torch.cuda.synchronize()
+    for i, (N, f) in enumerate(zip(Ns, fields)):
+        got = betas[i].cpu().numpy()
+        for b in range(f):
+            assert rel_l2(got[b], oracle.sht_inverse(N, grids[i][b])) <= tol, (i, b)
+    g.tune()
+    st = g.stats()
+    assert st["mode"] == "batched" and st["tuned"] and len(st["classes"]) == 4
+    for i in range(len(Ns)):
+        betas[i].copy_(torch.from_numpy(bnp[i]).to(dtype))
+    g.forward()
+    torch.cuda.synchronize()
+    check_forward()
+    f_eager = [t.clone() for t in fs]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g.capture("fwd", s)
+    for rep in range(3):
+        for t in fs:
+            t.zero_()
+        torch.cuda.synchronize()
+        g.replay("fwd", s)
+        s.synchronize()
+        for i in range(len(Ns)):
+            assert torch.equal(fs[i], f_eager[i]), (rep, i)
+        _ = torch.randn(1000, device="cuda").sum().item()
+    chosen = {c["N"]: (c["method"], c["leaf"]) for c in st["classes"]}
+    g.close()
+    g2 = Group(Ns, fields, dtype=dtype, mode="batched", tune_file=tune)
+    st2 = g2.stats()
+    assert {c["N"]: (c["method"], c["leaf"]) for c in st2["classes"]} == chosen
+    g2.close()

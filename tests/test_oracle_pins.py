@@ -343,3 +343,44 @@ def test_weighted_energy_gradient_closed_form():
     f = oracle.sht_forward(N, beta)
     grad = oracle.sht_adjoint(N, 2 * w[:, None] * f)
     np.testing.assert_allclose(grad, 2 * M * beta, rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- real fields
+def test_real_field_single_mode_closed_form():
+    """A real field with one coefficient c at (k0, m0 > 0) of the half layout is
+    f = 2 Re(c e^{i m0 phi}) Pbar_{k0}^{m0}(x) (the -m0 term is its conjugate);
+    at m0 = 0 it is Re(c) Pbar_{k0}^0(x)."""
+    N = 5
+    M = 4 * N - 1
+    x, _ = oracle.gauss_legendre(2 * N)
+    phi = 2 * np.pi * (np.arange(M) + 0.5) / M
+    for (k0, m0, c) in [(3, 2, 0.7 - 0.4j), (9, 9, -1.1 + 0.3j), (6, 1, 0.25j), (4, 0, 1.5 + 2.0j)]:
+        half = np.zeros(N * (2 * N + 1), complex)
+        off = 2 * N * m0 - m0 * (m0 - 1) // 2  # half layout: order m0 starts here
+        half[off + k0 - m0] = c
+        f = oracle.sht_forward_real(N, half)
+        p = np.array([oracle.plm(m0, k0, t)[k0 - m0] for t in x])
+        ref = p[:, None] * ((2 * (c * np.exp(1j * m0 * phi)).real) if m0 else np.full(M, c.real))[None, :]
+        np.testing.assert_allclose(f, ref, rtol=0, atol=4e-14)
+
+
+@pytest.mark.parametrize("N", [3, 8, 17])
+def test_real_field_extension_gives_real_grid_and_round_trip(N):
+    """beta_{k,-m} = conj(beta_{k,m}) makes the complex transform real (a
+    (-1)^m factor, the relation of Condon-Shortley-phased bases, would not),
+    and the inverse of a real grid returns the half coefficients (imaginary
+    part 0 at m = 0)."""
+    half = inputs.make_beta(N, 1, 60)[0][: N * (2 * N + 1)]
+    full = oracle.real_to_full(N, half)
+    f = oracle.sht_forward(N, full)
+    assert np.abs(f.imag).max() <= 1e-14 * np.abs(f.real).max()
+    k_of, m_of = inputs.layout(N)
+    wrong = full.copy()
+    neg = m_of < 0
+    wrong[neg] *= (-1.0) ** np.abs(m_of[neg])
+    assert np.abs(oracle.sht_forward(N, wrong).imag).max() > 1e-3 * np.abs(f.real).max()
+    back = oracle.sht_inverse_real(N, oracle.sht_forward_real(N, half))
+    ref = half.copy()
+    ref[: 2 * N] = ref[: 2 * N].real  # order 0 is real
+    np.testing.assert_allclose(back, ref, rtol=0, atol=1e-13)
+    np.testing.assert_array_equal(oracle.full_to_real(N, full), ref)
