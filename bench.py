@@ -324,6 +324,40 @@ def profile_target(args):
                       "alt_calls": args.steps, "copy_bytes": 2 * a.numel() * 8}), flush=True)
 
 
+def n4096_full(S, inputs, timer, no_check):
+    """N = 4096 (grid 8192 x 16383), 8 fields, FP64, plain form: full forward
+    and inverse SHT (the phi DFT rows exceed LDS and run as two four-step
+    kernels), with the error at sampled orders and rows against the oracle."""
+    import numpy as np
+    import torch
+    N, B = 4096, 8
+    M = 4 * N - 1
+    t0 = time.perf_counter()
+    p = S.Plan(N, B, dtype=torch.complex128, method="dense")
+    tb = time.perf_counter() - t0
+    beta_np = inputs.make_beta(N, B, 3, dist="decay")
+    beta = torch.from_numpy(beta_np).cuda()
+    f = p.forward(beta)
+    bo = p.inverse(f)
+    tf = timer.time(lambda: p.forward(beta, out=f), reps=2)
+    ti = timer.time(lambda: p.inverse(f, out=bo), reps=2)
+    r = {"fwd_ms": tf * 1e3, "inv_ms": ti * 1e3, "sht_per_s": 2 * B / (tf + ti), "plan_build_s": tb,
+         "alt_gcoef_per_s_fwd_incl_dft": B * 4 * N * N / tf / 1e9}
+    if not no_check:
+        import oracle
+        rows = [0, 4095, 8191]
+        g = oracle.alt_forward_rows(N, beta_np[0], rows)
+        gg = np.zeros((2 * N, M), complex)
+        gg[rows] = g
+        ref = oracle.dft_synthesis(N, gg, rows=rows)
+        r["fwd_sampled_rows_rel_l2"] = rel_l2(f[0, rows].cpu().numpy(), ref)
+        r["round_trip_rel_l2"] = rel_l2(bo.cpu().numpy(), beta_np)
+    p.close()
+    del beta, f, bo
+    torch.cuda.empty_cache()
+    return r
+
+
 def n4096_orders(args):
     """N = 4096 (grid 8192 x 16383), 8 fields, FP64: the fast form (plans
     restricted to 64-order windows, the unit of per-GPU sharding) against the
@@ -754,6 +788,21 @@ def main():
             torch.cuda.empty_cache()
         if args.dtype == "f64" and method == "idbf":
             det.update(fp32_legs(S, inputs, timer, N, batch, beta_np, args.no_check))
+        # real fields: 2 batch real fields on the same plan (two per complex
+        # transform), forward and inverse
+        nreal = 2 * batch
+        half = torch.from_numpy(inputs.make_beta(N, nreal, 8, dist="decay")[:, : N * (2 * N + 1)].copy()).to(cdt).cuda()
+        fr = plan.forward_real(half)
+        hb = plan.inverse_real(fr)
+        tfr = timer.time(lambda: plan.forward_real(half, out=fr), reps=3)
+        tir = timer.time(lambda: plan.inverse_real(fr, out=hb), reps=3)
+        det[f"real_fields_{nreal}"] = {"fwd_ms": tfr * 1e3, "inv_ms": tir * 1e3,
+                                       "sht_per_s": 2 * nreal / (tfr + tir),
+                                       "note": f"{nreal} real fields on the {batch}-field plan"}
+        del half, fr, hb
+        torch.cuda.empty_cache()
+        if N == 1024 and args.dtype == "f64":
+            det["n4096_plain_b8"] = n4096_full(S, inputs, timer, args.no_check)
         out["details"] = det
 
     if not args.no_cpu_baseline:

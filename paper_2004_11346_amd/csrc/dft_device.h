@@ -45,56 +45,153 @@ __device__ __forceinline__ typename V2<C>::t cmul(typename V2<C>::t a, typename 
 // entries of the two-level table of base Mt
 __host__ __device__ inline int tab_entries(int Mt) { return 64 + (2 * Mt + 63) / 64; }
 
-// e^{sgn i pi r / Mt}, 0 <= r < 2 Mt, from the table in LDS
-template <typename C>
-__device__ __forceinline__ typename V2<C>::t tw(const typename V2<C>::t *t, int r, C sgn) {
-    typename V2<C>::t p = cmul<C>(t[r & 63], t[64 + (r >> 6)]);
+// e^{sgn i pi r / Mt}, 0 <= r < 2 Mt, from the FP64 table in LDS
+__device__ __forceinline__ double2 twd(const double2 *t, int r, double sgn) {
+    double2 p = cmul<double>(t[r & 63], t[64 + (r >> 6)]);
     p.y *= sgn;
     return p;
 }
 
-// copy a table of base Mt from global memory to LDS
 template <typename C>
-__device__ __forceinline__ void load_tab(const C *__restrict__ g, int Mt, typename V2<C>::t *t) {
-    typedef typename V2<C>::t c2;
+__device__ __forceinline__ typename V2<C>::t tw(const double2 *t, int r, C sgn) {
+    const double2 p = twd(t, r, (double)sgn);
+    return typename V2<C>::t{(C)p.x, (C)p.y};
+}
+
+// copy a table of base Mt from global memory to LDS (FP64 for every element
+// type: twiddle powers are formed from it in FP64)
+__device__ __forceinline__ void load_tab(const double *__restrict__ g, int Mt, double2 *t) {
     const int n = tab_entries(Mt);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) t[i] = reinterpret_cast<const c2 *>(g)[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) t[i] = reinterpret_cast<const double2 *>(g)[i];
+}
+
+// a wave-uniform double moved to scalar registers
+__device__ __forceinline__ double uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// cos and sin of 2 pi q / R for q = 1 .. (R - 1) / 2 (odd R); the same for
+// every lane, so they live in scalar registers
+template <int R>
+__device__ __forceinline__ void roots(const double2 *t, int Mt, double (&c)[(R - 1) / 2 + 1],
+                                      double (&sn)[(R - 1) / 2 + 1]) {
+#pragma unroll
+    for (int q = 1; q <= (R - 1) / 2; ++q) {
+        const double2 w = twd(t, 2 * q * (Mt / R), 1.0);
+        c[q] = uniform(w.x);
+        sn[q] = uniform(w.y);
+    }
+}
+
+// R-point DFT of x (sign sgn) in place, odd R: with s_j = x_j + x_{R-j} and
+// d_j = x_j - x_{R-j}, y_k = x_0 + sum_j s_j cos(2 pi j k / R)
+// + i sgn sum_j d_j sin(2 pi j k / R) and y_{R-k} the same with -i: half the
+// products of the direct sum and half the roots.
+template <typename C, int R>
+__device__ __forceinline__ void dft_small(typename V2<C>::t (&x)[R], const double (&c)[(R - 1) / 2 + 1],
+                                          const double (&sn)[(R - 1) / 2 + 1], C sgn) {
+    typedef typename V2<C>::t c2;
+    if constexpr (R == 2) {
+        const c2 a = x[0], b = x[1];
+        x[0] = c2{a.x + b.x, a.y + b.y};
+        x[1] = c2{a.x - b.x, a.y - b.y};
+    } else {
+        constexpr int H = (R - 1) / 2;
+        c2 sj[H + 1], dj[H + 1];
+        c2 y0 = x[0];
+#pragma unroll
+        for (int j = 1; j <= H; ++j) {
+            sj[j] = c2{x[j].x + x[R - j].x, x[j].y + x[R - j].y};
+            dj[j] = c2{x[j].x - x[R - j].x, x[j].y - x[R - j].y};
+            y0.x += sj[j].x;
+            y0.y += sj[j].y;
+        }
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            c2 a = x[0], b = c2{(C)0, (C)0};
+#pragma unroll
+            for (int j = 1; j <= H; ++j) {
+                const int q = (j * k) % R;
+                const C cq = (C)(q <= H ? c[q] : c[R - q]);
+                const C sq = (C)(q <= H ? sn[q] : -sn[R - q]);
+                a.x += cq * sj[j].x;
+                a.y += cq * sj[j].y;
+                b.x += sq * dj[j].x;
+                b.y += sq * dj[j].y;
+            }
+            b.x *= sgn;
+            b.y *= sgn;
+            x[k] = c2{a.x - b.y, a.y + b.x};      // a + i b
+            x[R - k] = c2{a.x + b.y, a.y - b.x};  // a - i b
+        }
+        x[0] = y0;
+    }
 }
 
 // register butterflies of radix R over blocks of length L (table base Mt,
-// L divides Mt), `total` elements
+// L divides Mt), `total` elements.  The twiddles w_L^{n1 k2} of a butterfly
+// are powers of w_L^{n1}, formed in FP64 from one table lookup; the outputs
+// k and R - k are stored as soon as they are formed (w^{R-k} = w^R conj(w^k)),
+// which keeps the live registers to the sums and differences of the inputs.
 template <typename C, int R>
-__device__ __forceinline__ void pass_reg(typename V2<C>::t *buf, int total, int L, const typename V2<C>::t *t,
-                                         int Mt, C sgn) {
+__device__ __forceinline__ void pass_reg(typename V2<C>::t *buf, int total, int L, const double2 *t, int Mt,
+                                         C sgn) {
     typedef typename V2<C>::t c2;
+    constexpr int H = (R - 1) / 2;
     const int Ls = L / R;
-    const int twoM = 2 * Mt;
-    c2 wr[R];  // w_R^q
-#pragma unroll
-    for (int q = 0; q < R; ++q) wr[q] = tw<C>(t, (2 * q * (Mt / R)) % twoM, sgn);
+    double c[H + 1], sn[H + 1];
+    if constexpr (R > 2) roots<R>(t, Mt, c, sn);
     const int unitL = 2 * (Mt / L);
     const int nb = total / R;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         const int blk = b / Ls, n1 = b - blk * Ls;
         const int base = blk * L + n1;
-        c2 x[R];
+        const double2 w1 = twd(t, n1 * unitL, (double)sgn);
+        if constexpr (R == 2) {
+            const c2 x0 = buf[base], x1 = buf[base + Ls];
+            buf[base] = c2{x0.x + x1.x, x0.y + x1.y};
+            buf[base + Ls] = cmul<C>(c2{x0.x - x1.x, x0.y - x1.y}, c2{(C)w1.x, (C)w1.y});
+        } else {
+            const c2 x0 = buf[base];
+            c2 sj[H + 1], dj[H + 1];
+            c2 y0 = x0;
 #pragma unroll
-        for (int n2 = 0; n2 < R; ++n2) x[n2] = buf[base + Ls * n2];
-        const int step = n1 * unitL;  // < 2 Mt / R
-        int ti = 0;
-#pragma unroll
-        for (int k2 = 0; k2 < R; ++k2) {
-            c2 y = x[0];
-#pragma unroll
-            for (int n2 = 1; n2 < R; ++n2) {
-                const c2 p = cmul<C>(x[n2], wr[(n2 * k2) % R]);
-                y.x += p.x;
-                y.y += p.y;
+            for (int j = 1; j <= H; ++j) {
+                const c2 u = buf[base + Ls * j], v = buf[base + Ls * (R - j)];
+                sj[j] = c2{u.x + v.x, u.y + v.y};
+                dj[j] = c2{u.x - v.x, u.y - v.y};
+                y0.x += sj[j].x;
+                y0.y += sj[j].y;
             }
-            if (k2 > 0) y = cmul<C>(y, tw<C>(t, ti, sgn));
-            buf[base + Ls * k2] = y;
-            ti += step;
-            if (ti >= twoM) ti -= twoM;
+            buf[base] = y0;
+            // w^R for the conjugate-side twiddles
+            double2 wR = w1;
+#pragma unroll
+            for (int q = 1; q < R; ++q) wR = cmul<double>(wR, w1);
+            double2 wk = w1;
+#pragma unroll
+            for (int k = 1; k <= H; ++k) {
+                c2 a = x0, bb = c2{(C)0, (C)0};
+#pragma unroll
+                for (int j = 1; j <= H; ++j) {
+                    const int q = (j * k) % R;
+                    const C cq = (C)(q <= H ? c[q] : c[R - q]);
+                    const C sq = (C)(q <= H ? sn[q] : -sn[R - q]);
+                    a.x += cq * sj[j].x;
+                    a.y += cq * sj[j].y;
+                    bb.x += sq * dj[j].x;
+                    bb.y += sq * dj[j].y;
+                }
+                bb.x *= sgn;
+                bb.y *= sgn;
+                const double2 wm = cmul<double>(wR, double2{wk.x, -wk.y});  // w^{R-k}
+                buf[base + Ls * k] = cmul<C>(c2{a.x - bb.y, a.y + bb.x}, c2{(C)wk.x, (C)wk.y});
+                buf[base + Ls * (R - k)] = cmul<C>(c2{a.x + bb.y, a.y - bb.x}, c2{(C)wm.x, (C)wm.y});
+                wk = cmul<double>(wk, w1);
+            }
         }
     }
 }
@@ -102,8 +199,8 @@ __device__ __forceinline__ void pass_reg(typename V2<C>::t *buf, int total, int 
 // any radix: every output is an R-term sum held in registers until all
 // threads have read the pass's inputs.  At most MAXO outputs per thread.
 template <typename C, int MAXO>
-__device__ __forceinline__ void pass_sum(typename V2<C>::t *buf, int total, int R, int L, const typename V2<C>::t *t,
-                                         int Mt, C sgn) {
+__device__ __forceinline__ void pass_sum(typename V2<C>::t *buf, int total, int R, int L, const double2 *t, int Mt,
+                                         C sgn) {
     typedef typename V2<C>::t c2;
     const int Ls = L / R;
     const int twoM = 2 * Mt;
@@ -140,8 +237,8 @@ __device__ __forceinline__ void pass_sum(typename V2<C>::t *buf, int total, int 
 // all passes of `ps` over `total` elements (segments of length ps.L[0]);
 // ends with a barrier
 template <typename C, int MAXO>
-__device__ __forceinline__ void run_passes(typename V2<C>::t *buf, int total, const Passes &ps,
-                                           const typename V2<C>::t *t, int Mt, C sgn) {
+__device__ __forceinline__ void run_passes(typename V2<C>::t *buf, int total, const Passes &ps, const double2 *t,
+                                           int Mt, C sgn) {
     for (int p = 0; p < ps.n; ++p) {
         const int R = ps.R[p], L = ps.L[p];
         switch (R) {
@@ -165,47 +262,36 @@ __device__ __forceinline__ void run_passes(typename V2<C>::t *buf, int total, co
 // the passes in reverse order (run_passes_inv), it takes a digit-reversed
 // spectrum back to natural order: M times the inverse transform.
 template <typename C, int R>
-__device__ __forceinline__ void pass_reg_inv(typename V2<C>::t *buf, int total, int L, const typename V2<C>::t *t,
-                                             int Mt, C sgn) {
+__device__ __forceinline__ void pass_reg_inv(typename V2<C>::t *buf, int total, int L, const double2 *t, int Mt,
+                                             C sgn) {
     typedef typename V2<C>::t c2;
     const int Ls = L / R;
-    const int twoM = 2 * Mt;
-    c2 wr[R];  // w_R^{-q}
-#pragma unroll
-    for (int q = 0; q < R; ++q) wr[q] = tw<C>(t, (2 * q * (Mt / R)) % twoM, -sgn);
+    double c[(R - 1) / 2 + 1], sn[(R - 1) / 2 + 1];
+    if constexpr (R > 2) roots<R>(t, Mt, c, sn);
     const int unitL = 2 * (Mt / L);
     const int nb = total / R;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         const int blk = b / Ls, n1 = b - blk * Ls;
         const int base = blk * L + n1;
-        const int step = n1 * unitL;
+        const double2 w1 = twd(t, n1 * unitL, -(double)sgn);
         c2 y[R];
-        int ti = 0;
+        y[0] = buf[base];
+        double2 wk = w1;
 #pragma unroll
-        for (int k2 = 0; k2 < R; ++k2) {
-            y[k2] = buf[base + Ls * k2];
-            if (k2 > 0) y[k2] = cmul<C>(y[k2], tw<C>(t, ti, -sgn));
-            ti += step;
-            if (ti >= twoM) ti -= twoM;
+        for (int k2 = 1; k2 < R; ++k2) {
+            y[k2] = cmul<C>(buf[base + Ls * k2], c2{(C)wk.x, (C)wk.y});
+            if (k2 + 1 < R) wk = cmul<double>(wk, w1);
         }
+        dft_small<C, R>(y, c, sn, -sgn);
 #pragma unroll
-        for (int n2 = 0; n2 < R; ++n2) {
-            c2 x = y[0];
-#pragma unroll
-            for (int k2 = 1; k2 < R; ++k2) {
-                const c2 p = cmul<C>(y[k2], wr[(n2 * k2) % R]);
-                x.x += p.x;
-                x.y += p.y;
-            }
-            buf[base + Ls * n2] = x;
-        }
+        for (int n2 = 0; n2 < R; ++n2) buf[base + Ls * n2] = y[n2];
     }
 }
 
 // generic-radix form of pass_reg_inv (MAXO inputs per thread)
 template <typename C, int MAXO>
-__device__ __forceinline__ void pass_sum_inv(typename V2<C>::t *buf, int total, int R, int L,
-                                             const typename V2<C>::t *t, int Mt, C sgn) {
+__device__ __forceinline__ void pass_sum_inv(typename V2<C>::t *buf, int total, int R, int L, const double2 *t,
+                                             int Mt, C sgn) {
     typedef typename V2<C>::t c2;
     const int Ls = L / R;
     const int twoM = 2 * Mt;
@@ -242,8 +328,8 @@ __device__ __forceinline__ void pass_sum_inv(typename V2<C>::t *buf, int total, 
 // reverse passes: digit-reversed spectrum (of run_passes with sign sgn) ->
 // natural order, times the segment length; ends with a barrier
 template <typename C, int MAXO>
-__device__ __forceinline__ void run_passes_inv(typename V2<C>::t *buf, int total, const Passes &ps,
-                                               const typename V2<C>::t *t, int Mt, C sgn) {
+__device__ __forceinline__ void run_passes_inv(typename V2<C>::t *buf, int total, const Passes &ps, const double2 *t,
+                                               int Mt, C sgn) {
     for (int p = ps.n - 1; p >= 0; --p) {
         const int R = ps.R[p], L = ps.L[p];
         switch (R) {
@@ -307,12 +393,12 @@ __device__ __forceinline__ int signed_order(int c, int N, int M) { return c <= 2
 // outputs per thread of the generic pass (radices above 13); 0 when every
 // radix has a register butterfly.
 template <typename C, typename T, int MAXO, int IO = 0>
-__device__ __forceinline__ void dft_row(int N, int M, const Passes &ps, const C *__restrict__ gtab,
+__device__ __forceinline__ void dft_row(int N, int M, const Passes &ps, const double *__restrict__ gtab,
                                         const int *__restrict__ src_pos, int mode, C scale, const T *src,
                                         const T *src2, T *dst, T *dst2, typename V2<C>::t *buf) {
     typedef typename V2<C>::t c2;
-    c2 *t = buf + M;
-    load_tab<C>(gtab, M, t);
+    double2 *t = reinterpret_cast<double2 *>(buf + M + (M & 1));  // 16-byte aligned after the row
+    load_tab(gtab, M, t);
     const int twoM = 2 * M;
     const C sgn = mode == 0 ? (C)1 : (C)-1;
     const int bd = blockDim.x;

@@ -499,7 +499,8 @@ int sht_group_create_ex(int n, const int *Ns, const int *fields, int dtype, cons
             goff += es * (size_t)fields[i] * 2 * Ns[i] * (4 * Ns[i] - 1);
             g->max_M = std::max(g->max_M, 4 * Ns[i] - 1);
         }
-        if (es * ((size_t)g->max_M + dev::dft::tab_entries(g->max_M)) > 160 * 1024) return SHT_ERR_UNSUPPORTED;
+        if (es * ((size_t)g->max_M + 1) + 16 * (size_t)dev::dft::tab_entries(g->max_M) > kGroupDftLds)
+            return SHT_ERR_UNSUPPORTED;
         if ((e = hipMalloc(&g->d_g.p, std::max<size_t>(goff, 16))) != hipSuccess) return hip_err(e, "group workspace");
         g->h_tr.resize(n);
         for (int i = 0; i < n; ++i) {

@@ -12,6 +12,8 @@ namespace sht {
 namespace group {
 
 constexpr int kMaxPass = 24;
+// dynamic LDS of the grouped DFT kernel (160 KB less room for its static LDS)
+constexpr int kGroupDftLds = 159 * 1024;
 
 // one transform, as the kernels see it
 struct GTrans {

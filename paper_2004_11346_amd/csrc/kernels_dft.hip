@@ -69,8 +69,10 @@ struct RowPtrs {
     }
 };
 
+// two 512-thread workgroups per CU (an FP64 row up to about 4900 points fills
+// half of the LDS) need at most 128 registers per lane: four waves per SIMD
 template <typename C, typename T, int MAXO, int IO>
-__global__ __launch_bounds__(kThreads) void k_dft_rows(int N, int M, Passes ps, const C *__restrict__ tab,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MAXO == 0 ? 4 : 1, 8))) void k_dft_rows(int N, int M, Passes ps, const double *__restrict__ tab,
                                                        const int *__restrict__ src_pos, int mode, C scale,
                                                        const T *in, T *out, int nreal) {
     extern __shared__ unsigned char smem_raw[];
@@ -81,20 +83,20 @@ __global__ __launch_bounds__(kThreads) void k_dft_rows(int N, int M, Passes ps, 
 
 // prime M by Rader's convolution
 template <typename C, typename T, int IO>
-__global__ __launch_bounds__(kThreads) void k_dft_rader(int N, int M, Passes pc, const C *__restrict__ tab,
-                                                        const C *__restrict__ ctab, const int *__restrict__ inslot,
+__global__ __launch_bounds__(kThreads) void k_dft_rader(int N, int M, Passes pc, const double *__restrict__ tab,
+                                                        const double *__restrict__ ctab, const int *__restrict__ inslot,
                                                         const int *__restrict__ outslot, const C *__restrict__ bspec,
                                                         int mode, C scale, const T *in, T *out, int nreal) {
     typedef typename V2<C>::t c2;
     extern __shared__ unsigned char smem_raw[];
     c2 *buf = reinterpret_cast<c2 *>(smem_raw);
     const int L = M - 1;
-    c2 *t = buf + L;
-    c2 *tc = t + tab_entries(M);
-    c2 *red = tc + tab_entries(L);  // [kThreads / 64 + 1]
+    double2 *t = reinterpret_cast<double2 *>(buf + L + (L & 1));  // 16-byte aligned after the row
+    double2 *tc = t + tab_entries(M);
+    c2 *red = reinterpret_cast<c2 *>(tc + tab_entries(L));  // [kThreads / 64 + 1]
     const RowPtrs<T, IO> r(N, M, blockIdx.y, blockIdx.x, nreal, in, out);
-    load_tab<C>(tab, M, t);
-    load_tab<C>(ctab, L, tc);
+    load_tab(tab, M, t);
+    load_tab(ctab, L, tc);
     __syncthreads();
     const int twoM = 2 * M;
     const int bd = blockDim.x;
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(kThreads) void k_dft_rader(int N, int M, Passes pc,
 // w_M^{n2 k1}, written to y[k1 M2 + n2]
 template <typename C, typename T, int IO>
 __global__ __launch_bounds__(kThreads) void k_dft_4s_a(int N, int M, int M1, int M2, int chunk, Passes ps,
-                                                       const C *__restrict__ tab, const int *__restrict__ src_pos,
+                                                       const double *__restrict__ tab, const int *__restrict__ src_pos,
                                                        int mode, const T *in, T *out, int nreal) {
     typedef typename V2<C>::t c2;
     extern __shared__ unsigned char smem_raw[];
@@ -205,13 +207,13 @@ __global__ __launch_bounds__(kThreads) void k_dft_4s_a(int N, int M, int M1, int
     const int n2_0 = blockIdx.x * chunk;
     const int cnt = min(chunk, M2 - n2_0);
     const int total = cnt * M1;
-    c2 *t = buf + chunk * M1;
+    double2 *t = reinterpret_cast<double2 *>(buf + chunk * M1 + ((chunk * M1) & 1));
     // input rows in the I/O mode (IO 2: two real rows); output: complex
     // intermediate rows
     const RowPtrs<T, IO == 2 ? 2 : 0> r(N, M, blockIdx.z, blockIdx.y, nreal, in, out);
     const T *src = r.src;
     T *dst = out + 2 * (((int64_t)blockIdx.z * 2 * N + blockIdx.y) * M);
-    load_tab<C>(tab, M, t);
+    load_tab(tab, M, t);
     __syncthreads();
     const int twoM = 2 * M;
     const C sgn = mode == 0 ? (C)1 : (C)-1;
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(kThreads) void k_dft_4s_a(int N, int M, int M1, int
 // (post-twiddled and scaled for analysis)
 template <typename C, typename T, int IO>
 __global__ __launch_bounds__(kThreads) void k_dft_4s_b(int N, int M, int M1, int M2, int chunk, Passes ps,
-                                                       const C *__restrict__ tab, const int *__restrict__ src_pos,
+                                                       const double *__restrict__ tab, const int *__restrict__ src_pos,
                                                        int mode, C scale, const T *in, T *out, int nreal) {
     typedef typename V2<C>::t c2;
     extern __shared__ unsigned char smem_raw[];
@@ -274,12 +276,12 @@ __global__ __launch_bounds__(kThreads) void k_dft_4s_b(int N, int M, int M1, int
     const int k1_0 = blockIdx.x * chunk;
     const int cnt = min(chunk, M1 - k1_0);
     const int total = cnt * M2;
-    c2 *t = buf + chunk * M2;
+    double2 *t = reinterpret_cast<double2 *>(buf + chunk * M2 + ((chunk * M2) & 1));
     // input: complex intermediate rows; output rows in the I/O mode (IO 1:
     // two real rows)
     const T *src = in + 2 * (((int64_t)blockIdx.z * 2 * N + blockIdx.y) * M) + 2 * (int64_t)k1_0 * M2;
     const RowPtrs<T, IO == 1 ? 1 : 0> r(N, M, blockIdx.z, blockIdx.y, nreal, in, out);
-    load_tab<C>(tab, M, t);
+    load_tab(tab, M, t);
     const int twoM = 2 * M;
     const C sgn = mode == 0 ? (C)1 : (C)-1;
     const int bd = blockDim.x;
@@ -375,12 +377,14 @@ hipError_t launch(const DftPlan &p, int batch, int mode, double scale, const voi
     hipError_t e = set_attrs<C>();
     if (e != hipSuccess) return e;
     const bool f64 = sizeof(C) == 8;
-    const C *tab = f64 ? (const C *)p.tab : (const C *)p.tabf;
+    const double *tab = p.tab;
     const int M = p.M;
+    // LDS: the row (padded to 16 bytes), then FP64 phase tables
+    auto row_bytes = [](int64_t n) { return sizeof(c2) * (size_t)(n + (n & 1)); };
     prof::Scope sc(s, mode == 0 ? "k_dft_synthesis" : "k_dft_analysis");
     if (p.kind == kDftRows) {
         const Passes ps = to_passes(p.nrad, p.radix, p.blen);
-        const size_t lds = sizeof(c2) * ((size_t)M + tab_entries(M));
+        const size_t lds = row_bytes(M) + 16 * (size_t)tab_entries(M);
         const int maxr = max_radix(p.nrad, p.radix);
         const dim3 grid(2 * p.N, batch);
 #define SHT_ROWS(MX)                                                                                        \
@@ -399,9 +403,10 @@ hipError_t launch(const DftPlan &p, int batch, int mode, double scale, const voi
     }
     if (p.kind == kDftRader) {
         const Passes pc = to_passes(p.nrad, p.radix, p.blen);
-        const size_t lds = sizeof(c2) * ((size_t)(M - 1) + tab_entries(M) + tab_entries(M - 1) + kThreads / 64 + 1);
+        const size_t lds = row_bytes(M - 1) + 16 * ((size_t)tab_entries(M) + tab_entries(M - 1)) +
+                           sizeof(c2) * (kThreads / 64 + 1);
         hipLaunchKernelGGL((k_dft_rader<C, T, IO>), dim3(2 * p.N, batch), dim3(kThreads), lds, s, p.N, M, pc, tab,
-                           f64 ? (const C *)p.ctab : (const C *)p.ctabf, p.inslot, p.outslot,
+                           p.ctab, p.inslot, p.outslot,
                            f64 ? (const C *)p.bspec : (const C *)p.bspecf, mode, (C)scale, (const T *)in, (T *)out,
                            nreal);
         return hipGetLastError();
@@ -410,8 +415,8 @@ hipError_t launch(const DftPlan &p, int batch, int mode, double scale, const voi
         if (!p.scratch) return hipErrorInvalidValue;
         const Passes pa = to_passes(p.nrad, p.radix, p.blen);
         const Passes pb = to_passes(p.nrad2, p.radix2, p.blen2);
-        const size_t la = sizeof(c2) * ((size_t)p.chunk1 * p.M1 + tab_entries(M));
-        const size_t lb = sizeof(c2) * ((size_t)p.chunk2 * p.M2 + tab_entries(M));
+        const size_t la = row_bytes((int64_t)p.chunk1 * p.M1) + 16 * (size_t)tab_entries(M);
+        const size_t lb = row_bytes((int64_t)p.chunk2 * p.M2) + 16 * (size_t)tab_entries(M);
         T *scr = (T *)p.scratch;
         hipLaunchKernelGGL((k_dft_4s_a<C, T, IO>), dim3((p.M2 + p.chunk1 - 1) / p.chunk1, 2 * p.N, batch),
                            dim3(kThreads), la, s, p.N, M, p.M1, p.M2, p.chunk1, pa, tab, p.src_pos, mode,
@@ -512,13 +517,13 @@ int primitive_root(int M) {
 bool fits_rows(int M, size_t elt) {
     const std::vector<int> f = prime_factors(M);
     const int maxp = f.empty() ? 1 : *std::max_element(f.begin(), f.end());
-    return elt * ((size_t)M + tab_entries(M)) <= kLds && (maxp <= 13 || M <= 32 * kThreads);
+    return elt * ((size_t)M + 1) + 16 * (size_t)tab_entries(M) <= kLds && (maxp <= 13 || M <= 32 * kThreads);
 }
 
 bool fits_rader(int M, size_t elt) {
     const std::vector<int> f = prime_factors(M - 1);
     const int maxp = f.empty() ? 1 : *std::max_element(f.begin(), f.end());
-    return elt * ((size_t)(M - 1) + tab_entries(M) + tab_entries(M - 1) + kThreads / 64 + 1) <= kLds &&
+    return elt * ((size_t)M + kThreads / 64 + 1) + 16 * ((size_t)tab_entries(M) + tab_entries(M - 1)) <= kLds &&
            (maxp <= 13 || M - 1 <= kRaderMaxo * kThreads);
 }
 
@@ -531,7 +536,7 @@ bool four_step_split(int M, size_t elt, int &M1, int &M2, int &c1, int &c2) {
         // each workgroup holds chunk x length <= 8192 elements (the generic
         // pass holds 16 outputs per thread) plus the table
         if (b > 16 * kThreads) continue;
-        if (elt * ((size_t)b + tab_entries(M)) > kLds) continue;
+        if (elt * ((size_t)b + 1) + 16 * (size_t)tab_entries(M) > kLds) continue;
         if (best < 0 || b < M / best) best = a;
     }
     if (best < 0) return false;
@@ -542,8 +547,8 @@ bool four_step_split(int M, size_t elt, int &M1, int &M2, int &c1, int &c2) {
     const int target = elt == 16 ? 4096 : 8192;
     c1 = std::max(1, std::min(M2, target / M1));
     c2 = std::max(1, std::min(M1, target / M2));
-    while (c1 > 1 && elt * ((size_t)c1 * M1 + tab_entries(M)) > kLds) --c1;
-    while (c2 > 1 && elt * ((size_t)c2 * M2 + tab_entries(M)) > kLds) --c2;
+    while (c1 > 1 && elt * ((size_t)c1 * M1 + 1) + 16 * (size_t)tab_entries(M) > kLds) --c1;
+    while (c2 > 1 && elt * ((size_t)c2 * M2 + 1) + 16 * (size_t)tab_entries(M) > kLds) --c2;
     return true;
 }
 

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(512) void k_group_dft(const GTrans *__restrict__ tr
         }
         __syncthreads();
         const int64_t base = 2 * ((int64_t)w.a * 2 * d.N * d.M + (int64_t)w.b * d.M);
-        const C *tw = sizeof(C) == 8 ? (const C *)d.tab : (const C *)d.tabf;
+        const double *tw = d.tab;
         if (mode == 0) {
             T *row = (T *)d.f + base;
             dev::dft::dft_row<C, T, 8>(d.N, d.M, ps, tw, d.src_pos, 0, (C)1, row, nullptr, row, nullptr, buf);
@@ -158,7 +158,7 @@ int fwd_rows_per_tile() { return 64 * kNpl; }
 
 hipError_t init_attributes() {
     for (const void *fn : {(const void *)&k_group_dft<double, double>, (const void *)&k_group_dft<float, float>}) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kGroupDftLds);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -192,7 +192,7 @@ hipError_t launch_phase(int phase, int dtype, int grid, const GTrans *tr, const 
         default: {
             const int mode = phase == kDftSyn ? 0 : 1;
             prof::Scope ps(s, mode == 0 ? "k_group_dft_synthesis" : "k_group_dft_analysis");
-            const size_t lds = (dtype == 0 ? 16 : 8) * ((size_t)max_M + dev::dft::tab_entries(max_M));
+            const size_t lds = (dtype == 0 ? 16 : 8) * ((size_t)max_M + 1) + 16 * (size_t)dev::dft::tab_entries(max_M);
             if (dtype == 0)
                 hipLaunchKernelGGL((k_group_dft<double, double>), dim3(grid), dim3(512), lds, s, tr, items, nitems,
                                    counter, mode);
