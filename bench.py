@@ -121,21 +121,38 @@ def cpu_baseline(N: int):
 # SHA-256 of the kernel sources it was measured with; a changed source makes
 # the figure stale and it is reported as null.
 TRAFFIC = {
-    # HBM bytes per forward ALT call of each kernel family: rocprofv3 FETCH_SIZE
-    # and WRITE_SIZE runs (two calls each), scaled by what the counters read
-    # for a 1 GiB copy in the same run; valid for the kernel sources of "sha"
+    # HBM bytes per call of each kernel family (all its dispatches): rocprofv3
+    # FETCH_SIZE and WRITE_SIZE runs over two calls each, scaled by what the
+    # counters read for a 1 GiB copy in the same run (fetch x 2.0, write x 1.0);
+    # valid for the kernel sources of "sha"
     ("dense", 1024, 32, "f64", "k_dense_fwd_mfma"): {"bytes_per_call": 24.06e9, "sha": "21a5dbab89ebbe02",
                                                      "profile": "profiles/alt_fwd_dense_n1024_b32_f64.md"},
     ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7513e9, "sha": "21a5dbab89ebbe02",
                                                     "profile": "profiles/alt_fwd_dense_n1024_b1_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_gen_fwd_mfma"): {"bytes_per_call": 15.37e9, "sha": "d9dc951b5db97d43",
-                                                   "profile": "profiles/alt_fwd_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_ops_mfma"): {"bytes_per_call": 4.346e9, "sha": "d9dc951b5db97d43",
-                                               "profile": "profiles/alt_fwd_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 1, "f64", "k_ops"): {"bytes_per_call": 0.1472e9, "sha": "d9dc951b5db97d43",
-                                         "profile": "profiles/alt_fwd_idbf_n1024_b1_f64.md"},
-    ("idbf", 1024, 1, "f64", "k_gen_fwd"): {"bytes_per_call": 0.811e9, "sha": "d9dc951b5db97d43",
-                                             "profile": "profiles/alt_fwd_idbf_n1024_b1_f64.md"},
+    ("idbf", 1024, 32, "f64", "k_gen_adj"): {"bytes_per_call": 22.977e9, "sha": "5dfee2315eda4eae",
+                                              "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
+    ("idbf", 1024, 32, "f64", "k_gen_fwd_mfma"): {"bytes_per_call": 12.627e9, "sha": "5dfee2315eda4eae",
+                                                   "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
+    ("idbf", 1024, 32, "f64", "k_pack"): {"bytes_per_call": 4.403e9, "sha": "94cc9b348a22cb57",
+                                           "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
+    ("idbf", 1024, 32, "f64", "k_combine"): {"bytes_per_call": 8.659e9, "sha": "94cc9b348a22cb57",
+                                              "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
+    ("idbf", 1024, 32, "f64", "k_fold"): {"bytes_per_call": 9.046e9, "sha": "94cc9b348a22cb57",
+                                           "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
+    ("idbf", 1024, 32, "f64", "k_scatter"): {"bytes_per_call": 4.307e9, "sha": "94cc9b348a22cb57",
+                                              "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
+}
+
+# the sources each kernel family is built from
+FAMILY_SOURCES = {
+    "k_dense": ["kernels_dense.hip", "dense_device.h"],
+    "k_gen": ["idbf_kernels.hip", "idbf_pack.cpp"],
+    "k_ops": ["idbf_kernels.hip", "idbf_pack.cpp"],
+    "k_dft": ["kernels_dft.hip", "dft_device.h"],
+    "k_pack": ["kernels_panels.hip"],
+    "k_scatter": ["kernels_panels.hip"],
+    "k_combine": ["kernels_panels.hip"],
+    "k_fold": ["kernels_panels.hip"],
 }
 
 
@@ -247,7 +264,9 @@ def step_roofline(method, N, batch, dtype, prog, kern_fwd, kern_inv, reps):
         r = {"ms_per_step": f["ms_per_step"], "launches_per_step": f["launches_per_step"]}
         if w:
             bound, work, (unit, peak), disp, what = w
-            per_call_s = f["ms_per_step"] / f["launches_per_step"] / 1e3
+            # every family runs once per step (ops stages split by direction),
+            # whatever number of launches that call makes
+            per_call_s = f["ms_per_step"] / 1e3
             ach = work / per_call_s / (1e12 if unit == "TFLOP/s" else 1e9)
             r.update({"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
                       "work_per_call": work, "work": what})
@@ -259,12 +278,15 @@ def step_roofline(method, N, batch, dtype, prog, kern_fwd, kern_inv, reps):
             sb = 8 if dtype == "f64" else 4
             r["schedule_bytes"] = ((float(prog.get(d + "_gather_rows", 0)) + float(prog.get(d + "_out_rows", 0)))
                                    * 4 * batch * sb)
+        t = traffic_of(method, N, batch, dtype, key)
+        if t["traffic"] is not None:
+            r["traffic"] = t["traffic"]
         rows[key] = r
     dom = max((k for k in rows if "frac" in rows[k]), key=lambda k: rows[k]["ms_per_step"])
     d = rows[dom]
     roof = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
             "frac": d["frac"], "kernel": dom, "work": d["work"], "work_per_call": d["work_per_call"],
-            "kernel_ms_per_call": d["ms_per_step"] / d["launches_per_step"],
+            "kernel_ms_per_call": d["ms_per_step"],
             "kernel_share_of_step_kernels": d["ms_per_step"] / sum(r["ms_per_step"] for r in rows.values())}
     if "dispatches_per_call" in d:
         roof["dispatches_per_call"] = d["dispatches_per_call"]
@@ -277,10 +299,9 @@ def traffic_of(method, N, batch, dtype, fam):
     """Measured HBM bytes per call of a kernel family (rocprofv3 FETCH_SIZE +
     WRITE_SIZE, scaled), with the profile it comes from; null when the kernel
     sources changed since the counters were taken."""
-    files = {"dense": ["kernels_dense.hip", "dense_device.h"],
-             "idbf": ["idbf_kernels.hip", "idbf_pack.cpp"]}[method]
-    if fam.startswith("k_dft"):
-        files = ["kernels_dft.hip", "dft_device.h"]
+    files = next((v for k, v in FAMILY_SOURCES.items() if fam.startswith(k)), None)
+    if files is None:
+        return {"traffic": None, "traffic_profile": None, "kernel_src_sha": None}
     sha = kernel_source_sha(files)
     t = TRAFFIC.get((method, N, batch, dtype, fam))
     ok = bool(t) and t["sha"] == sha

@@ -483,6 +483,9 @@ __global__ __launch_bounds__(256) void k_ops_bf16(const Op *__restrict__ ops, co
 // state with the two-step recurrence; coefficients and input rows staged in
 // LDS by 64-column chunks.  The tile's sums are added to Y once at the end
 // (items of one tile are one workgroup, so no two workgroups add to a row).
+// task carries kGenOverwrite when the item is the first writer of its output
+// tile (no stored factor contributes to it, so the op program leaves it alone)
+constexpr int32_t kGenOverwrite = 1 << 30;
 struct GenItem {
     int32_t task, row0, seg_begin, seg_end;
 };
@@ -502,12 +505,14 @@ __global__ __launch_bounds__(64) void k_gen_fwd(const GenItem *__restrict__ item
     const int ii = xcd_item(n_items, kXc);
     if (ii >= n_items) return;
     const GenItem it = items[item0 + ii];
+    const int task = it.task & ~kGenOverwrite;
+    const bool ow = (it.task & kGenOverwrite) != 0;  // first writer of its output tile
     const int lane = threadIdx.x;
     const int r = it.row0 + lane;
-    const int a = it.task >> 1, par = it.task & 1;
+    const int a = task >> 1, par = task & 1;
     const double x = xh[r < N ? r : N - 1], x2 = x * x;
     const double *cfo = coef2 + 3 * (d_tri_offset2(N, a) + par);
-    const T *Xt = X + x_off[it.task] * R;
+    const T *Xt = X + x_off[task] * R;
     T acc[RC];
 #pragma unroll
     for (int q = 0; q < RC; ++q) acc[q] = (T)0;
@@ -536,10 +541,10 @@ __global__ __launch_bounds__(64) void k_gen_fwd(const GenItem *__restrict__ item
         }
     }
     if (r < N) {
-        T *y = Y + ((int64_t)it.task * N + r) * R;
+        T *y = Y + ((int64_t)task * N + r) * R;
 #pragma unroll
         for (int q = 0; q < RC; ++q)
-            if (q < rc) y[q] += acc[q];
+            if (q < rc) y[q] = ow ? acc[q] : y[q] + acc[q];
     }
 }
 
@@ -566,12 +571,14 @@ void k_gen_fwd_mfma(const GenItem *__restrict__ items, int n_items, int xc, int 
     const int ii = xcd_item(n_items, xc);
     if (ii >= n_items) return;
     const GenItem it = items[item0 + ii];
+    const int task = it.task & ~kGenOverwrite;
+    const bool ow = (it.task & kGenOverwrite) != 0;  // first writer of its output tile
     const int lane = threadIdx.x, jl = lane >> 4, cl = lane & 15;
     const int r = it.row0 + lane;
-    const int a = it.task >> 1, par = it.task & 1;
+    const int a = task >> 1, par = task & 1;
     const double x = xh[r < N ? r : N - 1], x2 = x * x;
     const double *cfo = coef2 + 3 * (d_tri_offset2(N, a) + par);
-    const T *Xt = X + x_off[it.task] * R;
+    const T *Xt = X + x_off[task] * R;
     d4v D[4][CBP];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -657,8 +664,8 @@ void k_gen_fwd_mfma(const GenItem *__restrict__ items, int n_items, int xc, int 
             for (int i = 0; i < 4; ++i) {
                 const int row = it.row0 + 16 * t + jl + 4 * i;
                 if (row < N) {
-                    T *y = Y + ((int64_t)it.task * N + row) * R + col;
-                    *y = (T)((double)*y + D[t][cb][i]);
+                    T *y = Y + ((int64_t)task * N + row) * R + col;
+                    *y = ow ? (T)D[t][cb][i] : (T)((double)*y + D[t][cb][i]);
                 }
             }
         }
@@ -694,11 +701,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(CBP == 1 ? 1
     const int ii = xcd_item(n_items, xc);
     if (ii >= n_items) return;
     const GenItemA it = items[item0 + ii];
+    const int task = it.task & ~kGenOverwrite;
+    const bool ow = (it.task & kGenOverwrite) != 0;  // first writer of its output tile
     const int lane = threadIdx.x, jl = lane >> 4, cl = lane & 15;
-    const int a = it.task >> 1, par = it.task & 1;
+    const int a = task >> 1, par = task & 1;
     const double *cfo = coef2 + 3 * (d_tri_offset2(N, a) + par);
-    const int cols_task = (int)(x_off[it.task + 1] - x_off[it.task]);
-    const T *Ht = H + (int64_t)it.task * N * R;
+    const int cols_task = (int)(x_off[task + 1] - x_off[task]);
+    const T *Ht = H + (int64_t)task * N * R;
     d4v D[4][CBP];
 #pragma unroll
     for (int g = 0; g < 4; ++g)
@@ -793,14 +802,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(CBP == 1 ? 1
             for (int i = 0; i < 4; ++i) {
                 const int oc = it.col0 + 16 * g + jl + 4 * i;
                 if (oc < cols_task) {
-                    T *xo = X + (x_off[it.task] + oc) * R + col;
-                    *xo = (T)((double)*xo + D[g][cb][i]);
+                    T *xo = X + (x_off[task] + oc) * R + col;
+                    *xo = ow ? (T)D[g][cb][i] : (T)((double)*xo + D[g][cb][i]);
                 }
             }
         }
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
 
 template <typename T>
 hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir, const void *inp, void *outp,

@@ -402,8 +402,12 @@ struct Emitter {
     }
 };
 
+// gen_tiles[t][i]: the regenerated blocks have an item for output tile i of
+// task t.  A final op with no contribution is left out for such a tile (the
+// item writes it); written[t][i] records which tiles got a final op.
 void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t> &out_off,
-              const std::vector<int64_t> &in_off, bool fwd, int64_t value_hint, Program &p) {
+              const std::vector<int64_t> &in_off, bool fwd, int64_t value_hint, Program &p,
+              const std::vector<std::vector<char>> &gen_tiles, std::vector<std::vector<char>> &written) {
     const int64_t in_rows = in_off[ntask];
     int D = 0;  // number of work stages
     for (auto &b : bps) D = std::max(D, (int)b.levels.size());
@@ -520,8 +524,10 @@ void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t>
     for (size_t bi = 0; bi < bps.size(); ++bi) by_task[bps[bi].task].push_back(bi);
     Stage fst{};
     fst.op_begin = (int32_t)p.ops.size();
+    written.assign(ntask, {});
     for (int t = 0; t < ntask; ++t) {
         const int64_t r0 = out_off[t], r1 = out_off[t + 1];
+        written[t].assign((size_t)((r1 - r0 + kTile - 1) / kTile), 0);
         for (int64_t T0 = r0; T0 < r1; T0 += kTile) {
             const int64_t T1 = std::min(r1, T0 + kTile);
             Op op{};
@@ -546,6 +552,9 @@ void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t>
                 }
             }
             op.nsub = (int32_t)subs.size();
+            const size_t ti = (size_t)((T0 - r0) / kTile);
+            if (subs.empty() && ti < gen_tiles[t].size() && gen_tiles[t][ti]) continue;
+            written[t][ti] = 1;
             p.subs.insert(p.subs.end(), subs.begin(), subs.end());
             p.ops.push_back(op);
             p.op_task.push_back(t);
@@ -670,6 +679,18 @@ void pack_programs(const HostPlanData &hp, PackedPlan &pk) {
     int64_t nblocks = 0;
     for (const Task &t : hp.tasks) nblocks += (int64_t)t.blocks.size();
     const int64_t hint = hp.stats.stored + 64 * nblocks + 1024;
+    // regenerated-block items first: the op programs leave the output tiles
+    // that only these items contribute to
+    std::thread tg([&] { build_gen_adjoint(hp, pk.gen_adj); });
+    build_gen_forward(hp, pk.gen_fwd);
+    tg.join();
+    std::vector<std::vector<char>> cov_fwd(ntask), cov_adj(ntask), wr_fwd, wr_adj;
+    for (int t = 0; t < ntask; ++t) {
+        cov_fwd[t].assign((size_t)((N + kTile - 1) / kTile), 0);
+        cov_adj[t].assign((size_t)((std::max(0, hp.tasks[t].cols) + kTile - 1) / kTile), 0);
+    }
+    for (const GenForward::Item &it : pk.gen_fwd.items) cov_fwd[it.task][it.row0 / kTile] = 1;
+    for (const GenAdjoint::Item &it : pk.gen_adj.items) cov_adj[it.task][it.col0 / kTile] = 1;
     auto pack_dir = [&](bool fwd) {
         auto t0 = T();
         std::vector<BlockProg> bps;
@@ -684,20 +705,19 @@ void pack_programs(const HostPlanData &hp, PackedPlan &pk) {
             }
         auto t1 = T();
         if (fwd)
-            schedule(bps, ntask, of.y, of.x, true, hint, pk.fwd);
+            schedule(bps, ntask, of.y, of.x, true, hint, pk.fwd, cov_fwd, wr_fwd);
         else
-            schedule(bps, ntask, of.x, of.y, false, hint, pk.adj);
+            schedule(bps, ntask, of.x, of.y, false, hint, pk.adj, cov_adj, wr_adj);
         if (verbose)
             std::fprintf(stderr, "[sht] %s chains %.2fs schedule %.2fs\n", fwd ? "fwd" : "adj", D(t0, t1), D(t1, T()));
     };
     std::thread th([&] { pack_dir(false); });
     pack_dir(true);
     th.join();
-    std::thread tg([&] {
-        build_gen_adjoint(hp, pk.gen_adj);
-    });
-    build_gen_forward(hp, pk.gen_fwd);
-    tg.join();
+    for (GenForward::Item &it : pk.gen_fwd.items)
+        if (!wr_fwd[it.task][it.row0 / kTile]) it.task |= GenForward::kOverwrite;
+    for (GenAdjoint::Item &it : pk.gen_adj.items)
+        if (!wr_adj[it.task][it.col0 / kTile]) it.task |= GenAdjoint::kOverwrite;
 }
 
 void host_run_gen_forward(const GenForward &gf, int N, int t_lo, int t_hi, int R, const std::vector<int64_t> &x_off,
@@ -705,12 +725,14 @@ void host_run_gen_forward(const GenForward &gf, int N, int t_lo, int t_hi, int R
                           const double *coef2) {
     for (int i = gf.task_first[t_lo]; i < gf.task_first[t_hi + 1]; ++i) {
         const GenForward::Item &it = gf.items[i];
-        const int a = it.task / 2, par = it.task % 2;
+        const int task = it.task & ~GenForward::kOverwrite;
+        const int a = task / 2, par = task % 2;
         const double *cf = coef2 + 3 * (tri_offset(N, a) + par);
         for (int q = 0; q < 64 && it.row0 + q < N; ++q) {
             const int r = it.row0 + q;
             const double x = xh[r], x2 = x * x;
-            double *y = out + (size_t)(y_off[it.task] + r) * R;
+            double *y = out + (size_t)(y_off[task] + r) * R;
+            if (it.task & GenForward::kOverwrite) std::fill(y, y + R, 0.0);
             for (int s = it.seg_begin; s < it.seg_end; ++s) {
                 const GenForward::Seg &sg = gf.segs[s];
                 double p0 = gf.ck[2 * ((int64_t)sg.ck + q)], p1 = gf.ck[2 * ((int64_t)sg.ck + q) + 1];
@@ -729,7 +751,7 @@ void host_run_gen_forward(const GenForward &gf, int N, int t_lo, int t_hi, int R
                         }
                     }
                     const double v = e < -1074 ? 0.0 : p1 * std::ldexp(1.0, e);
-                    const double *xr = in + (size_t)(x_off[it.task] + c) * R;
+                    const double *xr = in + (size_t)(x_off[task] + c) * R;
                     for (int k = 0; k < R; ++k) y[k] += v * xr[k];
                 }
             }
@@ -742,8 +764,14 @@ void host_run_gen_adjoint(const GenAdjoint &ga, int N, int t_lo, int t_hi, int R
                           const double *coef2) {
     for (int i = ga.task_first[t_lo]; i < ga.task_first[t_hi + 1]; ++i) {
         const GenAdjoint::Item &it = ga.items[i];
-        const int a = it.task / 2, par = it.task % 2;
+        const int task = it.task & ~GenAdjoint::kOverwrite;
+        const int a = task / 2, par = task % 2;
         const double *cf = coef2 + 3 * (tri_offset(N, a) + par);
+        if (it.task & GenAdjoint::kOverwrite) {
+            const int64_t cols = x_off[task + 1] - x_off[task];
+            for (int64_t c = it.col0; c < std::min<int64_t>(cols, it.col0 + 64); ++c)
+                std::fill(out + (size_t)(x_off[task] + c) * R, out + (size_t)(x_off[task] + c + 1) * R, 0.0);
+        }
         for (int s = it.seg_begin; s < it.seg_end; ++s) {
             const GenAdjoint::Seg &sg = ga.segs[s];
             for (int q = 0; q < 64 && sg.row0 + q < N; ++q) {
@@ -751,7 +779,7 @@ void host_run_gen_adjoint(const GenAdjoint &ga, int N, int t_lo, int t_hi, int R
                 const double x = xh[r], x2 = x * x;
                 double p0 = ga.ck[2 * ((int64_t)sg.ck + q)], p1 = ga.ck[2 * ((int64_t)sg.ck + q) + 1];
                 int e = ga.ckexp[sg.ck + q];
-                const double *h = in + (size_t)(y_off[it.task] + r) * R;
+                const double *h = in + (size_t)(y_off[task] + r) * R;
                 for (int t = 0; t < sg.ncol; ++t) {
                     const int c = sg.c0 + t;
                     if (t > 0) {
@@ -766,7 +794,7 @@ void host_run_gen_adjoint(const GenAdjoint &ga, int N, int t_lo, int t_hi, int R
                         }
                     }
                     const double v = e < -1074 ? 0.0 : p1 * std::ldexp(1.0, e);
-                    double *xo = out + (size_t)(x_off[it.task] + c) * R;
+                    double *xo = out + (size_t)(x_off[task] + c) * R;
                     for (int k = 0; k < R; ++k) xo[k] += v * h[k];
                 }
             }

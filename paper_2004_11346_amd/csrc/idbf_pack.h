@@ -15,7 +15,11 @@ namespace idbf {
 // the blocks crossing that tile as segments.  A segment holds, for each of the
 // tile's 64 rows, the same-parity recurrence pair (degrees k - 2, k) at the
 // block's first column (zeros for rows outside the block).
+// Items whose output tile gets no contribution from the op program carry
+// kOverwrite in `task`: their kernel writes the tile instead of adding to it,
+// and the op program has no final op for that tile.
 struct GenForward {
+    static constexpr int32_t kOverwrite = 1 << 30;
     struct Item {
         int32_t task, row0, seg_begin, seg_end;
     };
@@ -35,6 +39,7 @@ struct GenForward {
 // and columns [c0, c0 + ncol) inside the tile, with the recurrence pair of
 // each of the 64 rows at column c0 (zeros for rows outside the block).
 struct GenAdjoint {
+    static constexpr int32_t kOverwrite = 1 << 30;  // as GenForward::kOverwrite
     struct Item {
         int32_t task, col0, seg_begin, seg_end;
     };

@@ -18,7 +18,7 @@ namespace {
 constexpr char kMagic[8] = {'S', 'H', 'T', 'P', 'L', 'A', 'N', 0};
 constexpr uint32_t kFormat = 1;
 // bump when the builder or the packer changes what a plan contains
-constexpr int kPlanVersion = 1;
+constexpr int kPlanVersion = 2;
 
 uint64_t fnv1a(const unsigned char *p, size_t n) {
     uint64_t h = 1469598103934665603ULL;

@@ -64,3 +64,29 @@ def test_n1024_32_fields_sampled_orders(method, tol, kw):
                 worst = max(worst, rel_l2(bo[i][m_of == m], bref[q, sgn, : 2 * N - a]))
         print(f"field {b}: transposed worst order rel l2 {worst:.2e}", flush=True)
         assert worst <= tol
+
+
+@pytest.mark.parametrize("f32_mode,name", [(0, "fp32 storage, FP64 matrix cores"), (2, "split-BF16 six products")])
+def test_n1024_32_fields_fp32_fast_forms(f32_mode, name):
+    """The FP32 fast forms at the benchmark's configuration against the FP64
+    oracle (on the FP32-rounded coefficients) at sampled orders, held to the
+    FP32 bar 2e-6: FP32 storage with FP64 products, and the split-BF16 form
+    with six products (stored factors on the BF16 matrix cores, regenerated
+    blocks on the FP64 matrix cores)."""
+    from paper_2004_11346_amd.sht import Plan
+    N, batch = 1024, 32
+    M = 4 * N - 1
+    print(f"FP32 {name} N=1024 batch 32 (plan build)", flush=True)
+    p = Plan(N, batch, dtype=torch.complex64, method="idbf", f32_mode=f32_mode)
+    beta = inputs.make_beta(N, batch, 2, dist="decay").astype(np.complex64)
+    absm = sorted({0, 1, N // 2, N, 3 * N // 2, 2 * N - 1} | {int(a) for a in inputs.sample_indices(2 * N, 6, 22)})
+    g = torch.zeros((batch, 2 * N, M), dtype=torch.complex64, device="cuda")
+    p.alt(0, 2 * N - 1, "fwd", torch.from_numpy(beta).cuda(), g)
+    for b in (0, 31):
+        ref = oracle.alt_forward_orders(N, beta[b].astype(np.complex128), absm)
+        gb = g[b].cpu().numpy().astype(np.complex128)
+        got = np.stack([np.stack([gb[:, a % M], gb[:, (-a) % M]]) for a in absm])
+        e = rel_l2(got, ref)
+        print(f"field {b}: forward rel l2 {e:.2e}", flush=True)
+        assert e <= 2e-6
+    p.close()
