@@ -45,10 +45,12 @@ def parse():
     ap.add_argument("--profile-dirs", default="fwd",
                     help="calls run by --profile-target (comma separated: fwd, inv = ALT only; sht_fwd, "
                          "sht_inv = full transforms)")
-    ap.add_argument("--workload", choices=["default", "n4096-orders", "uneven", "rank-study"], default="default",
+    ap.add_argument("--workload", choices=["default", "n4096-orders", "uneven", "rank-study", "levels"],
+                    default="default",
                     help="n4096-orders: N=4096, 8 fields, fast vs plain ALT on 64-order windows across the "
                          "order range; uneven: the grouped 64-transform workload; rank-study: ID sampling "
-                         "(mock-Chebyshev vs random rows), adaptive rank r_k and tolerance sweeps at m = N")
+                         "(mock-Chebyshev vs random rows), adaptive rank r_k and tolerance sweeps at m = N; "
+                         "levels: staged vs fused butterfly levels at leaf 32/64/128")
     return ap.parse_args()
 
 
@@ -115,16 +117,13 @@ def cpu_baseline(N: int):
     }
 
 
-# HBM bytes per ALT call read from rocprofv3 counters (FETCH_SIZE and
-# WRITE_SIZE in separate runs, see profiles/), scaled by the ratio that the
-# same counters give for a 1 GiB device copy.  Each entry is keyed on the
-# SHA-256 of the kernel sources it was measured with; a changed source makes
-# the figure stale and it is reported as null.
+# HBM bytes per call of each kernel family (all its dispatches): rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs (separate runs, two calls each, see
+# profiles/), scaled by what the counters read for a 1 GiB device copy in the
+# same run (fetch x 2.0, write x 1.0).  Each entry is keyed on the SHA-256 of
+# the kernel sources it was measured with; a changed source makes the figure
+# stale and it is reported as null.
 TRAFFIC = {
-    # HBM bytes per call of each kernel family (all its dispatches): rocprofv3
-    # FETCH_SIZE and WRITE_SIZE runs over two calls each, scaled by what the
-    # counters read for a 1 GiB copy in the same run (fetch x 2.0, write x 1.0);
-    # valid for the kernel sources of "sha"
     ("dense", 1024, 32, "f64", "k_dense_fwd_mfma"): {"bytes_per_call": 24.06e9, "sha": "21a5dbab89ebbe02",
                                                      "profile": "profiles/alt_fwd_dense_n1024_b32_f64.md"},
     ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7513e9, "sha": "21a5dbab89ebbe02",
@@ -170,8 +169,11 @@ GBS = ("GB/s", PEAK_HBM_GBS)
 
 
 def family(name):
-    """Kernel family of a recorder label ("k_ops_mfma[L2]" -> "k_ops_mfma")."""
-    return name.split("[", 1)[0]
+    """Kernel family of a recorder label ("k_ops_mfma[L2]" -> "k_ops_mfma");
+    the fused levels and the final stage of the op program on the matrix
+    cores form one family."""
+    f = name.split("[", 1)[0]
+    return "k_ops_mfma" if f == "k_ops_fused" else f
 
 
 def kernel_work(fam, method, N, batch, dtype, prog):
@@ -183,10 +185,11 @@ def kernel_work(fam, method, N, batch, dtype, prog):
       products with regenerated entries (plain form, regenerated blocks of the
         fast form): (2 R + 3) flops per entry -- the product with every
         right-hand side and about 3 flops to generate the entry;
-      op stages (stored factors): values s + index bytes + the vector rows one
+      op program (stored factors): on the matrix cores (R >= 16) 2 R flops
+        per stored value; else values s + index bytes + the vector rows one
         call must move once (distinct input-panel rows read, output rows
-        written) R s; the rows the level-by-level schedule moves beyond that
-        are reported as "schedule_bytes";
+        written) R s, with the rows the level-by-level schedule moves beyond
+        that reported as "schedule_bytes";
       panel moves and phi DFTs: one read and one write of the data they move.
     """
     R = 4 * batch
@@ -214,7 +217,12 @@ def kernel_work(fam, method, N, batch, dtype, prog):
         return "mfma", (2.0 * R + 3) * ng, TFLOPS, 1 if R <= 16 else gen_disp, "(2R+3) x regenerated entries flops"
     if fam.startswith("k_ops"):
         d = "adj" if fam.endswith("@inv") else "fwd"
-        vals = float(prog.get(d + "_values", 0)) * sb
+        nv = float(prog.get(d + "_values", 0))
+        if fam.startswith("k_ops_mfma") and R >= 16:
+            # many right-hand sides: 2 R flops per stored value (above the
+            # FP64 ridge from R = 40)
+            return "mfma", 2.0 * R * nv, TFLOPS, None, "2R x stored values flops"
+        vals = nv * sb
         idx = float(prog.get(d + "_index_bytes", 0))
         vec = (float(prog.get(d + "_vector_in_rows", 0)) + float(prog.get(d + "_vector_out_rows", 0))) * R * sb
         return "hbm", vals + idx + vec, GBS, None, "values s + index + distinct vector rows R s"
@@ -605,6 +613,66 @@ def rank_study(args):
                                  "cases": cases}, "results": out}), flush=True)
 
 
+def level_schedules(args):
+    """The butterfly levels of the fast form at N = 1024, 32 fields, FP64, with
+    butterflies from 128, 256 and 512 columns (leaf 32, 64, 128): staged
+    schedule (one launch per level) against the fused one (every block's
+    levels in one workgroup, rows in LDS), per kernel family of one forward and
+    one inverse SHT (HIP events on the launch stream), and the step time."""
+    import torch
+
+    import paper_2004_11346_amd.sht as S
+    from paper_2004_11346_amd import inputs
+    from paper_2004_11346_amd import lib as L
+    torch.cuda.init()
+    N, batch = args.N, args.batch
+    beta = torch.from_numpy(inputs.make_beta(N, batch, 2, dist="decay")).cuda()
+    out = {}
+    for leaf in (32, 64, 128):
+        for name, ls in (("staged", L.SHT_LEVELS_STAGED), ("fused", L.SHT_LEVELS_FUSED)):
+            plan = S.Plan(N, batch, method="idbf", leaf=leaf, level_schedule=ls)
+            f = plan.empty_grid()
+            bo = plan.empty_coefs()
+            for _ in range(2):
+                plan.forward(beta, out=f)
+                plan.inverse(f, out=bo)
+            torch.cuda.synchronize()
+            rec = {}
+            for d in ("fwd", "inv"):
+                plan.profile(True)
+                for _ in range(args.steps):
+                    if d == "fwd":
+                        plan.forward(beta, out=f)
+                    else:
+                        plan.inverse(f, out=bo)
+                torch.cuda.synchronize()
+                rep = plan.profile_report()
+                fam = {}
+                for k, v in rep.items():
+                    fk = k.split("[", 1)[0] + ("[final]" if k.endswith("[final]") else "")
+                    fam[fk] = fam.get(fk, 0.0) + v["total_ms"] / args.steps
+                rec[d] = {k: round(v, 4) for k, v in fam.items()}
+            plan.profile(False)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                plan.forward(beta, out=f)
+                plan.inverse(f, out=bo)
+            e1.record()
+            torch.cuda.synchronize()
+            rec["step_ms"] = e0.elapsed_time(e1) / args.steps
+            st = plan.stats()["program"]
+            rec["stored_values"] = st["fwd_values"]
+            rec["generated_entries"] = st["generated_entries"]
+            out[f"leaf{leaf}_{name}"] = rec
+            print(json.dumps({f"leaf{leaf}_{name}": rec}), flush=True)
+            plan.close()
+    print(json.dumps({"metric": "level schedules of the fast form", "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": f"SHT N={N}, {batch} fields, f64, idbf leaf 32/64/128",
+                                 "N": N, "batch": batch}, "results": out}))
+
+
 def fp32_legs(S, inputs, timer, N, batch, beta_np, no_check):
     """FP32 plans at the same workload: plain form, fast form on the VALU and
     fast form on the BF16 matrix cores (split-BF16, three and six products),
@@ -665,6 +733,9 @@ def main():
         return
     if args.workload == "rank-study":
         rank_study(args)
+        return
+    if args.workload == "levels":
+        level_schedules(args)
         return
 
     import numpy as np

@@ -97,6 +97,11 @@ extern "C" {
 #define SHT_DFT_RADER 2     /* prime M: Rader's length-(M-1) convolution in LDS */
 #define SHT_DFT_FOUR_STEP 3 /* M = M1 M2: two kernels through a grid-sized buffer */
 
+/* fast-form level schedules (sht_plan_opts.level_schedule) */
+#define SHT_LEVELS_AUTO 0
+#define SHT_LEVELS_STAGED 1
+#define SHT_LEVELS_FUSED 2
+
 /* ID row sampling (Section 2.1) */
 #define SHT_SAMPLE_MOCK_CHEB 0
 #define SHT_SAMPLE_RANDOM 1
@@ -157,6 +162,21 @@ typedef struct sht_plan_opts {
                           sht_plan_cache_verify) is rebuilt and rewritten; the
                           plan statistics report "plan_cache": "hit", "miss",
                           "corrupt_rebuilt" or "off". */
+    int level_schedule; /* fast form, non-final levels of the butterflies
+                          (Section 2.2: column IDs level by level, middle
+                          couplings, row IDs) and of the low-rank blocks
+                          (Section 2.3).  SHT_LEVELS_AUTO (default) and
+                          SHT_LEVELS_STAGED: one launch per level, the
+                          intermediate rows of every level through the
+                          scratch buffers (the faster schedule on MI355X).
+                          SHT_LEVELS_FUSED: one workgroup per block and 16
+                          right-hand sides runs all the block's levels, the
+                          intermediate rows in LDS (in HBM rows of its own
+                          for blocks whose levels exceed 512 rows); it needs
+                          the matrix-core executor (16 or more real
+                          right-hand sides, not split-BF16), else plan
+                          creation fails with UNSUPPORTED.  The products and
+                          their order are the same in every schedule. */
 } sht_plan_opts;
 
 void sht_plan_opts_default(sht_plan_opts *opts);

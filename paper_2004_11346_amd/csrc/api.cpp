@@ -182,6 +182,8 @@ void sht_plan_opts_default(sht_plan_opts *o) {
     o->m_hi = -1;
     o->dft_schedule = SHT_DFT_AUTO;
     o->id_check = 1;
+    o->cache_dir = nullptr;
+    o->level_schedule = SHT_LEVELS_AUTO;
 }
 
 const char *sht_strerror(int code) {
@@ -278,6 +280,10 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
         dev::DftHost dh;
         if (p->opts.dft_schedule < SHT_DFT_AUTO || p->opts.dft_schedule > SHT_DFT_FOUR_STEP) {
             set_error_detail("unknown phi DFT schedule");
+            return SHT_ERR_INVALID_ARG;
+        }
+        if (p->opts.level_schedule < SHT_LEVELS_AUTO || p->opts.level_schedule > SHT_LEVELS_FUSED) {
+            set_error_detail("unknown level schedule");
             return SHT_ERR_INVALID_ARG;
         }
         dev::dft_build(p->M, dtype, dh, p->opts.dft_schedule);

@@ -213,15 +213,15 @@ __device__ __forceinline__ void pass_sum(typename V2<C>::t *buf, int total, int 
         const int b = o / L, rem = o - b * L;
         const int k2 = rem / Ls, n1 = rem - k2 * Ls;
         const int base = b * L + n1;
-        const int step = (k2 * unitR) % twoM;
+        // phases w_R^{n2 k2}: powers of one table lookup, formed in FP64
+        const double2 ws = twd(t, (k2 * unitR) % twoM, (double)sgn);
+        double2 w = double2{1.0, 0.0};
         c2 y = c2{(C)0, (C)0};
-        int ti = 0;
         for (int n2 = 0; n2 < R; ++n2) {
-            const c2 p = cmul<C>(buf[base + Ls * n2], tw<C>(t, ti, sgn));
+            const c2 p = cmul<C>(buf[base + Ls * n2], c2{(C)w.x, (C)w.y});
             y.x += p.x;
             y.y += p.y;
-            ti += step;
-            if (ti >= twoM) ti -= twoM;
+            w = cmul<double>(w, ws);
         }
         const int tl = (int)(((long long)n1 * k2 * unitL) % twoM);
         out[j] = cmul<C>(y, tw<C>(t, tl, sgn));
@@ -304,16 +304,15 @@ __device__ __forceinline__ void pass_sum_inv(typename V2<C>::t *buf, int total, 
         const int b = o / L, rem = o - b * L;
         const int n2 = rem / Ls, n1 = rem - n2 * Ls;
         const int base = b * L + n1;
-        // x[n2] = sum_k2 w_R^{-n2 k2} w_L^{-n1 k2} y[k2]
-        const int step = (int)(((long long)n2 * unitR + (long long)n1 * unitL) % twoM);
+        // x[n2] = sum_k2 w_R^{-n2 k2} w_L^{-n1 k2} y[k2]: powers of one phase
+        const double2 ws = twd(t, (int)(((long long)n2 * unitR + (long long)n1 * unitL) % twoM), -(double)sgn);
+        double2 w = double2{1.0, 0.0};
         c2 x = c2{(C)0, (C)0};
-        int ti = 0;
         for (int k2 = 0; k2 < R; ++k2) {
-            const c2 p = cmul<C>(buf[base + Ls * k2], tw<C>(t, ti, -sgn));
+            const c2 p = cmul<C>(buf[base + Ls * k2], c2{(C)w.x, (C)w.y});
             x.x += p.x;
             x.y += p.y;
-            ti += step;
-            if (ti >= twoM) ti -= twoM;
+            w = cmul<double>(w, ws);
         }
         out[j] = x;
     }

@@ -102,7 +102,9 @@ int sht_host_plan_apply(const sht_host_plan_t *hp, int absm, int parity, int dir
     const int64_t ob = fwd ? pk.y_off[task] : pk.x_off[task];
     const int nin = fwd ? cols : rows, nout = fwd ? rows : cols;
     std::memcpy(&pin[(size_t)ib * R], in, sizeof(double) * (size_t)nin * R);
-    idbf::host_run_program(p, R, pin.data(), pout.data());
+    // the fused level form where the plan would run it (same arithmetic)
+    const bool fused = hp->data.opts.level_schedule == SHT_LEVELS_FUSED && p.fused_ok;
+    idbf::host_run_program(p, R, pin.data(), pout.data(), fused);
     if (fwd)
         idbf::host_run_gen_forward(pk.gen_fwd, N, task, task, R, pk.x_off, pk.y_off, pin.data(), pout.data(),
                                    hp->data.lt.xh.data(), hp->data.lt.coef2.data());
@@ -135,7 +137,8 @@ int sht_host_plan_stats(const sht_host_plan_t *hp, char *json, size_t cap) {
              ",\"adj_stages\":" + std::to_string(pk.adj.stages.size()) + ",\"scratch_rows\":" +
              std::to_string(std::max(pk.fwd.scr_rows, pk.adj.scr_rows)) + ",\"max_n_out\":" +
              std::to_string(pk.fwd.max_n_out) + ",\"max_n_in\":" + std::to_string(pk.fwd.max_n_in) +
-             ",\"fwd_values\":" + std::to_string(pk.fwd.vals.size()) + ",\"adj_values\":" + std::to_string(pk.adj.vals.size());
+             ",\"fwd_values\":" + std::to_string(pk.fwd.vals.size()) + ",\"adj_values\":" + std::to_string(pk.adj.vals.size()) +
+             idbf::fused_stats_json(pk);
         // stored values by sub-op output count (1-8, 9-16, 17-32, 33-64),
         // work stages vs final stage, per program
         for (int d = 0; d < 2; ++d) {
@@ -192,6 +195,20 @@ int sht_host_plan_stats(const sht_host_plan_t *hp, char *json, size_t cap) {
             cols = 0;
             for (auto &sg : pk.gen_fwd.segs) cols += sg.ncol;
             s += ",\"gen_fwd_seg_cols\":" + std::to_string(cols);
+            // entries the matrix-core kernels multiply: 16-column groups of the
+            // transposed items' 64-column tiles times 64 rows; 8-column steps of
+            // the forward segments times 64 rows
+            int64_t ea = 0, ef = 0;
+            for (auto &it : pk.gen_adj.items)
+                for (int q = it.seg_begin; q < it.seg_end; ++q) {
+                    const auto &sg = pk.gen_adj.segs[q];
+                    for (int g = 0; g < 4; ++g) {
+                        const int g0 = it.col0 + 16 * g;
+                        if (g0 + 16 > sg.c0 && g0 < sg.c0 + sg.ncol) ea += 16 * 64;
+                    }
+                }
+            for (auto &sg : pk.gen_fwd.segs) ef += (int64_t)((sg.ncol + 7) / 8) * 8 * 64;
+            s += ",\"gen_adj_mfma_entries\":" + std::to_string(ea) + ",\"gen_fwd_mfma_entries\":" + std::to_string(ef);
         }
         s += "}";
     }

@@ -24,6 +24,7 @@ namespace idbf {
 struct HostProgram {
     int N = 0;
     int f32_mode = 0;  // SHT_F32_VALU or SHT_F32_SPLIT_BF16
+    int level_schedule = 0;  // SHT_LEVELS_*
     PackedPlan packed;
     BuildStats stats;
     std::string stats_json;

@@ -21,12 +21,28 @@ struct DeviceProgramDir {
     // entry ntask is the stage end
     std::vector<std::vector<int32_t>> stage_task_first;
     std::vector<Stage> stages;  // host copy (LDS sizing per stage)
+    // fused levels: groups split into size classes (LDS buffers of up to
+    // kFusedRowsSmall rows, up to kFusedMaxRows rows, staged rows in HBM);
+    // class c's group ids are glist[cls_first[c] ..], task ranges by
+    // cls_task_first[c][t]
+    bool fused_ok = false;
+    FusedGroup *d_fgroups = nullptr;
+    FusedLevel *d_flevels = nullptr;
+    Op *d_fops = nullptr;
+    SubOp *d_fsubs = nullptr;
+    int32_t *d_glist = nullptr;
+    std::vector<int32_t> cls_first;                    // [3]
+    std::vector<std::vector<int32_t>> cls_task_first;  // [3][ntask + 1], relative to cls_first
 };
+
+// groups with at most this many rows per LDS buffer run in 64 KB of LDS
+constexpr int kFusedRowsSmall = 256;
 
 struct DeviceProgram {
     bool valid = false;
     int N = 0, batch = 0, dtype = 0, RC = 16;
     int RCW = 0;  // > 0: matrix-core executor with RCW columns per pass
+    bool fused = false;  // the matrix-core executor runs the fused level form
     bool bf16 = false;  // FP32 plan on the BF16 matrix cores (split-BF16)
     int bf16_terms = 3;  // 3 or 6 products per value pair
     void *d_X = nullptr, *d_Y = nullptr, *d_scrA = nullptr, *d_scrB = nullptr;

@@ -809,6 +809,159 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(CBP == 1 ? 1
         }
 }
 
+// Fused levels (the work stages in one launch): one workgroup of NW waves per
+// (block, 16 right-hand sides).  The block's levels run in order; the ops of a
+// level are spread over the waves (one wave per op, lanes as in k_ops_mfma)
+// and accumulate straight into their rows of the level's LDS buffer, which
+// the workgroup clears first (ops of a level write disjoint rows, so no two
+// waves touch one row).  The next level reads those rows from LDS; the last
+// level goes to the scratch rows the final stage reads.  GLOBAL: blocks whose
+// levels exceed the LDS buffers keep their scratch rows in HBM; each wave then
+// sums an op in its own 64-row LDS accumulator and writes the rows out.
+template <typename T>
+__device__ __forceinline__ void fused_op(const Op &op, const SubOp *__restrict__ subs, const int32_t *__restrict__ idx,
+                                         const T *__restrict__ vals, const T *in, int64_t in_stride, const T *scrA,
+                                         const T *scrB, int64_t scr_stride, const double *lds, int col, bool cok,
+                                         double *acc) {
+    const int lane = threadIdx.x & 63, jl = lane >> 4, cl = lane & 15;
+    for (int s = 0; s < op.nsub; ++s) {
+        const SubOp sb = subs[op.sub0 + s];
+        const bool local = sb.src == kLds;
+        const T *src = sb.src == kIn ? in : sb.src == kScrA ? scrA : scrB;
+        const int64_t sstride = sb.src == kIn ? in_stride : scr_stride;
+        const int nin = sb.n_in, nmap = sb.n_map;
+        if (nmap > 0) {
+            const int32_t *inr = idx + sb.in_off;
+            int rows[16];
+#pragma unroll
+            for (int st = 0; st < 16; ++st) {
+                const int j = 4 * st + jl;
+                rows[st] = j < nin ? inr[j] : -1;
+            }
+            double B[16];
+            if (local) {
+#pragma unroll
+                for (int st = 0; st < 16; ++st) B[st] = rows[st] >= 0 ? lds[rows[st] * 16 + cl] : 0.0;
+            } else {
+#pragma unroll
+                for (int st = 0; st < 16; ++st)
+                    B[st] = (rows[st] >= 0 && cok) ? (double)src[(int64_t)rows[st] * sstride + col] : 0.0;
+            }
+            const int32_t *map = idx + sb.map_off;
+            const T *mv = vals + sb.mat_off;
+            const int ntile = (nmap + 15) >> 4;
+            for (int t = 0; t < ntile; ++t) {
+                const int q = 16 * t + cl;
+                const int aoff = jl * nmap + q;
+                double A[16];
+#pragma unroll
+                for (int st = 0; st < 16; ++st) {
+                    const T *mg = mv + (int64_t)(4 * st) * nmap;
+                    A[st] = (q < nmap && 4 * st + jl < nin) ? (double)mg[aoff] : 0.0;
+                }
+                int dst[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int qq = 16 * t + jl + 4 * i;
+                    dst[i] = qq < nmap ? map[qq] : -1;
+                }
+                d4v D = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int st = 0; st < 16; ++st) {
+                    if (4 * st >= nin) break;
+                    D = __builtin_amdgcn_mfma_f64_16x16x4f64(A[st], B[st], D, 0, 0, 0);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (dst[i] >= 0) acc[dst[i] * 16 + cl] += D[i];
+            }
+        }
+        if (sb.n_dir > 0) {
+            // the identity terms may land on rows the products just wrote
+            // (other lanes of this wave): LDS accesses of one wave stay in order
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int32_t *dir = idx + sb.dir_off;
+            for (int d0 = 0; d0 < sb.n_dir; d0 += 32) {
+                int sr[8], dr[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int d = d0 + 4 * k + jl;
+                    sr[k] = d < sb.n_dir ? dir[2 * d] : -1;
+                    dr[k] = d < sb.n_dir ? dir[2 * d + 1] : -1;
+                }
+                double v[8];
+                if (local) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) v[k] = sr[k] >= 0 ? lds[sr[k] * 16 + cl] : 0.0;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        v[k] = (sr[k] >= 0 && cok) ? (double)src[(int64_t)sr[k] * sstride + col] : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (dr[k] >= 0) acc[dr[k] * 16 + cl] += v[k];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+template <typename T, int NW, bool GLOBAL>
+__global__ __launch_bounds__(64 * NW) void k_ops_fused(const FusedGroup *__restrict__ groups,
+                                                        const int32_t *__restrict__ glist, int g0, int n_items, int ncb,
+                                                        const FusedLevel *__restrict__ levels,
+                                                        const Op *__restrict__ fops, const SubOp *__restrict__ fsubs,
+                                                        const int32_t *__restrict__ idx, const T *__restrict__ vals,
+                                                        const T *__restrict__ in, int64_t in_stride, T *scrA, T *scrB,
+                                                        int64_t scr_stride, int rc) {
+    extern __shared__ double fsm[];
+    const int wi = xcd_item(n_items, kXc);
+    if (wi >= n_items) return;
+    const int gi = glist[g0 + wi / ncb], cb = wi % ncb;
+    const FusedGroup g = groups[gi];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, cl = lane & 15, jl = lane >> 4;
+    const int col = 16 * cb + cl;
+    const bool cok = col < rc;
+    const int lr = g.lds_rows;
+    for (int l = 0; l < g.nlev; ++l) {
+        const FusedLevel fl = levels[g.lvl_begin + l];
+        if (!GLOBAL) {
+            double *ob = fsm + (size_t)(l & 1) * lr * 16;
+            for (int e = threadIdx.x; e < fl.rows * 16; e += 64 * NW) ob[e] = 0.0;
+            __syncthreads();
+        }
+        for (int o = fl.op_begin + wave; o < fl.op_end; o += NW) {
+            const Op op = fops[o];
+            if (GLOBAL) {
+                double *acc = fsm + (size_t)wave * 64 * 16;
+                for (int e = lane; e < op.n_out * 16; e += 64) acc[e] = 0.0;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                fused_op<T>(op, fsubs, idx, vals, in, in_stride, scrA, scrB, scr_stride, fsm, col, cok, acc);
+                T *dst = op.dst == kScrA ? scrA : scrB;
+                if (cok)
+                    for (int i = jl; i < op.n_out; i += 4) dst[(op.dst_row + i) * scr_stride + col] = (T)acc[i * 16 + cl];
+            } else {
+                fused_op<T>(op, fsubs, idx, vals, in, in_stride, scrA, scrB, scr_stride, fsm, col, cok,
+                            fsm + (size_t)op.dst_row * 16);
+            }
+        }
+        __syncthreads();
+    }
+    if (!GLOBAL) {
+        const FusedLevel last = levels[g.lvl_begin + g.nlev - 1];
+        const double *lb = fsm + (size_t)((g.nlev - 1) & 1) * lr * 16;
+        T *dst = g.out_buf == kScrA ? scrA : scrB;
+        for (int e = threadIdx.x; e < last.rows * 16; e += 64 * NW) {
+            const int r = e >> 4, c = e & 15;
+            if (16 * cb + c < rc) dst[(g.out_row + r) * scr_stride + 16 * cb + c] = (T)lb[e];
+        }
+    }
+}
+
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 
@@ -834,9 +987,33 @@ hipError_t run_t(const DeviceProgram &p, int batch, int a_lo, int a_hi, int dir,
     const bool mfma = p.RCW > 0 && !p.bf16;
     const bool bf16 = sizeof(T) == 4 && p.bf16;
     const int RC = (mfma || bf16) ? p.RCW : p.RC;
+    const bool fused = mfma && p.fused;
     for (int c0 = 0; c0 < R; c0 += RC) {
         const int rc = std::min(RC, R - c0);
-        for (size_t st = 0; st < pd.stage_task_first.size(); ++st) {
+        if (fused) {
+            // every block's levels in one launch per size class
+            prof::Scope ps(s, "k_ops_fused");
+            const int ncb = (rc + 15) / 16;
+            for (int c = 0; c < 3; ++c) {
+                const std::vector<int32_t> &tf = pd.cls_task_first[c];
+                const int gb = tf[t_lo], ge = tf[t_hi + 1];
+                if (ge <= gb) continue;
+                const int n_items = (ge - gb) * ncb;
+                const int g0 = pd.cls_first[c] + gb;
+#define SHT_FUSED_LAUNCH(NW, GL, LDSB)                                                                             \
+    hipLaunchKernelGGL((k_ops_fused<T, NW, GL>), dim3(xcd_grid(n_items)), dim3(64 * NW), LDSB, s, pd.d_fgroups,      \
+                       pd.d_glist, g0, n_items, ncb, pd.d_flevels, pd.d_fops, pd.d_fsubs, pd.d_idx, vals,            \
+                       (const T *)(in + c0), (int64_t)R, scrA, scrB, (int64_t)RC, rc)
+                if (c == 0)
+                    SHT_FUSED_LAUNCH(4, false, 2 * kFusedRowsSmall * 16 * sizeof(double));
+                else if (c == 1)
+                    SHT_FUSED_LAUNCH(8, false, 2 * kFusedMaxRows * 16 * sizeof(double));
+                else
+                    SHT_FUSED_LAUNCH(4, true, 4 * 64 * 16 * sizeof(double));
+#undef SHT_FUSED_LAUNCH
+            }
+        }
+        for (size_t st = fused ? (size_t)pd.stages.size() - 1 : 0; st < pd.stage_task_first.size(); ++st) {
             const std::vector<int32_t> &tf = pd.stage_task_first[st];
             const int ob = tf[t_lo], oe = tf[t_hi + 1];
             if (oe <= ob) continue;
@@ -970,7 +1147,10 @@ hipError_t set_kernel_attributes() {
                          (const void *)&k_ops_bf16<16, 3>,
                          (const void *)&k_ops_bf16<32, 3>,  (const void *)&k_ops_bf16<64, 3>,
                          (const void *)&k_ops_bf16<16, 6>,  (const void *)&k_ops_bf16<32, 6>,
-                         (const void *)&k_ops_bf16<64, 6>};
+                         (const void *)&k_ops_bf16<64, 6>,
+                         (const void *)&k_ops_fused<double, 4, false>, (const void *)&k_ops_fused<double, 8, false>,
+                         (const void *)&k_ops_fused<double, 4, true>,  (const void *)&k_ops_fused<float, 4, false>,
+                         (const void *)&k_ops_fused<float, 8, false>,  (const void *)&k_ops_fused<float, 4, true>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;

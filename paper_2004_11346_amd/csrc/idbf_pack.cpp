@@ -414,6 +414,7 @@ void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t>
     std::vector<std::vector<Op>> st_ops(D);
     std::vector<std::vector<int32_t>> st_task(D);
     std::vector<std::vector<std::vector<SubOp>>> st_subs(D);
+    std::vector<std::vector<std::vector<int>>> st_sublvl(D);  // source level of every sub-op
     std::vector<int64_t> st_rows(D, 0);
     Emitter em(p);
     p.ops.clear();
@@ -464,11 +465,15 @@ void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t>
             base = bbase[bi][lvl];
         }
     };
+    // ops of level l of block bi: st_ops[s][lvl_ops[bi][l].first .. second)
+    std::vector<std::vector<std::pair<size_t, size_t>>> lvl_ops(bps.size());
     for (size_t bi = 0; bi < bps.size(); ++bi) {
         BlockProg &b = bps[bi];
+        lvl_ops[bi].resize(b.levels.size());
         for (int l = 0; l < (int)b.levels.size(); ++l) {
             const int s = bstage[bi][l];
             Level &lv = b.levels[l];
+            lvl_ops[bi][l].first = st_ops[s].size();
             for (size_t q = 0; q < lv.ops.size(); ++q) {
                 const LOp &lo = lv.ops[q];
                 // outputs in chunks of at most kTile rows; every chunk keeps the
@@ -480,6 +485,7 @@ void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t>
                     op.dst = (s & 1) ? kScrB : kScrA;
                     op.dst_row = bbase[bi][l] + lv.off[q] + p0;
                     std::vector<SubOp> subs;
+                    std::vector<int> sublvl;
                     for (const LSub &ls : lo.subs) {
                         int buf;
                         int64_t base;
@@ -491,14 +497,17 @@ void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t>
                             if (ls.dir[i].second >= p0 && ls.dir[i].second < p1) dsel.push_back((int)i);
                         if (sel.empty() && dsel.empty()) continue;
                         em.emit(ls, sel, dsel, buf, base, p0, subs);
+                        sublvl.resize(subs.size(), ls.src_level);
                     }
                     op.nsub = (int32_t)subs.size();
                     st_ops[s].push_back(op);
                     st_task[s].push_back(b.task);
                     st_subs[s].push_back(std::move(subs));
+                    st_sublvl[s].push_back(std::move(sublvl));
                     if (lo.n_out == 0) break;
                 }
             }
+            lvl_ops[bi][l].second = st_ops[s].size();
         }
     }
     for (int s = 0; s < D; ++s) {
@@ -519,6 +528,146 @@ void schedule(std::vector<BlockProg> &bps, int ntask, const std::vector<int64_t>
         p.max_n_out = std::max(p.max_n_out, st.max_out);
     }
     p.n_work_stages = D;
+    // fused form of the work stages: one group per block with levels.  An LDS
+    // group's levels alternate between two LDS buffers of lr rows.  A group
+    // whose levels exceed them keeps its rows in HBM, but in rows of its own
+    // past the staged scratch rows (buffer A): its workgroup runs all its
+    // levels while other groups run, so the staged rows, which later stages
+    // reuse, are not free for it; its last level goes to the staged rows the
+    // final stage reads, as an LDS group's does.
+    p.fgroups.clear();
+    p.flevels.clear();
+    p.fops.clear();
+    p.fsubs.clear();
+    p.f_max_lds_rows = 0;
+    p.f_extra_rows = 0;
+    bool fok = true;
+    for (size_t bi = 0; bi < bps.size(); ++bi) {
+        const BlockProg &b = bps[bi];
+        const int nl = (int)b.levels.size();
+        if (nl == 0) continue;
+        int64_t lr = 0;
+        for (const Level &lv : b.levels) lr = std::max(lr, lv.rows);
+        const bool inlds = lr <= kFusedMaxRows;
+        // first row of level l in its buffer, and the buffer
+        std::vector<int64_t> lbase(nl);
+        std::vector<int32_t> lbuf(nl);
+        for (int l = 0; l < nl; ++l) {
+            if (inlds) {
+                lbase[l] = (int64_t)(l & 1) * lr;
+                lbuf[l] = kLds;
+            } else if (l < nl - 1) {
+                lbase[l] = p.scr_rows + p.f_extra_rows;
+                lbuf[l] = kScrA;
+                p.f_extra_rows += b.levels[l].rows;
+            } else {
+                lbase[l] = bbase[bi][l];
+                lbuf[l] = (bstage[bi][l] & 1) ? kScrB : kScrA;
+            }
+        }
+        FusedGroup g{};
+        g.lvl_begin = (int32_t)p.flevels.size();
+        g.nlev = nl;
+        g.lds_rows = (int32_t)std::min<int64_t>(lr, INT32_MAX);
+        g.out_buf = (bstage[bi][nl - 1] & 1) ? kScrB : kScrA;
+        g.out_row = bbase[bi][nl - 1];
+        g.task = b.task;
+        for (int l = 0; l < nl; ++l) {
+            const int s = bstage[bi][l];
+            FusedLevel fl{};
+            fl.op_begin = (int32_t)p.fops.size();
+            fl.rows = (int32_t)b.levels[l].rows;
+            for (size_t q = lvl_ops[bi][l].first; q < lvl_ops[bi][l].second; ++q) {
+                const Op &so = p.ops[(size_t)p.stages[s].op_begin + q];
+                Op fo = so;
+                fo.dst = lbuf[l];
+                fo.dst_row = lbase[l] + (so.dst_row - bbase[bi][l]);
+                fo.sub0 = (int32_t)p.fsubs.size();
+                for (int k = 0; k < so.nsub; ++k) {
+                    SubOp fs = p.subs[(size_t)so.sub0 + k];
+                    if (fs.src != kIn) {
+                        const int sl = st_sublvl[s][q][k];
+                        if (sl != l - 1 || sl < 0) {
+                            fok = false;
+                        } else {
+                            const int64_t off = lbase[sl] - bbase[bi][sl];
+                            std::vector<int32_t> in(fs.n_in), dr(2 * (size_t)fs.n_dir);
+                            for (int j = 0; j < fs.n_in; ++j) in[j] = (int32_t)(p.idx[fs.in_off + j] + off);
+                            for (int d = 0; d < fs.n_dir; ++d) {
+                                dr[2 * d] = (int32_t)(p.idx[fs.dir_off + 2 * d] + off);
+                                dr[2 * d + 1] = p.idx[fs.dir_off + 2 * d + 1];
+                            }
+                            fs.src = lbuf[sl];
+                            fs.in_off = em.push_idx(in);
+                            fs.dir_off = em.push_idx(dr);
+                        }
+                    }
+                    p.fsubs.push_back(fs);
+                }
+                p.fops.push_back(fo);
+            }
+            fl.op_end = (int32_t)p.fops.size();
+            p.flevels.push_back(fl);
+        }
+        p.fgroups.push_back(g);
+        p.f_max_lds_rows = std::max(p.f_max_lds_rows, g.lds_rows);
+    }
+    // bounds of the fused form, as its kernel assumes them: an LDS group's ops
+    // write inside the rows its level clears and read inside the rows of the
+    // level before; a staged-row group's ops fit the 64-row accumulator
+    for (const FusedGroup &g : p.fgroups) {
+        const bool inlds = g.lds_rows <= kFusedMaxRows;
+        for (int l = 0; l < g.nlev && fok; ++l) {
+            const FusedLevel &fl = p.flevels[(size_t)g.lvl_begin + l];
+            const int64_t lo = (int64_t)(l & 1) * g.lds_rows, hi = lo + fl.rows;
+            const int64_t plo = (int64_t)((l + 1) & 1) * g.lds_rows;
+            const int64_t phi = l > 0 ? plo + p.flevels[(size_t)g.lvl_begin + l - 1].rows : plo;
+            if (fl.rows > g.lds_rows) fok = false;
+            for (int q = fl.op_begin; q < fl.op_end && fok; ++q) {
+                const Op &op = p.fops[q];
+                if (inlds ? (op.dst != kLds || op.dst_row < lo || op.dst_row + op.n_out > hi)
+                          : (op.n_out > kTile || (op.dst != kScrA && op.dst != kScrB) || op.dst_row < 0 ||
+                             op.dst_row + op.n_out > p.scr_rows + p.f_extra_rows ||
+                             (l < g.nlev - 1 && (op.dst != kScrA || op.dst_row < p.scr_rows))))
+                    fok = false;
+                for (int k = 0; k < op.nsub && fok; ++k) {
+                    const SubOp &so = p.fsubs[(size_t)op.sub0 + k];
+                    for (int q2 = 0; q2 < so.n_map; ++q2) {
+                        const int32_t m = p.idx[(size_t)so.map_off + q2];
+                        if (m < 0 || m >= op.n_out) fok = false;
+                    }
+                    for (int d = 0; d < so.n_dir; ++d) {
+                        const int32_t m = p.idx[(size_t)so.dir_off + 2 * d + 1];
+                        if (m < 0 || m >= op.n_out) fok = false;
+                    }
+                    if (so.src == kScrA || so.src == kScrB) {
+                        // a staged-row group reads its own rows of the level before
+                        if (inlds || so.src != kScrA) fok = false;
+                        for (int j = 0; j < so.n_in; ++j) {
+                            const int32_t r = p.idx[(size_t)so.in_off + j];
+                            if (r < p.scr_rows || r >= p.scr_rows + p.f_extra_rows) fok = false;
+                        }
+                        for (int d = 0; d < so.n_dir; ++d) {
+                            const int32_t r = p.idx[(size_t)so.dir_off + 2 * d];
+                            if (r < p.scr_rows || r >= p.scr_rows + p.f_extra_rows) fok = false;
+                        }
+                    }
+                    if (so.src == kLds) {
+                        if (!inlds) fok = false;
+                        for (int j = 0; j < so.n_in; ++j) {
+                            const int32_t r = p.idx[(size_t)so.in_off + j];
+                            if (r < plo || r >= phi) fok = false;
+                        }
+                        for (int d = 0; d < so.n_dir; ++d) {
+                            const int32_t r = p.idx[(size_t)so.dir_off + 2 * d];
+                            if (r < plo || r >= phi) fok = false;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    p.fused_ok = fok ? 1 : 0;
     // final stage: output tiles per task
     std::vector<std::vector<size_t>> by_task(ntask);
     for (size_t bi = 0; bi < bps.size(); ++bi) by_task[bps[bi].task].push_back(bi);
@@ -802,35 +951,114 @@ void host_run_gen_adjoint(const GenAdjoint &ga, int N, int t_lo, int t_hi, int R
     }
 }
 
-void host_run_program(const Program &p, int R, const double *in, double *out) {
+std::string fused_stats_json(const PackedPlan &pk) {
+    std::string s;
+    for (int d = 0; d < 2; ++d) {
+        const Program &p = d ? pk.adj : pk.fwd;
+        const std::string pre = d ? ",\"adj_fused_" : ",\"fwd_fused_";
+        s += pre + "ok\":" + std::to_string(p.fused_ok) + pre + "groups\":" + std::to_string(p.fgroups.size()) +
+             pre + "max_lds_rows\":" + std::to_string(p.f_max_lds_rows) + pre + "ops\":" + std::to_string(p.fops.size());
+        // groups and their stored values by rows per buffer (up to 128, 256,
+        // 384, 512, 768, more)
+        const int lim[5] = {128, 256, 384, 512, 768};
+        int64_t ng[6] = {0}, nv[6] = {0};
+        for (const FusedGroup &g : p.fgroups) {
+            int b = 0;
+            while (b < 5 && g.lds_rows > lim[b]) ++b;
+            ++ng[b];
+            for (int l = 0; l < g.nlev; ++l) {
+                const FusedLevel &fl = p.flevels[(size_t)g.lvl_begin + l];
+                for (int q = fl.op_begin; q < fl.op_end; ++q)
+                    for (int k = 0; k < p.fops[q].nsub; ++k) {
+                        const SubOp &so = p.fsubs[(size_t)p.fops[q].sub0 + k];
+                        nv[b] += (int64_t)so.n_map * so.n_in;
+                    }
+            }
+        }
+        s += pre + "rows_hist\":[";
+        for (int b = 0; b < 6; ++b) s += "[" + std::to_string(ng[b]) + "," + std::to_string(nv[b]) + "]" + (b < 5 ? "," : "");
+        s += "]";
+    }
+    return s;
+}
+
+namespace {
+
+// acc[0 .. n_out) += the sub-ops of op (rows of R values); src_of maps a
+// buffer id to its rows
+template <typename Src>
+void host_op(const Program &p, const Op &op, const std::vector<SubOp> &subs, int R, Src src_of, double *acc) {
+    for (int s = 0; s < op.nsub; ++s) {
+        const SubOp &sb = subs[(size_t)op.sub0 + s];
+        const double *src = src_of(sb.src);
+        const int32_t *inr = &p.idx[sb.in_off];
+        const int32_t *map = &p.idx[sb.map_off];
+        for (int qq = 0; qq < sb.n_map; ++qq) {
+            double *a = acc + (size_t)map[qq] * R;
+            for (int j = 0; j < sb.n_in; ++j) {
+                const double mv = p.vals[sb.mat_off + (int64_t)j * sb.n_map + qq];
+                const double *x = src + (size_t)inr[j] * R;
+                for (int r = 0; r < R; ++r) a[r] += mv * x[r];
+            }
+        }
+        const int32_t *dir = &p.idx[sb.dir_off];
+        for (int d = 0; d < sb.n_dir; ++d) {
+            const double *x = src + (size_t)dir[2 * d] * R;
+            double *a = acc + (size_t)dir[2 * d + 1] * R;
+            for (int r = 0; r < R; ++r) a[r] += x[r];
+        }
+    }
+}
+
+}  // namespace
+
+void host_run_program(const Program &p, int R, const double *in, double *out, bool fused) {
     std::vector<double> scr[2];
-    scr[0].assign((size_t)std::max<int64_t>(1, p.scr_rows) * R, 0.0);
+    scr[0].assign((size_t)std::max<int64_t>(1, p.scr_rows + (fused ? p.f_extra_rows : 0)) * R, 0.0);
     scr[1].assign((size_t)std::max<int64_t>(1, p.scr_rows) * R, 0.0);
-    std::vector<double> acc;
-    for (const Stage &st : p.stages) {
+    std::vector<double> acc, lds;
+    size_t st0 = 0;
+    if (fused) {
+        auto gsrc = [&](int32_t b) { return b == kIn ? in : b == kScrA ? scr[0].data() : scr[1].data(); };
+        for (const FusedGroup &g : p.fgroups) {
+            if (g.lds_rows > kFusedMaxRows) {  // staged rows, level by level
+                for (int l = 0; l < g.nlev; ++l) {
+                    const FusedLevel &fl = p.flevels[(size_t)g.lvl_begin + l];
+                    for (int q = fl.op_begin; q < fl.op_end; ++q) {
+                        const Op &op = p.fops[q];
+                        acc.assign((size_t)op.n_out * R, 0.0);
+                        host_op(p, op, p.fsubs, R, gsrc, acc.data());
+                        double *dst = op.dst == kScrA ? scr[0].data() : scr[1].data();
+                        std::memcpy(dst + (size_t)op.dst_row * R, acc.data(), sizeof(double) * acc.size());
+                    }
+                }
+                continue;
+            }
+            lds.assign(2 * (size_t)g.lds_rows * R, 0.0);
+            auto src_of = [&](int32_t b) { return b == kIn ? in : lds.data(); };
+            for (int l = 0; l < g.nlev; ++l) {
+                const FusedLevel &fl = p.flevels[(size_t)g.lvl_begin + l];
+                double *buf = lds.data() + (size_t)(l & 1) * g.lds_rows * R;
+                std::fill(buf, buf + (size_t)fl.rows * R, 0.0);
+                for (int q = fl.op_begin; q < fl.op_end; ++q) {
+                    const Op &op = p.fops[q];
+                    host_op(p, op, p.fsubs, R, src_of, lds.data() + (size_t)op.dst_row * R);
+                }
+            }
+            const FusedLevel &last = p.flevels[(size_t)g.lvl_begin + g.nlev - 1];
+            const double *buf = lds.data() + (size_t)((g.nlev - 1) & 1) * g.lds_rows * R;
+            double *dst = (g.out_buf == kScrA ? scr[0].data() : scr[1].data()) + (size_t)g.out_row * R;
+            std::memcpy(dst, buf, sizeof(double) * (size_t)last.rows * R);
+        }
+        st0 = (size_t)p.n_work_stages;
+    }
+    auto src_of = [&](int32_t b) { return b == kIn ? in : b == kScrA ? scr[0].data() : scr[1].data(); };
+    for (size_t si = st0; si < p.stages.size(); ++si) {
+        const Stage &st = p.stages[si];
         for (int q = st.op_begin; q < st.op_end; ++q) {
             const Op &op = p.ops[q];
             acc.assign((size_t)op.n_out * R, 0.0);
-            for (int s = 0; s < op.nsub; ++s) {
-                const SubOp &sb = p.subs[op.sub0 + s];
-                const double *src = sb.src == kIn ? in : sb.src == kScrA ? scr[0].data() : scr[1].data();
-                const int32_t *inr = &p.idx[sb.in_off];
-                const int32_t *map = &p.idx[sb.map_off];
-                for (int qq = 0; qq < sb.n_map; ++qq) {
-                    double *a = &acc[(size_t)map[qq] * R];
-                    for (int j = 0; j < sb.n_in; ++j) {
-                        const double mv = p.vals[sb.mat_off + (int64_t)j * sb.n_map + qq];
-                        const double *x = src + (size_t)inr[j] * R;
-                        for (int r = 0; r < R; ++r) a[r] += mv * x[r];
-                    }
-                }
-                const int32_t *dir = &p.idx[sb.dir_off];
-                for (int d = 0; d < sb.n_dir; ++d) {
-                    const double *x = src + (size_t)dir[2 * d] * R;
-                    double *a = &acc[(size_t)dir[2 * d + 1] * R];
-                    for (int r = 0; r < R; ++r) a[r] += x[r];
-                }
-            }
+            host_op(p, op, p.subs, R, src_of, acc.data());
             double *dst = op.dst == kOut ? out : op.dst == kScrA ? scr[0].data() : scr[1].data();
             std::memcpy(dst + (size_t)op.dst_row * R, acc.data(), sizeof(double) * acc.size());
         }

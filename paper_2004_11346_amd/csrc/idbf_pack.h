@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <string>
 #include <vector>
 
 #include "idbf_build.h"
@@ -63,6 +64,9 @@ struct PackedPlan {
 };
 
 void pack_programs(const HostPlanData &hp, PackedPlan &pk);
+
+// ",\"fused_ok\":..." statistics of the fused level form of both programs
+std::string fused_stats_json(const PackedPlan &pk);
 
 // Host application of the regenerated transposed blocks of tasks t_lo..t_hi
 // (verification): out (X panels) += blocks^T x in (Y panels).

@@ -48,6 +48,28 @@ hipError_t upload_dir(Program &p, int ntask, int dtype, DeviceProgramDir &d) {
         tf[ntask] = st.op_end;
         d.stage_task_first.push_back(std::move(tf));
     }
+    d.fused_ok = p.fused_ok != 0;
+    if (d.fused_ok) {
+        if ((e = up(p.fgroups, &d.d_fgroups)) != hipSuccess || (e = up(p.flevels, &d.d_flevels)) != hipSuccess ||
+            (e = up(p.fops, &d.d_fops)) != hipSuccess || (e = up(p.fsubs, &d.d_fsubs)) != hipSuccess)
+            return e;
+        std::vector<int32_t> glist;
+        d.cls_first.assign(3, 0);
+        d.cls_task_first.assign(3, std::vector<int32_t>(ntask + 1, 0));
+        for (int c = 0; c < 3; ++c) {
+            d.cls_first[c] = (int32_t)glist.size();
+            std::vector<int32_t> &tf = d.cls_task_first[c];
+            for (size_t gi = 0; gi < p.fgroups.size(); ++gi) {
+                const int r = p.fgroups[gi].lds_rows;
+                const int gc = r <= kFusedRowsSmall ? 0 : r <= kFusedMaxRows ? 1 : 2;
+                if (gc != c) continue;
+                tf[p.fgroups[gi].task + 1]++;
+                glist.push_back((int32_t)gi);
+            }
+            for (int t = 0; t < ntask; ++t) tf[t + 1] += tf[t];
+        }
+        if ((e = up(glist, &d.d_glist)) != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 
@@ -64,6 +86,10 @@ void DeviceProgram::release() {
     for (void *p : {d_X, d_Y, d_scrA, d_scrB, (void *)d_x_off, fwd.d_vals, (void *)fwd.d_ops, (void *)fwd.d_subs,
                     (void *)fwd.d_idx, adj.d_vals, (void *)adj.d_ops, (void *)adj.d_subs, (void *)adj.d_idx})
         if (p) (void)hipFree(p);
+    for (DeviceProgramDir *dd : {&fwd, &adj})
+        for (void *p : {(void *)dd->d_fgroups, (void *)dd->d_flevels, (void *)dd->d_fops, (void *)dd->d_fsubs,
+                        (void *)dd->d_glist})
+            if (p) (void)hipFree(p);
     for (Gen *g : {&gen, &gena}) {
         for (void *q : {g->d_items, g->d_segs, (void *)g->d_ck, (void *)g->d_ckexp})
             if (q) (void)hipFree(q);
@@ -99,6 +125,7 @@ int build_program(int N, int batch, const LegendreTables &lt, const sht_plan_opt
     }
     out.N = N;
     out.f32_mode = opts.f32_mode;
+    out.level_schedule = opts.level_schedule;
     std::ostringstream os;
     std::string base = idbf::stats_json(out.stats, opts);
     base.pop_back();  // strip '}'
@@ -113,7 +140,7 @@ int build_program(int N, int batch, const LegendreTables &lt, const sht_plan_opt
        << ",\"fwd_stages\":" << out.packed.fwd.stages.size() << ",\"fwd_work_stages\":"
        << out.packed.fwd.n_work_stages << ",\"adj_stages\":" << out.packed.adj.stages.size()
        << ",\"fwd_ops\":" << out.packed.fwd.ops.size() << ",\"scratch_rows\":"
-       << std::max(out.packed.fwd.scr_rows, out.packed.adj.scr_rows);
+       << std::max(out.packed.fwd.scr_rows, out.packed.adj.scr_rows) << fused_stats_json(out.packed);
     // per direction: index stream and recurrence states read by one call
     const PackedPlan &pk = out.packed;
     const int64_t fwd_idx = 4 * (int64_t)pk.fwd.idx.size() + (int64_t)pk.fwd.ops.size() * sizeof(Op) +
@@ -209,6 +236,14 @@ int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, co
     d.d_coef2 = d_coef2;
     if ((e = upload_dir(hp.packed.fwd, ntask, dtype, d.fwd)) != hipSuccess) return fail(e, "upload program");
     if ((e = upload_dir(hp.packed.adj, ntask, dtype, d.adj)) != hipSuccess) return fail(e, "upload program");
+    // fused levels on request, on the matrix-core executor (every block's
+    // levels in one workgroup); the staged schedule otherwise
+    d.fused = d.RCW > 0 && !d.bf16 && hp.level_schedule == SHT_LEVELS_FUSED && d.fwd.fused_ok && d.adj.fused_ok;
+    if (hp.level_schedule == SHT_LEVELS_FUSED && !d.fused) {
+        set_error_detail("fused levels need the FP64 matrix-core executor (16 or more right-hand sides, "
+                         "not split-BF16)");
+        return SHT_ERR_UNSUPPORTED;
+    }
     {
         GenForward &gf = pk.gen_fwd;
         d.gen.n_items = (int)gf.items.size();
@@ -237,9 +272,12 @@ int upload_program(HostProgram &hp, int dtype, int batch, const double *d_wh, co
         return fail(e, "X panels");
     if ((e = hipMalloc(&d.d_Y, es * std::max<int64_t>(1, pk.y_off[ntask]) * R)) != hipSuccess)
         return fail(e, "Y panels");
+    // the fused form's rows of its own follow the staged rows in buffer A
     const int64_t sr = std::max<int64_t>(1, std::max(pk.fwd.scr_rows, pk.adj.scr_rows));
+    const int64_t sra = std::max<int64_t>(sr, std::max(pk.fwd.scr_rows + pk.fwd.f_extra_rows,
+                                                       pk.adj.scr_rows + pk.adj.f_extra_rows));
     const int64_t sw = std::max(d.RC, d.RCW);
-    if ((e = hipMalloc(&d.d_scrA, es * sr * sw)) != hipSuccess) return fail(e, "scratch");
+    if ((e = hipMalloc(&d.d_scrA, es * sra * sw)) != hipSuccess) return fail(e, "scratch");
     if ((e = hipMalloc(&d.d_scrB, es * sr * sw)) != hipSuccess) return fail(e, "scratch");
     if ((e = set_kernel_attributes()) != hipSuccess) return fail(e, "kernel attributes");
     d.valid = true;

@@ -25,8 +25,8 @@
 namespace sht {
 namespace idbf {
 
-// source / destination buffers
-enum Buf : int32_t { kIn = 0, kScrA = 1, kScrB = 2, kOut = 3 };
+// source / destination buffers (kLds: the fused form's workgroup-local rows)
+enum Buf : int32_t { kIn = 0, kScrA = 1, kScrB = 2, kOut = 3, kLds = 4 };
 
 struct SubOp {
     int64_t mat_off;  // value offset of the output-major matrix (n_in x n_map)
@@ -53,6 +53,31 @@ struct Stage {
     int32_t max_out, max_in;   // largest n_out / n_in of the stage (LDS sizing)
 };
 
+// Fused form of the work stages: all non-final levels of one block (a
+// butterfly's column pass, middle couplings and row pass, or a low-rank
+// block's V^T) run in one workgroup, level after level, with the intermediate
+// rows in two LDS buffers that alternate between levels (level l writes
+// buffer l & 1).  Ops and sub-ops are those of the staged program with rows
+// renumbered into the buffers (src / dst kLds); the matrices are the staged
+// program's (same value offsets).  The block's last level is then written to
+// the scratch rows the final stage reads.  A block whose levels exceed
+// kFusedMaxRows rows keeps its intermediate rows in HBM (rows of its own past
+// the staged scratch rows) and runs its levels in its workgroup.
+struct FusedLevel {
+    int32_t op_begin, op_end;  // range in Program::fops
+    int32_t rows;              // rows the level writes (from row 0 of its buffer)
+    int32_t pad;
+};
+
+struct FusedGroup {
+    int32_t lvl_begin, nlev;  // range in Program::flevels
+    int32_t lds_rows;         // rows of each LDS buffer (> kFusedMaxRows: rows in HBM)
+    int32_t out_buf;          // kScrA / kScrB: destination of the last level
+    int64_t out_row;          // its first scratch row
+    int32_t task;
+    int32_t pad;
+};
+
 struct Program {
     std::vector<Op> ops;
     std::vector<int32_t> op_task;  // task of every op (ops of a stage are sorted by task)
@@ -64,12 +89,26 @@ struct Program {
     int64_t scr_rows = 0;          // rows of each scratch buffer
     int64_t in_rows = 0, out_rows = 0;
     int max_n_out = 0, max_n_in = 0;
+    // fused form of stages [0, n_work_stages) (groups sorted by task);
+    // fused_ok: every sub-op reads the input panel or the level before its
+    // own
+    std::vector<FusedGroup> fgroups;
+    std::vector<FusedLevel> flevels;
+    std::vector<Op> fops;
+    std::vector<SubOp> fsubs;
+    int32_t f_max_lds_rows = 0;
+    int32_t fused_ok = 0;
+    int64_t f_extra_rows = 0;  // rows of scratch buffer A past scr_rows used by the fused form
 };
+
+// LDS rows per buffer of a fused group (two buffers of 16 FP64 columns: 128 KB)
+constexpr int kFusedMaxRows = 512;
 
 // Host execution of a program (verification): in [in_rows][R], out
 // [out_rows][R] (overwritten).  Regenerated dense blocks are not part of a
 // program; they run separately (see the regenerated-block executors).
-void host_run_program(const Program &p, int R, const double *in, double *out);
+// fused: the work stages run in their fused form (requires fused_ok).
+void host_run_program(const Program &p, int R, const double *in, double *out, bool fused = false);
 
 }  // namespace idbf
 }  // namespace sht

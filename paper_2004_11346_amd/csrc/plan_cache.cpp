@@ -18,7 +18,7 @@ namespace {
 constexpr char kMagic[8] = {'S', 'H', 'T', 'P', 'L', 'A', 'N', 0};
 constexpr uint32_t kFormat = 1;
 // bump when the builder or the packer changes what a plan contains
-constexpr int kPlanVersion = 2;
+constexpr int kPlanVersion = 3;
 
 uint64_t fnv1a(const unsigned char *p, size_t n) {
     uint64_t h = 1469598103934665603ULL;
@@ -82,6 +82,13 @@ void put_program(Writer &w, const Program &p) {
     w.pod(p.out_rows);
     w.pod(p.max_n_out);
     w.pod(p.max_n_in);
+    w.vec(p.fgroups);
+    w.vec(p.flevels);
+    w.vec(p.fops);
+    w.vec(p.fsubs);
+    w.pod(p.f_max_lds_rows);
+    w.pod(p.fused_ok);
+    w.pod(p.f_extra_rows);
 }
 
 void get_program(Reader &r, Program &p) {
@@ -97,6 +104,13 @@ void get_program(Reader &r, Program &p) {
     r.pod(p.out_rows);
     r.pod(p.max_n_out);
     r.pod(p.max_n_in);
+    r.vec(p.fgroups);
+    r.vec(p.flevels);
+    r.vec(p.fops);
+    r.vec(p.fsubs);
+    r.pod(p.f_max_lds_rows);
+    r.pod(p.fused_ok);
+    r.pod(p.f_extra_rows);
 }
 
 std::vector<unsigned char> payload_of(const PackedPlan &pk, const BuildStats &st) {

@@ -23,6 +23,7 @@ SHT_FWD, SHT_INV, SHT_ADJ = 0, 1, 2
 SHT_F32_VALU, SHT_F32_SPLIT_BF16, SHT_F32_SPLIT_BF16_6 = 0, 1, 2
 SHT_SAMPLE_MOCK_CHEB, SHT_SAMPLE_RANDOM = 0, 1
 SHT_DFT_AUTO, SHT_DFT_ROWS, SHT_DFT_RADER, SHT_DFT_FOUR_STEP = 0, 1, 2, 3
+SHT_LEVELS_AUTO, SHT_LEVELS_STAGED, SHT_LEVELS_FUSED = 0, 1, 2
 SHT_ERR_INVALID_ARG, SHT_ERR_UNSUPPORTED, SHT_ERR_PLAN_CORRUPT = -1, -2, -7
 SHT_GROUP_PERSISTENT, SHT_GROUP_BATCHED = 0, 1
 
@@ -64,6 +65,7 @@ class PlanOpts(ctypes.Structure):
         ("dft_schedule", ctypes.c_int),
         ("id_check", ctypes.c_int),
         ("cache_dir", ctypes.c_char_p),
+        ("level_schedule", ctypes.c_int),
     ]
 
 

@@ -145,3 +145,29 @@ def test_plan_stats_are_consistent():
     assert st["dense_entries"] == 64 * 64 * (2 * 64 + 1)
     area = st["osc"]["area"] + st["nonosc"]["area"] + st["turning"]["area"]
     assert area <= st["dense_entries"]
+
+
+@pytest.mark.parametrize("N,kw", [(64, dict(n0=32, leaf=8, rsvd_r=4)), (128, dict(n0=64, leaf=8, rsvd_r=4)),
+                                  (256, dict(n0=128, leaf=16))])
+def test_fused_level_form_equals_staged(N, kw):
+    """The fused form of the work stages (every block's levels in one
+    workgroup, rows renumbered into two alternating buffers; blocks too large
+    for the buffers keep their scratch rows) runs the same products in the
+    same order as the staged program: the host executions agree bitwise, and
+    the packer's bounds check of the fused form passes."""
+    staged = HostPlan(N, level_schedule=L.SHT_LEVELS_STAGED, **kw)
+    fused = HostPlan(N, level_schedule=L.SHT_LEVELS_FUSED, **kw)
+    st = fused.stats()
+    assert st["fwd_fused_ok"] == 1 and st["adj_fused_ok"] == 1
+    assert st["fwd_fused_groups"] > 0
+    if N == 256:
+        assert st["fwd_fused_max_lds_rows"] > 512  # staged rows inside the fused form
+    rng = np.random.default_rng(N)
+    for a in range(0, 2 * N, max(1, N // 8)):
+        for p in (0, 1):
+            c = half_cols(N, a, p)
+            if c <= 0:
+                continue
+            for d in (L.SHT_FWD, L.SHT_ADJ):
+                x = rng.standard_normal((c if d == L.SHT_FWD else N, 3))
+                assert np.array_equal(staged.apply(a, p, d, x), fused.apply(a, p, d, x)), (a, p, d)
