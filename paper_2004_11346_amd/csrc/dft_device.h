@@ -133,9 +133,10 @@ __device__ __forceinline__ void dft_small(typename V2<C>::t (&x)[R], const doubl
 
 // register butterflies of radix R over blocks of length L (table base Mt,
 // L divides Mt), `total` elements.  The twiddles w_L^{n1 k2} of a butterfly
-// are powers of w_L^{n1}, formed in FP64 from one table lookup; the outputs
-// k and R - k are stored as soon as they are formed (w^{R-k} = w^R conj(w^k)),
-// which keeps the live registers to the sums and differences of the inputs.
+// are powers of w_L^{n1}, formed in FP64 from table lookups of w and w^R; the
+// outputs k and R - k are stored as soon as they are formed
+// (w^{R-k} = w^R conj(w^k)), which keeps the live registers to the sums and
+// differences of the inputs.
 template <typename C, int R>
 __device__ __forceinline__ void pass_reg(typename V2<C>::t *buf, int total, int L, const double2 *t, int Mt,
                                          C sgn) {
@@ -146,8 +147,10 @@ __device__ __forceinline__ void pass_reg(typename V2<C>::t *buf, int total, int 
     if constexpr (R > 2) roots<R>(t, Mt, c, sn);
     const int unitL = 2 * (Mt / L);
     const int nb = total / R;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        const int blk = b / Ls, n1 = b - blk * Ls;
+    // butterfly b = blk Ls + n1, stepped by the block size without divisions
+    const int bd = blockDim.x, sdiv = bd / Ls, smod = bd - sdiv * Ls;
+    int blk = (int)threadIdx.x / Ls, n1 = (int)threadIdx.x - blk * Ls;
+    for (int b = threadIdx.x; b < nb; b += bd) {
         const int base = blk * L + n1;
         const double2 w1 = twd(t, n1 * unitL, (double)sgn);
         if constexpr (R == 2) {
@@ -167,10 +170,9 @@ __device__ __forceinline__ void pass_reg(typename V2<C>::t *buf, int total, int 
                 y0.y += sj[j].y;
             }
             buf[base] = y0;
-            // w^R for the conjugate-side twiddles
-            double2 wR = w1;
-#pragma unroll
-            for (int q = 1; q < R; ++q) wR = cmul<double>(wR, w1);
+            // w^R for the conjugate-side twiddles: one more table lookup
+            // (n1 R unitL < 2 Mt since n1 < L / R)
+            const double2 wR = twd(t, n1 * R * unitL, (double)sgn);
             double2 wk = w1;
 #pragma unroll
             for (int k = 1; k <= H; ++k) {
@@ -192,6 +194,12 @@ __device__ __forceinline__ void pass_reg(typename V2<C>::t *buf, int total, int 
                 buf[base + Ls * (R - k)] = cmul<C>(c2{a.x + bb.y, a.y - bb.x}, c2{(C)wm.x, (C)wm.y});
                 wk = cmul<double>(wk, w1);
             }
+        }
+        n1 += smod;
+        blk += sdiv;
+        if (n1 >= Ls) {
+            n1 -= Ls;
+            ++blk;
         }
     }
 }
@@ -270,8 +278,9 @@ __device__ __forceinline__ void pass_reg_inv(typename V2<C>::t *buf, int total, 
     if constexpr (R > 2) roots<R>(t, Mt, c, sn);
     const int unitL = 2 * (Mt / L);
     const int nb = total / R;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        const int blk = b / Ls, n1 = b - blk * Ls;
+    const int bd = blockDim.x, sdiv = bd / Ls, smod = bd - sdiv * Ls;
+    int blk = (int)threadIdx.x / Ls, n1 = (int)threadIdx.x - blk * Ls;
+    for (int b = threadIdx.x; b < nb; b += bd) {
         const int base = blk * L + n1;
         const double2 w1 = twd(t, n1 * unitL, -(double)sgn);
         c2 y[R];
@@ -285,6 +294,12 @@ __device__ __forceinline__ void pass_reg_inv(typename V2<C>::t *buf, int total, 
         dft_small<C, R>(y, c, sn, -sgn);
 #pragma unroll
         for (int n2 = 0; n2 < R; ++n2) buf[base + Ls * n2] = y[n2];
+        n1 += smod;
+        blk += sdiv;
+        if (n1 >= Ls) {
+            n1 -= Ls;
+            ++blk;
+        }
     }
 }
 
