@@ -128,18 +128,22 @@ TRAFFIC = {
                                                      "profile": "profiles/alt_fwd_dense_n1024_b32_f64.md"},
     ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7513e9, "sha": "21a5dbab89ebbe02",
                                                     "profile": "profiles/alt_fwd_dense_n1024_b1_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_gen_adj"): {"bytes_per_call": 22.977e9, "sha": "5dfee2315eda4eae",
+    ("idbf", 1024, 32, "f64", "k_gen_adj"): {"bytes_per_call": 22.957e9, "sha": "d66b6ea43ce1ce31",
                                               "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_gen_fwd_mfma"): {"bytes_per_call": 12.627e9, "sha": "5dfee2315eda4eae",
+    ("idbf", 1024, 32, "f64", "k_gen_fwd_mfma"): {"bytes_per_call": 12.621e9, "sha": "d66b6ea43ce1ce31",
                                                    "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_pack"): {"bytes_per_call": 4.403e9, "sha": "94cc9b348a22cb57",
-                                           "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_combine"): {"bytes_per_call": 8.659e9, "sha": "94cc9b348a22cb57",
-                                              "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_fold"): {"bytes_per_call": 9.046e9, "sha": "94cc9b348a22cb57",
-                                           "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_scatter"): {"bytes_per_call": 4.307e9, "sha": "94cc9b348a22cb57",
-                                              "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
+    ("idbf", 1024, 32, "f64", "k_pack"): {"bytes_per_call": 4.403e9, "sha": "a900dd7b71176d56",
+                                          "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
+    ("idbf", 1024, 32, "f64", "k_combine"): {"bytes_per_call": 8.659e9, "sha": "a900dd7b71176d56",
+                                             "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
+    ("idbf", 1024, 32, "f64", "k_fold"): {"bytes_per_call": 9.046e9, "sha": "a900dd7b71176d56",
+                                          "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
+    ("idbf", 1024, 32, "f64", "k_scatter"): {"bytes_per_call": 4.306e9, "sha": "a900dd7b71176d56",
+                                             "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
+    ("idbf", 1024, 32, "f64", "k_dft_synthesis"): {"bytes_per_call": 8.605e9, "sha": "e319ba3bdef466d2",
+                                                    "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
+    ("idbf", 1024, 32, "f64", "k_dft_analysis"): {"bytes_per_call": 8.605e9, "sha": "e319ba3bdef466d2",
+                                                   "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
 }
 
 # the sources each kernel family is built from
@@ -383,6 +387,67 @@ def n4096_full(S, inputs, timer, no_check):
         r["round_trip_rel_l2"] = rel_l2(bo.cpu().numpy(), beta_np)
     p.close()
     del beta, f, bo
+    torch.cuda.empty_cache()
+    return r
+
+
+def n4096_window(S, inputs, timer, no_check):
+    """N = 4096 (grid 8192 x 16383), 8 fields, FP64, fast form on one
+    64-order window (orders 4096..4159, the unit of per-GPU sharding) against
+    the plain form on the same orders, with the errors of the forward and the
+    weighted transposed ALT at three orders of fields 0 and 7 against the
+    oracle."""
+    import numpy as np
+    import torch
+    N, B, lo, hi = 4096, 8, 4096, 4159
+    M = 4 * N - 1
+    t0 = time.perf_counter()
+    p = S.Plan(N, B, dtype=torch.complex128, method="idbf", m_lo=lo, m_hi=hi)
+    tb = time.perf_counter() - t0
+    dense = S.Plan(N, B, dtype=torch.complex128, method="dense")
+    beta_np = inputs.make_beta(N, B, 3, dist="decay")
+    beta = torch.from_numpy(beta_np).cuda()
+    g = torch.zeros((B, 2 * N, M), dtype=torch.complex128, device="cuda")
+    bo = torch.zeros_like(beta)
+    st = p.stats()["program"]
+    r = {"orders": [lo, hi], "plan_build_s": tb, "stored_over_dense": st["stored_entries"] / st["dense_entries"],
+         "generated_over_dense": st["generated_entries"] / st["dense_entries"]}
+    for name, pl in (("fast", p), ("plain", dense)):
+        r[name + "_fwd_ms"] = 1e3 * timer.time(lambda: pl.alt(lo, hi, "fwd", beta, g), reps=3)
+        r[name + "_inv_ms"] = 1e3 * timer.time(lambda: pl.alt(lo, hi, "inv", g, bo), reps=3)
+    r["fast_over_plain_fwd"] = r["plain_fwd_ms"] / r["fast_fwd_ms"]
+    r["fast_over_plain_inv"] = r["plain_inv_ms"] / r["fast_inv_ms"]
+    if not no_check:
+        import oracle
+        k_of, m_of = inputs.layout(N)
+        absm = [lo, lo + 31, hi]
+        g.zero_()
+        p.alt(lo, hi, "fwd", beta, g)
+        gin = torch.zeros_like(g)
+        ef = ei = 0.0
+        for b in (0, B - 1):
+            ref = oracle.alt_forward_orders(N, beta_np[b], absm)
+            gb = g[b]
+            got = np.stack([np.stack([gb[:, a % M].cpu().numpy(), gb[:, (-a) % M].cpu().numpy()]) for a in absm])
+            ef = max(ef, rel_l2(got, ref))
+            for i, a in enumerate(absm):
+                gin[b, :, a % M] = torch.from_numpy(ref[i, 0])
+                gin[b, :, (-a) % M] = torch.from_numpy(ref[i, 1])
+            refs = ref
+            bref = oracle.alt_transpose_orders(N, refs, absm, weights=True)
+            bo.zero_()
+            p.alt(lo, hi, "inv", gin, bo)
+            bob = bo[b].cpu().numpy()
+            for i, a in enumerate(absm):
+                for sgn, m in enumerate((a, -a)):
+                    sel = np.nonzero(m_of == m)[0]
+                    ei = max(ei, rel_l2(bob[sel], bref[i, sgn, : 2 * N - a]))
+        r["fwd_sampled_orders_rel_l2"] = ef
+        r["inv_sampled_orders_rel_l2"] = ei
+        r["sampled_orders"] = absm
+    p.close()
+    dense.close()
+    del beta, g, bo
     torch.cuda.empty_cache()
     return r
 
@@ -895,6 +960,7 @@ def main():
         torch.cuda.empty_cache()
         if N == 1024 and args.dtype == "f64":
             det["n4096_plain_b8"] = n4096_full(S, inputs, timer, args.no_check)
+            det["n4096_window_b8"] = n4096_window(S, inputs, timer, args.no_check)
         out["details"] = det
 
     if not args.no_cpu_baseline:

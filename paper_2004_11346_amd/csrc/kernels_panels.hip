@@ -31,6 +31,10 @@ __device__ __forceinline__ int64_t d_coef_offset(int N, int m) {
 // values, 256 bytes per panel row).
 constexpr int FC = 8;
 constexpr int kIt = 16;  // tile values per thread: every tile holds 4096 values, 256 threads
+// LDS row pitch (doubles) of the pack / scatter tile that keeps a
+// half-wave's 64-bit accesses on distinct banks when it reads across the rows
+// of 128 complex values (258 doubles = 516 dwords, 4 banks apart)
+constexpr int kPS = 258;
 static_assert(FC * 2 * 256 == 256 * kIt, "pack / scatter tile: [FC][2][128][2]");
 static_assert(2 * 64 * 4 * FC == 256 * kIt, "pack / scatter panel side: 2 parities x 64 rows x 4 FC");
 static_assert(2 * 64 * 4 * FC == 256 * kIt, "combine / fold tile: [2][64][4 FC]");
@@ -42,7 +46,7 @@ static_assert(FC * 2 * 2 * 64 * 2 == 256 * kIt, "combine / fold grid side: FC x 
 template <typename B, typename T>
 __global__ __launch_bounds__(256) void k_pack(int N, int batch, int a_lo, const int64_t *__restrict__ x_off,
                                               const B *__restrict__ beta, T *__restrict__ X) {
-    __shared__ double tile[FC][2][128][2];  // field, sign, degree, re/im
+    __shared__ double tile[FC * 2 * kPS];  // (field, sign) rows of 128 complex values, pitch kPS
     const int a = a_lo + blockIdx.y;
     const int j0 = 64 * blockIdx.x;
     const int64_t xe = x_off[2 * a], xo = x_off[2 * a + 1];
@@ -69,7 +73,7 @@ __global__ __launch_bounds__(256) void k_pack(int N, int batch, int a_lo, const 
 #pragma unroll
         for (int i = 0; i < kIt; ++i) {
             const int e = tid + 256 * i;
-            tile[e >> 9][(e >> 8) & 1][(e & 255) >> 1][e & 1] = v[i];
+            tile[(e >> 8) * kPS + (e & 255)] = v[i];
         }
         __syncthreads();
         // write: rows of both parity tasks, 4 FC values each (contiguous runs)
@@ -81,7 +85,8 @@ __global__ __launch_bounds__(256) void k_pack(int N, int batch, int a_lo, const 
             const int jj = rem / (4 * FC), c = rem - jj * (4 * FC);
             const int fi = c >> 2, sg = (c >> 1) & 1, ri = c & 1;
             const int j = j0 + jj;
-            if (fi < nf && j < (par ? co : ce)) X[((par ? xo : xe) + j) * R + 4 * f0 + c] = (T)tile[fi][sg][2 * jj + par][ri];
+            if (fi < nf && j < (par ? co : ce))
+                X[((par ? xo : xe) + j) * R + 4 * f0 + c] = (T)tile[(2 * fi + sg) * kPS + 2 * (2 * jj + par) + ri];
         }
     }
 }
@@ -90,7 +95,7 @@ __global__ __launch_bounds__(256) void k_pack(int N, int batch, int a_lo, const 
 template <typename B, typename T>
 __global__ __launch_bounds__(256) void k_scatter(int N, int batch, int a_lo, const int64_t *__restrict__ x_off,
                                                  const T *__restrict__ X, B *__restrict__ beta) {
-    __shared__ double tile[FC][2][128][2];
+    __shared__ double tile[FC * 2 * kPS];
     const int a = a_lo + blockIdx.y;
     const int j0 = 64 * blockIdx.x;
     const int64_t xe = x_off[2 * a], xo = x_off[2 * a + 1];
@@ -117,7 +122,7 @@ __global__ __launch_bounds__(256) void k_scatter(int N, int batch, int a_lo, con
             const int e = tid + 256 * i;
             const int par = e / (64 * 4 * FC), rem = e - par * (64 * 4 * FC);
             const int jj = rem / (4 * FC), c = rem - jj * (4 * FC);
-            tile[c >> 2][(c >> 1) & 1][2 * jj + par][c & 1] = v[i];
+            tile[(c >> 1) * kPS + 2 * (2 * jj + par) + (c & 1)] = v[i];
         }
         __syncthreads();
 #pragma unroll
@@ -126,7 +131,7 @@ __global__ __launch_bounds__(256) void k_scatter(int N, int batch, int a_lo, con
             const int fi = e >> 9, sg = (e >> 8) & 1, q = e & 255;
             const int kk = k0 + (q >> 1), f = f0 + fi;
             if (f < batch && kk < nk && (sg == 0 || a > 0))
-                beta[2 * ((int64_t)f * 4 * N * N + (sg ? offn : offp) + kk) + (q & 1)] = (B)tile[fi][sg][q >> 1][q & 1];
+                beta[2 * ((int64_t)f * 4 * N * N + (sg ? offn : offp) + kk) + (q & 1)] = (B)tile[(e >> 8) * kPS + q];
         }
     }
 }
