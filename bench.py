@@ -45,12 +45,14 @@ def parse():
     ap.add_argument("--profile-dirs", default="fwd",
                     help="calls run by --profile-target (comma separated: fwd, inv = ALT only; sht_fwd, "
                          "sht_inv = full transforms)")
-    ap.add_argument("--workload", choices=["default", "n4096-orders", "uneven", "rank-study", "levels"],
+    ap.add_argument("--workload", choices=["default", "n4096-orders", "uneven", "rank-study", "levels",
+                                           "plan-build"],
                     default="default",
                     help="n4096-orders: N=4096, 8 fields, fast vs plain ALT on 64-order windows across the "
                          "order range; uneven: the grouped 64-transform workload; rank-study: ID sampling "
                          "(mock-Chebyshev vs random rows), adaptive rank r_k and tolerance sweeps at m = N; "
-                         "levels: staged vs fused butterfly levels at leaf 32/64/128")
+                         "levels: staged vs fused butterfly levels at leaf 32/64/128; plan-build: host "
+                         "construction of the fast-form plan of every order of --N, window by window")
     return ap.parse_args()
 
 
@@ -738,6 +740,46 @@ def level_schedules(args):
                                  "N": N, "batch": batch}, "results": out}))
 
 
+def plan_build(args):
+    """Plan construction of the fast form for every order of one N, window by
+    window (64 orders per plan, the share a GPU builds and holds when the
+    transform is sharded by order): host build time (the Legendre tables,
+    partition, IDs, low-rank factors, packing; all host threads) and the plan's
+    size, per window and in total.  Runs on the host only."""
+    import ctypes
+
+    from paper_2004_11346_amd import lib as L
+    lib = L.load()
+    N, W = args.N, 64
+    rows = []
+    tot = {"build_s": 0.0, "wall_s": 0.0, "stored_entries": 0, "generated_entries": 0, "dense_entries": 0,
+           "value_bytes_f64": 0}
+    for a0 in range(0, 2 * N, W):
+        lo, hi = a0, min(2 * N - 1, a0 + W - 1)
+        o = L.default_opts(m_lo=lo, m_hi=hi)
+        h = ctypes.c_void_p()
+        t0 = time.perf_counter()
+        L.check(lib.sht_host_plan_create(N, L.SHT_IDBF, ctypes.byref(o), ctypes.byref(h)), "host plan")
+        wall = time.perf_counter() - t0
+        n = lib.sht_host_plan_stats(h, None, 0)
+        buf = ctypes.create_string_buffer(n)
+        lib.sht_host_plan_stats(h, buf, n)
+        st = json.loads(buf.value.decode())
+        lib.sht_host_plan_destroy(h)
+        r = {"orders": [lo, hi], "build_s": st["build_seconds"], "wall_s": wall,
+             "stored_entries": st["stored_entries"], "generated_entries": st["generated_entries"],
+             "dense_entries": st["dense_entries"],
+             "value_bytes_f64": 8 * (st["fwd_values"] + st["adj_values"])}
+        for k in tot:
+            tot[k] += r.get(k, 0)
+        rows.append(r)
+        print(json.dumps({"window": r}), flush=True)
+    print(json.dumps({"metric": f"fast-form plan construction, N={N}, all orders in {len(rows)} windows of {W}",
+                      "n_gpus": 0, "data": "synthetic", "config": {"workload": f"plan build N={N}", "N": N,
+                                                                    "windows": len(rows)},
+                      "threads": os.cpu_count(), "totals": tot}), flush=True)
+
+
 def fp32_legs(S, inputs, timer, N, batch, beta_np, no_check):
     """FP32 plans at the same workload: plain form, fast form on the VALU and
     fast form on the BF16 matrix cores (split-BF16, three and six products),
@@ -801,6 +843,9 @@ def main():
         return
     if args.workload == "levels":
         level_schedules(args)
+        return
+    if args.workload == "plan-build":
+        plan_build(args)
         return
 
     import numpy as np
