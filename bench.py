@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--profile-dirs", default="fwd",
                     help="calls run by --profile-target (comma separated: fwd, inv = ALT only; sht_fwd, "
                          "sht_inv = full transforms)")
+    ap.add_argument("--orders", default=None,
+                    help="plan-build: order range LO:HI of the windows built (default: every order)")
     ap.add_argument("--workload", choices=["default", "n4096-orders", "uneven", "rank-study", "levels",
                                            "plan-build"],
                     default="default",
@@ -754,7 +756,10 @@ def plan_build(args):
     rows = []
     tot = {"build_s": 0.0, "wall_s": 0.0, "stored_entries": 0, "generated_entries": 0, "dense_entries": 0,
            "value_bytes_f64": 0}
-    for a0 in range(0, 2 * N, W):
+    first, last = 0, 2 * N - 1
+    if args.orders:
+        first, last = (int(v) for v in args.orders.split(":"))
+    for a0 in range(first - first % W, min(last, 2 * N - 1) + 1, W):
         lo, hi = a0, min(2 * N - 1, a0 + W - 1)
         o = L.default_opts(m_lo=lo, m_hi=hi)
         h = ctypes.c_void_p()
@@ -774,7 +779,8 @@ def plan_build(args):
             tot[k] += r.get(k, 0)
         rows.append(r)
         print(json.dumps({"window": r}), flush=True)
-    print(json.dumps({"metric": f"fast-form plan construction, N={N}, all orders in {len(rows)} windows of {W}",
+    print(json.dumps({"metric": f"fast-form plan construction, N={N}, orders {first}:{last} in {len(rows)} windows "
+                                f"of {W}",
                       "n_gpus": 0, "data": "synthetic", "config": {"workload": f"plan build N={N}", "N": N,
                                                                     "windows": len(rows)},
                       "threads": os.cpu_count(), "totals": tot}), flush=True)

@@ -251,7 +251,7 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
 
     LegendreTables lt;
     try {
-        build_legendre_tables(N, lt);
+        build_legendre_tables(N, lt, p->opts.m_lo, p->opts.m_hi);
     } catch (const std::bad_alloc &) {
         return SHT_ERR_OOM;
     }

@@ -52,7 +52,7 @@ int sht_host_plan_create(int N, int method, const sht_plan_opts *opts, sht_host_
             if (loaded) {
                 hp->data.N = N;
                 hp->data.opts = o;
-                build_legendre_tables(N, hp->data.lt);
+                build_legendre_tables(N, hp->data.lt, o.m_lo, o.m_hi);
             } else {
                 int rc = idbf::build_all(N, o, hp->data);
                 if (rc) {

@@ -749,7 +749,7 @@ int build_all(int N, const sht_plan_opts &opts_in, HostPlanData &out, const Lege
     if (lt && lt->N == N)
         out.lt = *lt;
     else
-        build_legendre_tables(N, out.lt);
+        build_legendre_tables(N, out.lt, opts.m_lo, opts.m_hi);
     const int ntask = 4 * N;  // 2N orders x 2 parities
     out.tasks.assign(ntask, Task());
     int nth = opts.threads > 0 ? opts.threads : (int)std::thread::hardware_concurrency();

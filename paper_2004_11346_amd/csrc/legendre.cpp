@@ -90,8 +90,11 @@ void gauss_legendre(int n, double *x, double *w) {
     (void)half;
 }
 
-void build_legendre_tables(int N, LegendreTables &t) {
+void build_legendre_tables(int N, LegendreTables &t, int m_lo, int m_hi) {
     const int n = 2 * N;
+    // orders whose recurrence coefficients are computed (the others stay 0)
+    m_lo = std::max(0, m_lo);
+    m_hi = m_hi < 0 ? n - 1 : std::min(m_hi, n - 1);
     t.N = N;
     std::vector<double> x(n), w(n);
     gauss_legendre(n, x.data(), w.data());
@@ -111,7 +114,7 @@ void build_legendre_tables(int N, LegendreTables &t) {
         ld s = sqrtl((1.0L - xv) * (1.0L + xv));
         ld mu = 1.0L / sqrtl(2.0L);
         int e = 0;
-        for (int m = 0; m < n; ++m) {
+        for (int m = 0; m <= m_hi; ++m) {
             if (m > 0) mu *= fac[m] * s;
             int ee = 0;
             mu = frexpl(mu, &ee);
@@ -122,7 +125,8 @@ void build_legendre_tables(int N, LegendreTables &t) {
     });
     // recurrence coefficients
     t.coef.assign((size_t)2 * tri_offset(N, n), 0.0);
-    parallel_for(n, [&](int m) {
+    parallel_for(m_hi - m_lo + 1, [&](int i) {
+        const int m = m_lo + i;
         double *c = &t.coef[2 * tri_offset(N, m)];
         if (m + 1 < n) {
             c[2] = (double)sqrtl((ld)(2 * m + 3));
@@ -142,7 +146,8 @@ void build_legendre_tables(int N, LegendreTables &t) {
     //   gamma_k = -a_k a_{k-1} b_{k-1} b_{k-2};
     // b_{m+1} = 0 removes the terms that would need a_m or b_m
     t.coef2.assign((size_t)3 * tri_offset(N, n), 0.0);
-    parallel_for(n, [&](int m) {
+    parallel_for(m_hi - m_lo + 1, [&](int i) {
+        const int m = m_lo + i;
         double *c2 = &t.coef2[3 * tri_offset(N, m)];
         auto A = [&](int k) -> ld {
             if (k == m + 1) return sqrtl((ld)(2 * m + 3));

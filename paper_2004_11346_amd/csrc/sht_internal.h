@@ -70,7 +70,9 @@ struct LegendreTables {
     std::vector<double> coef2;
 };
 
-void build_legendre_tables(int N, LegendreTables &t);
+// Orders outside [m_lo, m_hi] (m_hi < 0: up to 2N - 1) get no recurrence
+// coefficients (zeros): plans restricted to an order range never read them.
+void build_legendre_tables(int N, LegendreTables &t, int m_lo = 0, int m_hi = -1);
 
 // Dense half-grid matrix of order a and parity p: out[r * cols + j] =
 // Pbar_{a + p + 2j}^{a}(xh[r]).  Uses the same scaled recurrence.
