@@ -47,13 +47,14 @@ def parse():
                          "sht_inv = full transforms)")
     ap.add_argument("--orders", default=None,
                     help="plan-build: order range LO:HI of the windows built (default: every order)")
-    ap.add_argument("--workload", choices=["default", "n4096-orders", "uneven", "rank-study", "levels",
-                                           "plan-build"],
+    ap.add_argument("--workload", choices=["default", "n4096-orders", "n4096-every-order", "uneven", "rank-study",
+                                           "levels", "plan-build"],
                     default="default",
                     help="n4096-orders: N=4096, 8 fields, fast vs plain ALT on 64-order windows across the "
                          "order range; uneven: the grouped 64-transform workload; rank-study: ID sampling "
                          "(mock-Chebyshev vs random rows), adaptive rank r_k and tolerance sweeps at m = N; "
-                         "levels: staged vs fused butterfly levels at leaf 32/64/128; plan-build: host "
+                         "levels: staged vs fused butterfly levels at leaf 32/64/128; n4096-every-order: the "
+                         "fast ALT of every order at N=4096 in 16 shares vs the plain form; plan-build: host "
                          "construction of the fast-form plan of every order of --N, window by window")
     return ap.parse_args()
 
@@ -514,6 +515,123 @@ def n4096_orders(args):
                       "fp32_windows": fp32}), flush=True)
 
 
+def n4096_every_order(args):
+    """N = 4096 (grid 8192 x 16383), 8 fields, FP64 (or FP32 with --dtype f32:
+    the fast form in split-BF16 with six products), every order: the fast ALT
+    built and applied share by share (16 plans of 512 orders, the shares a
+    sharded run gives each GPU: the full FP64 plan, 269 GB of factors, does not
+    fit one GPU beside its grids), against the plain form (one plan of all
+    orders) on the same data.  The phi DFTs, timed inside the plain form's
+    SHT, complete both SHTs.  Errors against the oracle at two orders of every
+    share, fields 0 and 7, forward and weighted transpose."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2004_11346_amd.sht as S
+    from paper_2004_11346_amd import inputs
+    torch.cuda.init()
+    N, B, W = 4096, 8, 512
+    M = 4 * N - 1
+    timer = Timer()
+    k_of, m_of = inputs.layout(N)
+    f32 = args.dtype == "f32"
+    cdt = torch.complex64 if f32 else torch.complex128
+    extra = {"f32_mode": 2} if f32 else {}  # FP32: split-BF16 with six products
+    beta_np = inputs.make_beta(N, B, 3, dist="decay")
+    if f32:
+        beta_np = beta_np.astype(np.complex64).astype(np.complex128)
+    beta = torch.from_numpy(beta_np).to(cdt).cuda()
+    g = torch.zeros((B, 2 * N, M), dtype=cdt, device="cuda")
+    bo = torch.zeros_like(beta)
+    t0 = time.perf_counter()
+    dense = S.Plan(N, B, dtype=cdt, method="dense")
+    out = {"plain": {"plan_build_s": time.perf_counter() - t0}}
+    out["plain"]["alt_fwd_ms"] = 1e3 * timer.time(lambda: dense.alt(0, 2 * N - 1, "fwd", beta, g), reps=2)
+    out["plain"]["alt_inv_ms"] = 1e3 * timer.time(lambda: dense.alt(0, 2 * N - 1, "inv", g, bo), reps=2)
+    f = dense.forward(beta)
+    dense.profile(True)
+    for _ in range(2):
+        dense.forward(beta, out=f)
+        dense.inverse(f, out=bo)
+    torch.cuda.synchronize()
+    rep = dense.profile_report()
+    dense.profile(False)
+    dft_ms = sum(v["total_ms"] for k, v in rep.items() if k.startswith("k_dft")) / 2
+    out["plain"]["sht_fwd_ms"] = 1e3 * timer.time(lambda: dense.forward(beta, out=f), reps=2)
+    out["plain"]["sht_inv_ms"] = 1e3 * timer.time(lambda: dense.inverse(f, out=bo), reps=2)
+    out["dft_ms_fwd_plus_inv"] = dft_ms
+    print(json.dumps({"plain": out["plain"], "dft_ms_fwd_plus_inv": dft_ms}), flush=True)
+    del f
+    dense.close()
+    torch.cuda.empty_cache()
+    shares = []
+    for lo in range(0, 2 * N, W):
+        hi = lo + W - 1
+        t0 = time.perf_counter()
+        p = S.Plan(N, B, dtype=cdt, method="idbf", m_lo=lo, m_hi=hi, **extra)
+        r = {"orders": [lo, hi], "plan_build_s": time.perf_counter() - t0}
+        st = p.stats()["program"]
+        r["stored_entries"] = st["stored_entries"]
+        r["generated_entries"] = st["generated_entries"]
+        r["fwd_ms"] = 1e3 * timer.time(lambda: p.alt(lo, hi, "fwd", beta, g), reps=2)
+        r["inv_ms"] = 1e3 * timer.time(lambda: p.alt(lo, hi, "inv", g, bo), reps=2)
+        if not args.no_check:
+            absm = [lo + 1, hi - 3]
+            p.alt(lo, hi, "fwd", beta, g)
+            gs = {b: g[b] for b in (0, B - 1)}
+            ef = ei = 0.0
+            refs = {}
+            for b in (0, B - 1):
+                ref = oracle.alt_forward_orders(N, beta_np[b], absm)
+                if f32:  # the transposed input as the FP32 plan receives it
+                    ref = ref.astype(np.complex64).astype(np.complex128)
+                refs[b] = ref
+                got = np.stack([np.stack([gs[b][:, a % M].cpu().numpy(), gs[b][:, (-a) % M].cpu().numpy()])
+                                for a in absm]).astype(np.complex128)
+                ef = max(ef, rel_l2(got, ref))
+            g.zero_()
+            for b, ref in refs.items():
+                for i, a in enumerate(absm):
+                    g[b, :, a % M] = torch.from_numpy(ref[i, 0]).to(cdt)
+                    g[b, :, (-a) % M] = torch.from_numpy(ref[i, 1]).to(cdt)
+            p.alt(lo, hi, "inv", g, bo)
+            for b, ref in refs.items():
+                bref = oracle.alt_transpose_orders(N, ref, absm, weights=True)
+                bob = bo[b].cpu().numpy().astype(np.complex128)
+                for i, a in enumerate(absm):
+                    for sg, m in enumerate((a, -a)):
+                        sel = np.nonzero(m_of == m)[0]
+                        ei = max(ei, rel_l2(bob[sel], bref[i, sg, : 2 * N - a]))
+            r["fwd_rel_l2"] = ef
+            r["inv_rel_l2"] = ei
+        shares.append(r)
+        print(json.dumps({"share": r}), flush=True)
+        p.close()
+        torch.cuda.empty_cache()
+    fast = {k: sum(r[k] for r in shares) for k in ("plan_build_s", "fwd_ms", "inv_ms", "stored_entries",
+                                                     "generated_entries")}
+    if not args.no_check:
+        fast["fwd_rel_l2_max"] = max(r["fwd_rel_l2"] for r in shares)
+        fast["inv_rel_l2_max"] = max(r["inv_rel_l2"] for r in shares)
+    coefs = B * 4 * N * N
+    res = {"metric": f"ALT Gcoef/s and SHT/s at N=4096, every order, fast (16 shares) vs plain, {args.dtype}, 8 fields",
+           "n_gpus": 1, "data": "synthetic", "dtype": args.dtype,
+           "fast_form": "split-BF16, six products" if f32 else "FP64",
+           "config": {"workload": "ALT/SHT N=4096 (grid 8192x16383), 8 fields, every order", "N": N, "batch": B,
+                      "shares": len(shares)},
+           "fast": fast, "plain": out["plain"], "dft_ms_fwd_plus_inv": dft_ms,
+           "alt_gcoef_per_s": {"fast_fwd": coefs / fast["fwd_ms"] / 1e6, "fast_inv": coefs / fast["inv_ms"] / 1e6,
+                               "plain_fwd": coefs / out["plain"]["alt_fwd_ms"] / 1e6,
+                               "plain_inv": coefs / out["plain"]["alt_inv_ms"] / 1e6},
+           "fast_over_plain_alt": {"fwd": out["plain"]["alt_fwd_ms"] / fast["fwd_ms"],
+                                   "inv": out["plain"]["alt_inv_ms"] / fast["inv_ms"]},
+           "sht_per_s": {"fast": 2 * B / ((fast["fwd_ms"] + fast["inv_ms"] + dft_ms) / 1e3),
+                         "plain": 2 * B / ((out["plain"]["sht_fwd_ms"] + out["plain"]["sht_inv_ms"]) / 1e3)},
+           "shares": shares}
+    print(json.dumps(res), flush=True)
+
+
 def n4096_fp32_windows(S, N, B, W):
     """FP32 fast-form plans on two 64-order windows at N = 4096 (8 fields):
     split-BF16 with six products and FP32 storage on the FP64 matrix cores,
@@ -840,6 +958,9 @@ def main():
         return
     if args.workload == "n4096-orders":
         n4096_orders(args)
+        return
+    if args.workload == "n4096-every-order":
+        n4096_every_order(args)
         return
     if args.workload == "uneven":
         uneven(args)
