@@ -11,8 +11,9 @@
 //    sub-rows of a four-step pass): a pass of radix R over blocks of length L
 //    splits each block into R interleaved sub-blocks of length L/R with
 //      y[n1 + (L/R) k2] = w_L^{n1 k2} sum_{n2} x[n1 + (L/R) n2] w_R^{n2 k2};
-//    radices up to 13 run as register butterflies, larger primes as R-term
-//    sums; after the passes every segment is in digit-reversed order;
+//    radices up to 13 (and 9 for a pair of 3s) run as register butterflies,
+//    larger primes as R-term sums; after the passes every segment is in
+//    digit-reversed order;
 //  * global loads and stores issued in unrolled groups, so that a thread's
 //    accesses are in flight together.
 #pragma once
@@ -73,11 +74,14 @@ __device__ __forceinline__ double uniform(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// cos and sin of 2 pi q / R for q = 1 .. (R - 1) / 2 (odd R); the same for
-// every lane, so they live in scalar registers
+// cos and sin of 2 pi q / R for q = 0 .. (R - 1) / 2 (odd R); the same for
+// every lane, so they live in scalar registers.  q = 0 is used by composite
+// R, where j k = 0 mod R for some j, k > 0 (j = k = 3 for R = 9).
 template <int R>
 __device__ __forceinline__ void roots(const double2 *t, int Mt, double (&c)[(R - 1) / 2 + 1],
                                       double (&sn)[(R - 1) / 2 + 1]) {
+    c[0] = 1.0;
+    sn[0] = 0.0;
 #pragma unroll
     for (int q = 1; q <= (R - 1) / 2; ++q) {
         const double2 w = twd(t, 2 * q * (Mt / R), 1.0);
@@ -254,6 +258,7 @@ __device__ __forceinline__ void run_passes(typename V2<C>::t *buf, int total, co
             case 3: pass_reg<C, 3>(buf, total, L, t, Mt, sgn); break;
             case 5: pass_reg<C, 5>(buf, total, L, t, Mt, sgn); break;
             case 7: pass_reg<C, 7>(buf, total, L, t, Mt, sgn); break;
+            case 9: pass_reg<C, 9>(buf, total, L, t, Mt, sgn); break;
             case 11: pass_reg<C, 11>(buf, total, L, t, Mt, sgn); break;
             case 13: pass_reg<C, 13>(buf, total, L, t, Mt, sgn); break;
             default:
@@ -351,6 +356,7 @@ __device__ __forceinline__ void run_passes_inv(typename V2<C>::t *buf, int total
             case 3: pass_reg_inv<C, 3>(buf, total, L, t, Mt, sgn); break;
             case 5: pass_reg_inv<C, 5>(buf, total, L, t, Mt, sgn); break;
             case 7: pass_reg_inv<C, 7>(buf, total, L, t, Mt, sgn); break;
+            case 9: pass_reg_inv<C, 9>(buf, total, L, t, Mt, sgn); break;
             case 11: pass_reg_inv<C, 11>(buf, total, L, t, Mt, sgn); break;
             case 13: pass_reg_inv<C, 13>(buf, total, L, t, Mt, sgn); break;
             default:

@@ -769,15 +769,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(CBP == 1 ? 1
                 gen_2step(s_c + 3 * 15, x2, p0, p1, ex, sc);
                 tile[15 * PAD + lane] = p1 * sc;
             } else {
+                // a group the segment covers in part: the column test is the
+                // same for every lane, and, as in gen_run, the rescale test
+                // runs once after the group's steps
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int t = gc0 + j - sg.c0;  // column index in the segment
                     double v = 0.0;
                     if (t >= 0 && t < sg.ncol) {
-                        if (t > 0) gen_2step(s_c + 3 * t, x2, p0, p1, ex, sc);
+                        if (t > 0) {
+                            const double *c = s_c + 3 * t;
+                            const double p2 = fma(c[0], x2, c[1]) * p1 + c[2] * p0;
+                            p0 = p1;
+                            p1 = p2;
+                        }
                         v = p1 * sc;
                     }
                     tile[j * PAD + lane] = v;
+                }
+                if (fabs(p1) > 0x1p200 || fabs(p0) > 0x1p200) {
+                    p0 *= 0x1p-200;
+                    p1 *= 0x1p-200;
+                    ex += 200;
+                    sc = scale_of(ex);
                 }
             }
             __syncthreads();

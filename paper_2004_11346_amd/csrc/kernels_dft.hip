@@ -447,7 +447,19 @@ std::vector<int> prime_factors(int m) {
 // radices (largest first), block lengths and the slot of every output
 // frequency after the DIF passes of length L
 void passes_of(int L, std::vector<int> &radix, std::vector<int> &blen, std::vector<int> &src_pos) {
-    radix = prime_factors(L);
+    // prime factors, with pairs of 3 merged into radix-9 passes (one pass
+    // and one LDS round trip fewer, and fewer products per point than two
+    // radix-3 passes)
+    radix.clear();
+    int threes = 0;
+    for (int p : prime_factors(L)) {
+        if (p == 3)
+            ++threes;
+        else
+            radix.push_back(p);
+    }
+    for (; threes >= 2; threes -= 2) radix.push_back(9);
+    if (threes) radix.push_back(3);
     std::sort(radix.rbegin(), radix.rend());
     blen.clear();
     int len = L;
