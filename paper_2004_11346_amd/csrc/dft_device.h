@@ -141,7 +141,8 @@ __device__ __forceinline__ void dft_small(typename V2<C>::t (&x)[R], const doubl
 // outputs k and R - k are stored as soon as they are formed
 // (w^{R-k} = w^R conj(w^k)), which keeps the live registers to the sums and
 // differences of the inputs.
-template <typename C, int R>
+// BD > 0: the block size as a compile-time constant (otherwise blockDim.x)
+template <typename C, int R, int BD = 0>
 __device__ __forceinline__ void pass_reg(typename V2<C>::t *buf, int total, int L, const double2 *t, int Mt,
                                          C sgn) {
     typedef typename V2<C>::t c2;
@@ -152,7 +153,7 @@ __device__ __forceinline__ void pass_reg(typename V2<C>::t *buf, int total, int 
     const int unitL = 2 * (Mt / L);
     const int nb = total / R;
     // butterfly b = blk Ls + n1, stepped by the block size without divisions
-    const int bd = blockDim.x, sdiv = bd / Ls, smod = bd - sdiv * Ls;
+    const int bd = BD > 0 ? BD : (int)blockDim.x, sdiv = bd / Ls, smod = bd - sdiv * Ls;
     int blk = (int)threadIdx.x / Ls, n1 = (int)threadIdx.x - blk * Ls;
     for (int b = threadIdx.x; b < nb; b += bd) {
         const int base = blk * L + n1;
@@ -264,6 +265,34 @@ __device__ __forceinline__ void run_passes(typename V2<C>::t *buf, int total, co
             default:
                 if constexpr (MAXO > 0) pass_sum<C, MAXO>(buf, total, R, L, t, Mt, sgn);
                 break;
+        }
+        __syncthreads();
+    }
+}
+
+// passes p0 .. p1 - 1 of `ps`, register butterflies of radix at most MAXR
+// only (a smaller MAXR keeps the larger butterflies, and their registers, out
+// of the code), BD threads per block; every pass ends with a barrier
+template <typename C, int MAXR, int BD>
+__device__ __forceinline__ void run_pass_range(typename V2<C>::t *buf, int total, const Passes &ps, int p0, int p1,
+                                               const double2 *t, int Mt, C sgn) {
+    for (int p = p0; p < p1; ++p) {
+        const int R = ps.R[p], L = ps.L[p];
+        switch (R) {
+            case 2: pass_reg<C, 2, BD>(buf, total, L, t, Mt, sgn); break;
+            case 3: pass_reg<C, 3, BD>(buf, total, L, t, Mt, sgn); break;
+            case 5: pass_reg<C, 5, BD>(buf, total, L, t, Mt, sgn); break;
+            case 7: pass_reg<C, 7, BD>(buf, total, L, t, Mt, sgn); break;
+            case 9:
+                if constexpr (MAXR >= 9) pass_reg<C, 9, BD>(buf, total, L, t, Mt, sgn);
+                break;
+            case 11:
+                if constexpr (MAXR >= 11) pass_reg<C, 11, BD>(buf, total, L, t, Mt, sgn);
+                break;
+            case 13:
+                if constexpr (MAXR >= 13) pass_reg<C, 13, BD>(buf, total, L, t, Mt, sgn);
+                break;
+            default: break;
         }
         __syncthreads();
     }

@@ -81,6 +81,87 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MAXO =
     dft_row<C, T, MAXO, IO>(N, M, ps, tab, src_pos, mode, scale, r.src, r.src2, r.dst, r.dst2, buf);
 }
 
+// Rows in LDS, persistent: workgroup w takes rows w, w + gridDim.x, ... of
+// the flattened (field, l) row list.  Rows of at most kUnroll * kThreads
+// points whose first pass has a register butterfly of radix up to 13 and
+// whose other passes radices up to 9.  Every thread loads its kUnroll points
+// of the next row into registers after the first pass of the current row, so
+// the loads are in flight during the remaining passes and the stores (the
+// larger butterflies stay out of that stretch, which keeps the registers
+// within four waves per SIMD); the output slots of its columns, the same for
+// every row, are read once.  Same arithmetic as k_dft_rows.
+template <typename C, typename T, int IO>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_dft_rows_pipe(
+    int N, int M, Passes ps, const double *__restrict__ tab, const int *__restrict__ src_pos, int mode, C scale,
+    const T *in, T *out, int nreal, int nrows) {
+    typedef typename V2<C>::t c2;
+    extern __shared__ unsigned char smem_raw[];
+    c2 *buf = reinterpret_cast<c2 *>(smem_raw);
+    double2 *t = reinterpret_cast<double2 *>(buf + M + (M & 1));
+    const int twoM = 2 * M, n = 2 * N;
+    const C sgn = mode == 0 ? (C)1 : (C)-1;
+    constexpr int bd = kThreads;  // the launch's block size
+    // column j of this thread, clamped so that every load is in bounds and
+    // unconditional (a clamped column is loaded and never stored)
+    int sp[kUnroll];
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j) sp[j] = src_pos[min((int)threadIdx.x + j * bd, M - 1)];
+    load_tab(tab, M, t);
+    c2 v[kUnroll];
+    int row = blockIdx.x;
+    {
+        const RowPtrs<T, IO> r(N, M, row / n, row % n, nreal, in, out);
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) v[j] = ld_in<C, T, IO>(r.src, r.src2, min((int)threadIdx.x + j * bd, M - 1));
+    }
+    __syncthreads();  // table
+    for (; row < nrows; row += gridDim.x) {
+        // the thread index as a value the compiler cannot follow across
+        // rows: the per-column phase-table addresses are recomputed for each
+        // row instead of being hoisted out of the loop (and spilled)
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int c = tid + j * bd;
+            if (c >= M) continue;
+            c2 x = v[j];
+            if (mode == 0) {
+                const int m = signed_order(c, N, M);
+                x = cmul<C>(x, tw<C>(t, m < 0 ? m + twoM : m, (C)1));
+            }
+            buf[c] = x;
+        }
+        __syncthreads();
+        run_pass_range<C, 13, kThreads>(buf, M, ps, 0, 1, t, M, sgn);
+        {
+            // the last row of a workgroup loads its own row again (unused)
+            const int next = row + (int)gridDim.x < nrows ? row + (int)gridDim.x : row;
+            const RowPtrs<T, IO> r(N, M, next / n, next % n, nreal, in, out);
+#pragma unroll
+            for (int j = 0; j < kUnroll; ++j) v[j] = ld_in<C, T, IO>(r.src, r.src2, min(tid + j * bd, M - 1));
+        }
+        run_pass_range<C, 9, kThreads>(buf, M, ps, 1, ps.n, t, M, sgn);
+        const RowPtrs<T, IO> r(N, M, row / n, row % n, nreal, in, out);
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int c = tid + j * bd;
+            if (c >= M) continue;
+            c2 x = buf[sp[j]];
+            if (mode == 1) {
+                const int m = signed_order(c, N, M);
+                int q = m < 0 ? -m : twoM - m;  // e^{-i pi m / M}
+                if (q == twoM) q = 0;
+                x = cmul<C>(x, tw<C>(t, q, (C)1));
+                x.x *= scale;
+                x.y *= scale;
+            }
+            st_out<C, T, IO>(r.dst, r.dst2, c, x);
+        }
+        __syncthreads();  // every read of buf done before the next row lands
+    }
+}
+
 // prime M by Rader's convolution
 template <typename C, typename T, int IO>
 __global__ __launch_bounds__(kThreads) void k_dft_rader(int N, int M, Passes pc, const double *__restrict__ tab,
@@ -343,9 +424,23 @@ int max_radix(int n, const int *R) {
     return m;
 }
 
+// compute units of the current device
+int cu_count() {
+    static int cus[64] = {0};
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) d = 0;
+    if (cus[d] <= 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess || n <= 0) n = 256;
+        cus[d] = n;
+    }
+    return cus[d];
+}
+
 template <typename C, int IO>
 hipError_t set_attrs_io() {
-    const void *fns[] = {(const void *)&k_dft_rows<C, C, 0, IO>,  (const void *)&k_dft_rows<C, C, 8, IO>,
+    const void *fns[] = {(const void *)&k_dft_rows_pipe<C, C, IO>,
+                         (const void *)&k_dft_rows<C, C, 0, IO>,  (const void *)&k_dft_rows<C, C, 8, IO>,
                          (const void *)&k_dft_rows<C, C, 16, IO>, (const void *)&k_dft_rows<C, C, 32, IO>,
                          (const void *)&k_dft_rader<C, C, IO>,    (const void *)&k_dft_4s_a<C, C, IO>,
                          (const void *)&k_dft_4s_b<C, C, IO>};
@@ -390,7 +485,16 @@ hipError_t launch(const DftPlan &p, int batch, int mode, double scale, const voi
 #define SHT_ROWS(MX)                                                                                        \
     hipLaunchKernelGGL((k_dft_rows<C, T, MX, IO>), grid, dim3(kThreads), lds, s, p.N, M, ps, tab, p.src_pos, \
                        mode, (C)scale, (const T *)in, (T *)out, nreal)
-        if (maxr <= 13)
+        const int nrows = 2 * p.N * batch;
+        if (nrows <= 0) return hipSuccess;
+        bool tail9 = p.nrad >= 1;
+        for (int i = 1; i < p.nrad; ++i) tail9 = tail9 && p.radix[i] <= 9;
+        if (maxr <= 13 && tail9 && M <= kUnroll * kThreads) {
+            // two workgroups per CU (LDS of two FP64 rows of up to 4096 points)
+            const int wg = std::min(nrows, 2 * cu_count());
+            hipLaunchKernelGGL((k_dft_rows_pipe<C, T, IO>), dim3(wg), dim3(kThreads), lds, s, p.N, M, ps, tab,
+                               p.src_pos, mode, (C)scale, (const T *)in, (T *)out, nreal, nrows);
+        } else if (maxr <= 13)
             SHT_ROWS(0);
         else if (M <= 8 * kThreads)
             SHT_ROWS(8);
