@@ -7,9 +7,12 @@
 // order side (with the signed order m), leaving a plain length-M DFT.
 //
 // Three schedules, chosen per M and element type when the plan is built:
-//  * rows in LDS: one workgroup per row, the row held once in LDS, mixed-radix
-//    passes over the prime factors of M (largest first), the digit-reversed
-//    result written back through a position table;
+//  * rows in LDS: the row held once in LDS, mixed-radix passes over the prime
+//    factors of M (largest first, pairs of 3 as radix 9), the digit-reversed
+//    result written back through a position table; rows of at most 4096
+//    points with small radices run persistently, two workgroups per CU, each
+//    loading the next row into registers during the current row's passes,
+//    the others one workgroup per row;
 //  * Rader (prime M): with a primitive root g of M, the outputs X_k, k != 0,
 //    are x_0 plus a cyclic convolution of length M - 1 of the inputs taken in
 //    the order x_{g^q} with the phases w^{g^{-q}}; the convolution runs in LDS
