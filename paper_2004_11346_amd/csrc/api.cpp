@@ -44,6 +44,10 @@ struct sht_plan {
     double *d_tab = nullptr, *d_ctab = nullptr, *d_bspec = nullptr;
     float *d_tabf = nullptr, *d_ctabf = nullptr, *d_bspecf = nullptr;
     int *d_src_pos = nullptr, *d_src_pos2 = nullptr, *d_inslot = nullptr, *d_outslot = nullptr;
+    // Rader last passes of the two pass lists
+    double *d_rl_ctab[2] = {nullptr, nullptr}, *d_rl_bspec[2] = {nullptr, nullptr};
+    float *d_rl_bspecf[2] = {nullptr, nullptr};
+    int *d_rl_inslot[2] = {nullptr, nullptr}, *d_rl_outslot[2] = {nullptr, nullptr};
     void *d_dft_scr = nullptr;
     dev::DenseTables dense;
     dev::DftPlan dft;
@@ -110,6 +114,10 @@ sht_plan::~sht_plan() {
                     (void *)d_bspecf, (void *)d_src_pos, (void *)d_src_pos2, (void *)d_inslot,
                     (void *)d_outslot, d_dft_scr})
         dfree(q);
+    for (int i = 0; i < 2; ++i)
+        for (void *q : {(void *)d_rl_ctab[i], (void *)d_rl_bspec[i], (void *)d_rl_bspecf[i], (void *)d_rl_inslot[i],
+                        (void *)d_rl_outslot[i]})
+            dfree(q);
     dfree(d_g);
     dfree(d_bz);
     dfree(d_X);
@@ -331,6 +339,26 @@ int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts
         d.outslot = p->d_outslot;
         d.bspec = p->d_bspec;
         d.bspecf = p->d_bspecf;
+        for (int i = 0; i < 2; ++i) {
+            if (!dh.rl_R[i]) continue;
+            if (dh.rl_radix[i].size() > 24) return SHT_ERR_UNSUPPORTED;
+            d.rl_R[i] = dh.rl_R[i];
+            d.rl_nrad[i] = (int)dh.rl_radix[i].size();
+            for (int q = 0; q < d.rl_nrad[i]; ++q) {
+                d.rl_radix[i][q] = dh.rl_radix[i][q];
+                d.rl_blen[i][q] = dh.rl_blen[i][q];
+            }
+            if ((rc = upload(dh.rl_ctab[i], &p->d_rl_ctab[i], "upload DFT table"))) return rc;
+            if ((rc = upload(dh.rl_bspec[i], &p->d_rl_bspec[i], "upload DFT spectrum"))) return rc;
+            if ((rc = upload(dh.rl_bspecf[i], &p->d_rl_bspecf[i], "upload DFT spectrum"))) return rc;
+            if ((rc = upload(dh.rl_inslot[i], &p->d_rl_inslot[i], "upload DFT slots"))) return rc;
+            if ((rc = upload(dh.rl_outslot[i], &p->d_rl_outslot[i], "upload DFT slots"))) return rc;
+            d.rl_ctab[i] = p->d_rl_ctab[i];
+            d.rl_bspec[i] = p->d_rl_bspec[i];
+            d.rl_bspecf[i] = p->d_rl_bspecf[i];
+            d.rl_inslot[i] = p->d_rl_inslot[i];
+            d.rl_outslot[i] = p->d_rl_outslot[i];
+        }
         if (dh.kind == dev::kDftFourStep) {
             HIP_TRY(hipMalloc(&p->d_dft_scr, 2 * elt_size(dtype) * (size_t)batch * 2 * N * p->M),
                     "DFT intermediate rows");
@@ -430,9 +458,13 @@ int sht_plan_nodes(const sht_plan_t *p, double *x, double *w) {
 int sht_plan_stats(const sht_plan_t *p, char *json, size_t cap) {
     if (!p) return SHT_ERR_INVALID_ARG;
     std::ostringstream os;
+    static const char *kinds[] = {"none", "rows", "rader", "four_step"};
+    const int kind = p->dft.kind + 1;  // kDftNone = -1
     os << "{\"N\":" << p->N << ",\"batch\":" << p->batch << ",\"dtype\":\""
        << (p->dtype == SHT_F64 ? "f64" : "f32") << "\",\"method\":\""
-       << (p->method == SHT_DENSE ? "dense" : "idbf") << "\",\"build_seconds\":" << p->build_seconds;
+       << (p->method == SHT_DENSE ? "dense" : "idbf") << "\",\"build_seconds\":" << p->build_seconds
+       << ",\"dft\":\"" << (kind >= 0 && kind <= 3 ? kinds[kind] : "?") << "\",\"dft_rader_last\":["
+       << p->dft.rl_R[0] << "," << p->dft.rl_R[1] << "]";
     if (p->method == SHT_IDBF && !p->stats.empty()) os << ",\"program\":" << p->stats;
     os << "}";
     std::string s = os.str();

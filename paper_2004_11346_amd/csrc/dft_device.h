@@ -247,12 +247,13 @@ __device__ __forceinline__ void pass_sum(typename V2<C>::t *buf, int total, int 
     }
 }
 
-// all passes of `ps` over `total` elements (segments of length ps.L[0]);
-// ends with a barrier
+// the first npass passes of `ps` (all of them when npass < 0) over `total`
+// elements (segments of length ps.L[0]); ends with a barrier
 template <typename C, int MAXO>
 __device__ __forceinline__ void run_passes(typename V2<C>::t *buf, int total, const Passes &ps, const double2 *t,
-                                           int Mt, C sgn) {
-    for (int p = 0; p < ps.n; ++p) {
+                                           int Mt, C sgn, int npass = -1) {
+    const int np = npass < 0 ? ps.n : npass;
+    for (int p = 0; p < np; ++p) {
         const int R = ps.R[p], L = ps.L[p];
         switch (R) {
             case 2: pass_reg<C, 2>(buf, total, L, t, Mt, sgn); break;
@@ -396,6 +397,73 @@ __device__ __forceinline__ void run_passes_inv(typename V2<C>::t *buf, int total
     }
 }
 
+// Tables of a last pass of prime radix R > 13 taken by Rader's convolution
+// (R - 1 a product of radices up to 13).  After the other passes the points
+// of every block of R contiguous elements want a plain length-R DFT (the last
+// pass has no twiddles); with a primitive root g of R, output g^{-p} is
+// x_0 plus the cyclic convolution of a_q = x_{g^q} with b_q = w^{g^{-q}}.
+//   inslot[n]: slot q of input n >= 1 (g^q = n); outslot[k]: slot of the
+//   convolution that output k >= 1 reads; pc: the passes of length R - 1;
+//   bspec: [2][R - 1] complex spectra of b (sign +1, then -1) under the
+//   sign -1 transform, divided by R - 1, in the passes' digit-reversed slots;
+//   ctab: phase table of base R - 1 (global).
+struct RaderLast {
+    int R;
+    Passes pc;
+    const double *ctab;
+    const int *inslot, *outslot;
+    const double *bspec;
+    const float *bspecf;
+};
+
+// LDS bytes past the row buffer for a Rader last pass over `total` points:
+// its phase table, the convolution buffer and two values per block
+__host__ __device__ inline size_t rader_last_lds(int total, int R, size_t elt) {
+    const int nblk = total / R;
+    return 16 * (size_t)tab_entries(R - 1) + elt * ((size_t)nblk * (R - 1) + 2 * (size_t)nblk);
+}
+
+// The last pass of radix rl.R over `total` points of buf (blocks of R
+// contiguous points, the transform of sign sgn) by Rader's convolution:
+// gather into cbuf, forward transform of the R - 1 slots (sign -1), product
+// with the spectrum, reverse passes (natural slot order), outputs back into
+// buf.  tc: rl.ctab in LDS; aux: [2 * total / R] values.  Ends with a barrier.
+template <typename C>
+__device__ __forceinline__ void rader_last(typename V2<C>::t *buf, typename V2<C>::t *cbuf, typename V2<C>::t *aux,
+                                           int total, const RaderLast &rl, const double2 *tc, C sgn) {
+    typedef typename V2<C>::t c2;
+    const int R = rl.R, L = R - 1, nblk = total / R;
+    const int bd = blockDim.x;
+    for (int i = threadIdx.x; i < total; i += bd) {
+        const int b = i / R, n = i - b * R;
+        const c2 x = buf[i];
+        if (n == 0)
+            aux[b] = x;  // x_0 of the block
+        else
+            cbuf[b * L + rl.inslot[n]] = x;
+    }
+    __syncthreads();
+    run_passes<C, 0>(cbuf, nblk * L, rl.pc, tc, L, (C)-1);
+    // frequency 0 of a (the sum of x_n, n >= 1) sits in slot 0
+    for (int b = threadIdx.x; b < nblk; b += bd) aux[nblk + b] = cbuf[b * L];
+    __syncthreads();
+    const c2 *bs = reinterpret_cast<const c2 *>(sizeof(C) == 8 ? (const void *)rl.bspec : (const void *)rl.bspecf) +
+                   (sgn > (C)0 ? 0 : L);
+    for (int i = threadIdx.x; i < nblk * L; i += bd) {
+        const int b = i / L, j = i - b * L;
+        cbuf[i] = cmul<C>(cbuf[i], bs[j]);
+    }
+    __syncthreads();
+    run_passes_inv<C, 0>(cbuf, nblk * L, rl.pc, tc, L, (C)-1);
+    for (int i = threadIdx.x; i < total; i += bd) {
+        const int b = i / R, k = i - b * R;
+        const c2 x0 = aux[b];
+        const c2 y = k == 0 ? aux[nblk + b] : cbuf[b * L + rl.outslot[k]];
+        buf[i] = c2{x0.x + y.x, x0.y + y.y};
+    }
+    __syncthreads();
+}
+
 template <typename C, typename T>
 __device__ __forceinline__ typename V2<C>::t ld(const T *p) {
     const typename V2<T>::t v = *reinterpret_cast<const typename V2<T>::t *>(p);
@@ -440,14 +508,19 @@ __device__ __forceinline__ int signed_order(int c, int N, int M) { return c <= 2
 // One row by one workgroup: src and dst point at the row (may alias), buf is
 // M complex values of LDS followed by the phase table (base M).  MAXO:
 // outputs per thread of the generic pass (radices above 13); 0 when every
-// radix has a register butterfly.
-template <typename C, typename T, int MAXO, int IO = 0>
+// radix has a register butterfly.  RL: the last pass is taken by Rader's
+// convolution (rl; its table, convolution buffer and block values follow
+// the phase table in LDS).
+template <typename C, typename T, int MAXO, int IO = 0, bool RL = false>
 __device__ __forceinline__ void dft_row(int N, int M, const Passes &ps, const double *__restrict__ gtab,
                                         const int *__restrict__ src_pos, int mode, C scale, const T *src,
-                                        const T *src2, T *dst, T *dst2, typename V2<C>::t *buf) {
+                                        const T *src2, T *dst, T *dst2, typename V2<C>::t *buf,
+                                        const RaderLast *rl = nullptr) {
     typedef typename V2<C>::t c2;
     double2 *t = reinterpret_cast<double2 *>(buf + M + (M & 1));  // 16-byte aligned after the row
     load_tab(gtab, M, t);
+    double2 *tc = t + tab_entries(M);
+    if constexpr (RL) load_tab(rl->ctab, rl->R - 1, tc);
     const int twoM = 2 * M;
     const C sgn = mode == 0 ? (C)1 : (C)-1;
     const int bd = blockDim.x;
@@ -472,7 +545,13 @@ __device__ __forceinline__ void dft_row(int N, int M, const Passes &ps, const do
         }
     }
     __syncthreads();
-    run_passes<C, MAXO>(buf, M, ps, t, M, sgn);
+    if constexpr (RL) {
+        run_passes<C, MAXO>(buf, M, ps, t, M, sgn, ps.n - 1);
+        c2 *cbuf = reinterpret_cast<c2 *>(tc + tab_entries(rl->R - 1));
+        rader_last<C>(buf, cbuf, cbuf + (M / rl->R) * (rl->R - 1), M, *rl, tc, sgn);
+    } else {
+        run_passes<C, MAXO>(buf, M, ps, t, M, sgn);
+    }
     for (int c0 = 0; c0 < M; c0 += kUnroll * bd) {
         int sp[kUnroll];
 #pragma unroll

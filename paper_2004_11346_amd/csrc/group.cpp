@@ -480,7 +480,7 @@ int sht_group_create_ex(int n, const int *Ns, const int *fields, int dtype, cons
                     (e = put(lt.coef, t->coef)) != hipSuccess)
                     return hip_err(e, "group tables");
                 dev::DftHost dh;
-                dev::dft_build(t->M, dtype, dh, 1);
+                dev::dft_build(t->M, dtype, dh, 1, false);
                 if (dh.kind != dev::kDftRows || (int)dh.radix.size() > kMaxPass) return SHT_ERR_UNSUPPORTED;
                 t->radix = dh.radix;
                 t->blen = dh.blen;

@@ -80,11 +80,20 @@ struct DftHost {
     std::vector<double> bspec;                 // Rader: [2][M - 1] complex spectra (synthesis, analysis)
     std::vector<float> bspecf;
     int M1 = 0, M2 = 0, chunk1 = 0, chunk2 = 0;  // four-step split and chunks
+    // last pass of prime radix rl_R[i] > 13 by Rader's convolution, for the
+    // passes of list i (0: radix/blen, 1: radix2/blen2); rl_R[i] = 0: none.
+    // Tables as for the Rader schedule with M replaced by rl_R[i].
+    int rl_R[2] = {0, 0};
+    std::vector<int> rl_radix[2], rl_blen[2], rl_inslot[2], rl_outslot[2];
+    std::vector<double> rl_ctab[2], rl_bspec[2];
+    std::vector<float> rl_ctabf[2], rl_bspecf[2];
 };
 // force: 0 = by length and type, 1 = rows in LDS (generic passes for large
 // primes), 2 = Rader (prime M), 3 = four-step; kind = kDftNone if the schedule
-// does not apply
-void dft_build(int M, int dtype, DftHost &h, int force = 0);
+// does not apply.  rader_last: a prime factor above 13 may run as a last pass
+// by Rader's convolution (rows and four-step kernels of a plan; the grouped
+// kernels take the generic passes).
+void dft_build(int M, int dtype, DftHost &h, int force = 0, bool rader_last = true);
 
 // device view of the tables (arrays owned by the plan or group)
 struct DftPlan {
@@ -101,6 +110,14 @@ struct DftPlan {
     const double *bspec = nullptr;
     const float *bspecf = nullptr;
     void *scratch = nullptr;  // four-step: [batch][2N][M] complex of the plan's type
+    // Rader last pass of pass list i (DftHost::rl_*)
+    int rl_R[2] = {0, 0};
+    int rl_nrad[2] = {0, 0}, rl_radix[2][24] = {{0}}, rl_blen[2][24] = {{0}};
+    const double *rl_ctab[2] = {nullptr, nullptr};
+    const float *rl_ctabf[2] = {nullptr, nullptr};
+    const int *rl_inslot[2] = {nullptr, nullptr}, *rl_outslot[2] = {nullptr, nullptr};
+    const double *rl_bspec[2] = {nullptr, nullptr};
+    const float *rl_bspecf[2] = {nullptr, nullptr};
 };
 // kernel attributes of the DFT kernels (once per process, before any capture)
 hipError_t dft_init();

@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "dft_device.h"
@@ -82,6 +83,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MAXO =
     typename V2<C>::t *buf = reinterpret_cast<typename V2<C>::t *>(smem_raw);
     const RowPtrs<T, IO> r(N, M, blockIdx.y, blockIdx.x, nreal, in, out);
     dft_row<C, T, MAXO, IO>(N, M, ps, tab, src_pos, mode, scale, r.src, r.src2, r.dst, r.dst2, buf);
+}
+
+// rows whose last pass is a prime radix above 13 taken by Rader's
+// convolution (the other passes as in k_dft_rows)
+template <typename C, typename T, int MAXO, int IO>
+__global__ __launch_bounds__(kThreads) void k_dft_rows_rl(int N, int M, Passes ps, const double *__restrict__ tab,
+                                                          const int *__restrict__ src_pos, int mode, C scale,
+                                                          const T *in, T *out, int nreal, RaderLast rl) {
+    extern __shared__ unsigned char smem_raw[];
+    typename V2<C>::t *buf = reinterpret_cast<typename V2<C>::t *>(smem_raw);
+    const RowPtrs<T, IO> r(N, M, blockIdx.y, blockIdx.x, nreal, in, out);
+    dft_row<C, T, MAXO, IO, true>(N, M, ps, tab, src_pos, mode, scale, r.src, r.src2, r.dst, r.dst2, buf, &rl);
 }
 
 // Rows in LDS, persistent: workgroup w takes rows w, w + gridDim.x, ... of
@@ -284,7 +297,7 @@ __global__ __launch_bounds__(kThreads) void k_dft_rader(int N, int M, Passes pc,
 template <typename C, typename T, int IO>
 __global__ __launch_bounds__(kThreads) void k_dft_4s_a(int N, int M, int M1, int M2, int chunk, Passes ps,
                                                        const double *__restrict__ tab, const int *__restrict__ src_pos,
-                                                       int mode, const T *in, T *out, int nreal) {
+                                                       int mode, const T *in, T *out, int nreal, RaderLast rl) {
     typedef typename V2<C>::t c2;
     extern __shared__ unsigned char smem_raw[];
     c2 *buf = reinterpret_cast<c2 *>(smem_raw);
@@ -292,12 +305,14 @@ __global__ __launch_bounds__(kThreads) void k_dft_4s_a(int N, int M, int M1, int
     const int cnt = min(chunk, M2 - n2_0);
     const int total = cnt * M1;
     double2 *t = reinterpret_cast<double2 *>(buf + chunk * M1 + ((chunk * M1) & 1));
+    double2 *tc = t + tab_entries(M);
     // input rows in the I/O mode (IO 2: two real rows); output: complex
     // intermediate rows
     const RowPtrs<T, IO == 2 ? 2 : 0> r(N, M, blockIdx.z, blockIdx.y, nreal, in, out);
     const T *src = r.src;
     T *dst = out + 2 * (((int64_t)blockIdx.z * 2 * N + blockIdx.y) * M);
     load_tab(tab, M, t);
+    if (rl.R > 0) load_tab(rl.ctab, rl.R - 1, tc);
     __syncthreads();
     const int twoM = 2 * M;
     const C sgn = mode == 0 ? (C)1 : (C)-1;
@@ -326,7 +341,13 @@ __global__ __launch_bounds__(kThreads) void k_dft_4s_a(int N, int M, int M1, int
         }
     }
     __syncthreads();
-    run_passes<C, kSegMaxo>(buf, total, ps, t, M, sgn);
+    if (rl.R > 0) {
+        run_passes<C, kSegMaxo>(buf, total, ps, t, M, sgn, ps.n - 1);
+        c2 *cbuf = reinterpret_cast<c2 *>(tc + tab_entries(rl.R - 1));
+        rader_last<C>(buf, cbuf, cbuf + (chunk * M1 / rl.R) * (rl.R - 1), total, rl, tc, sgn);
+    } else {
+        run_passes<C, kSegMaxo>(buf, total, ps, t, M, sgn);
+    }
     for (int e0 = 0; e0 < total; e0 += kUnroll * bd) {
         int sp[kUnroll];
 #pragma unroll
@@ -353,7 +374,8 @@ __global__ __launch_bounds__(kThreads) void k_dft_4s_a(int N, int M, int M1, int
 template <typename C, typename T, int IO>
 __global__ __launch_bounds__(kThreads) void k_dft_4s_b(int N, int M, int M1, int M2, int chunk, Passes ps,
                                                        const double *__restrict__ tab, const int *__restrict__ src_pos,
-                                                       int mode, C scale, const T *in, T *out, int nreal) {
+                                                       int mode, C scale, const T *in, T *out, int nreal,
+                                                       RaderLast rl) {
     typedef typename V2<C>::t c2;
     extern __shared__ unsigned char smem_raw[];
     c2 *buf = reinterpret_cast<c2 *>(smem_raw);
@@ -361,11 +383,13 @@ __global__ __launch_bounds__(kThreads) void k_dft_4s_b(int N, int M, int M1, int
     const int cnt = min(chunk, M1 - k1_0);
     const int total = cnt * M2;
     double2 *t = reinterpret_cast<double2 *>(buf + chunk * M2 + ((chunk * M2) & 1));
+    double2 *tc = t + tab_entries(M);
     // input: complex intermediate rows; output rows in the I/O mode (IO 1:
     // two real rows)
     const T *src = in + 2 * (((int64_t)blockIdx.z * 2 * N + blockIdx.y) * M) + 2 * (int64_t)k1_0 * M2;
     const RowPtrs<T, IO == 1 ? 1 : 0> r(N, M, blockIdx.z, blockIdx.y, nreal, in, out);
     load_tab(tab, M, t);
+    if (rl.R > 0) load_tab(rl.ctab, rl.R - 1, tc);
     const int twoM = 2 * M;
     const C sgn = mode == 0 ? (C)1 : (C)-1;
     const int bd = blockDim.x;
@@ -383,7 +407,13 @@ __global__ __launch_bounds__(kThreads) void k_dft_4s_b(int N, int M, int M1, int
         }
     }
     __syncthreads();
-    run_passes<C, kSegMaxo>(buf, total, ps, t, M, sgn);
+    if (rl.R > 0) {
+        run_passes<C, kSegMaxo>(buf, total, ps, t, M, sgn, ps.n - 1);
+        c2 *cbuf = reinterpret_cast<c2 *>(tc + tab_entries(rl.R - 1));
+        rader_last<C>(buf, cbuf, cbuf + (chunk * M2 / rl.R) * (rl.R - 1), total, rl, tc, sgn);
+    } else {
+        run_passes<C, kSegMaxo>(buf, total, ps, t, M, sgn);
+    }
     for (int e0 = 0; e0 < total; e0 += kUnroll * bd) {
         int sp[kUnroll];
 #pragma unroll
@@ -440,9 +470,26 @@ int cu_count() {
     return cus[d];
 }
 
+// device view of the Rader last pass of pass list i (R = 0: none)
+RaderLast rader_last_of(const DftPlan &p, int i) {
+    RaderLast r;
+    std::memset(&r, 0, sizeof r);
+    r.R = p.rl_R[i];
+    if (r.R > 0) {
+        r.pc = to_passes(p.rl_nrad[i], p.rl_radix[i], p.rl_blen[i]);
+        r.ctab = p.rl_ctab[i];
+        r.inslot = p.rl_inslot[i];
+        r.outslot = p.rl_outslot[i];
+        r.bspec = p.rl_bspec[i];
+        r.bspecf = p.rl_bspecf[i];
+    }
+    return r;
+}
+
 template <typename C, int IO>
 hipError_t set_attrs_io() {
     const void *fns[] = {(const void *)&k_dft_rows_pipe<C, C, IO>,
+                         (const void *)&k_dft_rows_rl<C, C, 0, IO>, (const void *)&k_dft_rows_rl<C, C, 8, IO>,
                          (const void *)&k_dft_rows<C, C, 0, IO>,  (const void *)&k_dft_rows<C, C, 8, IO>,
                          (const void *)&k_dft_rows<C, C, 16, IO>, (const void *)&k_dft_rows<C, C, 32, IO>,
                          (const void *)&k_dft_rader<C, C, IO>,    (const void *)&k_dft_4s_a<C, C, IO>,
@@ -490,6 +537,19 @@ hipError_t launch(const DftPlan &p, int batch, int mode, double scale, const voi
                        mode, (C)scale, (const T *)in, (T *)out, nreal)
         const int nrows = 2 * p.N * batch;
         if (nrows <= 0) return hipSuccess;
+        if (p.rl_R[0] > 0) {
+            // the last pass by Rader's convolution; generic passes before it
+            // only for radices above 13 (rows of at most 8 kThreads points)
+            const RaderLast rl = rader_last_of(p, 0);
+            const size_t lrl = lds + rader_last_lds(M, rl.R, sizeof(c2));
+            if (max_radix(p.nrad - 1, p.radix) <= 13)
+                hipLaunchKernelGGL((k_dft_rows_rl<C, T, 0, IO>), grid, dim3(kThreads), lrl, s, p.N, M, ps, tab,
+                                   p.src_pos, mode, (C)scale, (const T *)in, (T *)out, nreal, rl);
+            else
+                hipLaunchKernelGGL((k_dft_rows_rl<C, T, 8, IO>), grid, dim3(kThreads), lrl, s, p.N, M, ps, tab,
+                                   p.src_pos, mode, (C)scale, (const T *)in, (T *)out, nreal, rl);
+            return hipGetLastError();
+        }
         bool tail9 = p.nrad >= 1;
         for (int i = 1; i < p.nrad; ++i) tail9 = tail9 && p.radix[i] <= 9;
         if (maxr <= 13 && tail9 && M <= kUnroll * kThreads) {
@@ -522,17 +582,20 @@ hipError_t launch(const DftPlan &p, int batch, int mode, double scale, const voi
         if (!p.scratch) return hipErrorInvalidValue;
         const Passes pa = to_passes(p.nrad, p.radix, p.blen);
         const Passes pb = to_passes(p.nrad2, p.radix2, p.blen2);
-        const size_t la = row_bytes((int64_t)p.chunk1 * p.M1) + 16 * (size_t)tab_entries(M);
-        const size_t lb = row_bytes((int64_t)p.chunk2 * p.M2) + 16 * (size_t)tab_entries(M);
+        const RaderLast rla = rader_last_of(p, 0), rlb = rader_last_of(p, 1);
+        const size_t la = row_bytes((int64_t)p.chunk1 * p.M1) + 16 * (size_t)tab_entries(M) +
+                          (rla.R ? rader_last_lds(p.chunk1 * p.M1, rla.R, sizeof(c2)) : 0);
+        const size_t lb = row_bytes((int64_t)p.chunk2 * p.M2) + 16 * (size_t)tab_entries(M) +
+                          (rlb.R ? rader_last_lds(p.chunk2 * p.M2, rlb.R, sizeof(c2)) : 0);
         T *scr = (T *)p.scratch;
         hipLaunchKernelGGL((k_dft_4s_a<C, T, IO>), dim3((p.M2 + p.chunk1 - 1) / p.chunk1, 2 * p.N, batch),
                            dim3(kThreads), la, s, p.N, M, p.M1, p.M2, p.chunk1, pa, tab, p.src_pos, mode,
-                           (const T *)in, scr, nreal);
+                           (const T *)in, scr, nreal, rla);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_dft_4s_b<C, T, IO>), dim3((p.M1 + p.chunk2 - 1) / p.chunk2, 2 * p.N, batch),
                            dim3(kThreads), lb, s, p.N, M, p.M1, p.M2, p.chunk2, pb, tab, p.src_pos2, mode, (C)scale,
-                           (const T *)scr, (T *)out, nreal);
+                           (const T *)scr, (T *)out, nreal, rlb);
         return hipGetLastError();
     }
     return hipErrorInvalidValue;
@@ -551,16 +614,20 @@ std::vector<int> prime_factors(int m) {
     return f;
 }
 
-// radices (largest first), block lengths and the slot of every output
-// frequency after the DIF passes of length L
-void passes_of(int L, std::vector<int> &radix, std::vector<int> &blen, std::vector<int> &src_pos) {
+// radices (largest first; `last`, a prime factor of L, moved to the end when
+// given), block lengths and the slot of every output frequency after the DIF
+// passes of length L
+void passes_of(int L, std::vector<int> &radix, std::vector<int> &blen, std::vector<int> &src_pos, int last = 0) {
     // prime factors, with pairs of 3 merged into radix-9 passes (one pass
     // and one LDS round trip fewer, and fewer products per point than two
     // radix-3 passes)
     radix.clear();
     int threes = 0;
+    bool took_last = false;
     for (int p : prime_factors(L)) {
-        if (p == 3)
+        if (p == last && !took_last)
+            took_last = true;
+        else if (p == 3)
             ++threes;
         else
             radix.push_back(p);
@@ -568,6 +635,7 @@ void passes_of(int L, std::vector<int> &radix, std::vector<int> &blen, std::vect
     for (; threes >= 2; threes -= 2) radix.push_back(9);
     if (threes) radix.push_back(3);
     std::sort(radix.rbegin(), radix.rend());
+    if (took_last) radix.push_back(last);
     blen.clear();
     int len = L;
     for (int R : radix) {
@@ -633,6 +701,105 @@ int primitive_root(int M) {
     return 1;
 }
 
+// Rader tables of a prime P: the passes of the convolution length P - 1, the
+// phase table of base P - 1, the slot of every input n >= 1 (g^q = n for a
+// primitive root g), the convolution slot of every output k >= 1, and the
+// spectra of b_q = e^{sgn 2 pi i g^{-q} / P} (sgn = +1, then -1) under the
+// sign -1 transform of length P - 1, divided by P - 1, in the digit-reversed
+// slots of those passes
+void rader_tables(int P, std::vector<int> &radix, std::vector<int> &blen, std::vector<int> &src_pos,
+                  std::vector<double> &ctab, std::vector<float> &ctabf, std::vector<int> &inslot,
+                  std::vector<int> &outslot, std::vector<double> &bspec, std::vector<float> &bspecf) {
+    const int L = P - 1;
+    passes_of(L, radix, blen, src_pos);
+    phase_table(L, ctab, ctabf);
+    const int g = primitive_root(P);
+    inslot.assign(P, 0);
+    outslot.assign(P, 0);
+    std::vector<int> gpow(L);
+    long long v = 1;
+    for (int q = 0; q < L; ++q) {
+        gpow[q] = (int)v;
+        inslot[(int)v] = q;
+        v = v * g % P;
+    }
+    for (int k = 1; k < P; ++k) outslot[k] = (L - inslot[k]) % L;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<long double> cr(L), ci(L);
+    for (int j = 0; j < L; ++j) {
+        cr[j] = cosl(2 * pi * j / L);
+        ci[j] = -sinl(2 * pi * j / L);
+    }
+    bspec.assign(4 * (size_t)L, 0.0);
+    bspecf.assign(4 * (size_t)L, 0.0f);
+    for (int si = 0; si < 2; ++si) {
+        const long double sgn = si == 0 ? 1.0L : -1.0L;
+        std::vector<long double> br(L), bi(L);
+        for (int q = 0; q < L; ++q) {
+            const int e = gpow[(L - q) % L];  // g^{-q}
+            br[q] = cosl(2 * pi * e / P);
+            bi[q] = sgn * sinl(2 * pi * e / P);
+        }
+        for (int j = 0; j < L; ++j) {
+            long double sr = 0, sim = 0;
+            long long idx = 0;
+            for (int q = 0; q < L; ++q) {
+                sr += br[q] * cr[idx] - bi[q] * ci[idx];
+                sim += br[q] * ci[idx] + bi[q] * cr[idx];
+                idx += j;
+                if (idx >= L) idx -= L;
+            }
+            const size_t o = 2 * ((size_t)si * L + src_pos[j]);
+            bspec[o] = (double)(sr / L);
+            bspec[o + 1] = (double)(sim / L);
+            bspecf[o] = (float)(sr / L);
+            bspecf[o + 1] = (float)(sim / L);
+        }
+    }
+}
+
+// the largest prime factor P of L with minp <= P <= 4097 whose P - 1 has
+// register radices only, or 0.  Smaller primes keep the direct P-term sums of
+// the generic pass, which cost less than the convolution's extra passes:
+// measured at N = 64 to 4096, in the four-step kernels (thousands of points
+// per workgroup) Rader's form wins from 43 on and loses at 17 and 31; in
+// rows of a few hundred points it loses at 73 and wins at 89.
+constexpr int kRaderLastMin = 41;      // four-step kernels
+constexpr int kRaderLastRowsMin = 80;  // rows in LDS
+int rader_last_prime(int L, int minp = kRaderLastMin) {
+    int best = 0;
+    for (int p : prime_factors(L)) {
+        if (p < minp || p > 4097 || p <= best) continue;
+        bool smooth = true;
+        for (int q : prime_factors(p - 1)) smooth = smooth && q <= 13;
+        if (smooth) best = p;
+    }
+    return best;
+}
+
+// fill the Rader-last tables of pass list i for prime P
+void set_rader_last(DftHost &h, int i, int P) {
+    std::vector<int> sp;
+    h.rl_R[i] = P;
+    rader_tables(P, h.rl_radix[i], h.rl_blen[i], sp, h.rl_ctab[i], h.rl_ctabf[i], h.rl_inslot[i], h.rl_outslot[i],
+                 h.rl_bspec[i], h.rl_bspecf[i]);
+}
+
+// the largest prime factor of L left to a generic pass (above 13) once
+// `rl` (0: none) runs as the Rader last pass
+int generic_prime(int L, int rl) {
+    int g = 0;
+    bool took = false;
+    for (int p : prime_factors(L)) {
+        if (p == rl && !took) {
+            took = true;
+            continue;
+        }
+        if (p > 13) g = std::max(g, p);
+    }
+    return g;
+}
+
 bool fits_rows(int M, size_t elt) {
     const std::vector<int> f = prime_factors(M);
     const int maxp = f.empty() ? 1 : *std::max_element(f.begin(), f.end());
@@ -647,7 +814,7 @@ bool fits_rader(int M, size_t elt) {
 }
 
 // four-step split with the smallest larger factor whose segments fit
-bool four_step_split(int M, size_t elt, int &M1, int &M2, int &c1, int &c2) {
+bool four_step_split(int M, size_t elt, int &M1, int &M2, int &c1, int &c2, bool rader_last) {
     int best = -1;
     for (int d = 2; (long long)d * d <= M; ++d) {
         if (M % d) continue;
@@ -662,92 +829,79 @@ bool four_step_split(int M, size_t elt, int &M1, int &M2, int &c1, int &c2) {
     M2 = best;  // length of the second pass's transforms
     M1 = M / best;
     // chunks: about 4096 elements (FP64; 8192 FP32) so that two workgroups fit
-    // a CU where possible
-    const int target = elt == 16 ? 4096 : 8192;
-    c1 = std::max(1, std::min(M2, target / M1));
-    c2 = std::max(1, std::min(M1, target / M2));
-    while (c1 > 1 && elt * ((size_t)c1 * M1 + 1) + 16 * (size_t)tab_entries(M) > kLds) --c1;
-    while (c2 > 1 && elt * ((size_t)c2 * M2 + 1) + 16 * (size_t)tab_entries(M) > kLds) --c2;
-    return true;
+    // a CU where possible; half that where a Rader last pass needs its
+    // convolution buffer beside the rows
+    const int p1 = rader_last ? rader_last_prime(M1) : 0, p2 = rader_last ? rader_last_prime(M2) : 0;
+    const int target1 = (elt == 16 ? 4096 : 8192) / (p1 ? 2 : 1), target2 = (elt == 16 ? 4096 : 8192) / (p2 ? 2 : 1);
+    c1 = std::max(1, std::min(M2, target1 / M1));
+    c2 = std::max(1, std::min(M1, target2 / M2));
+    auto lds = [&](int c, int Ml, int p) {
+        return elt * ((size_t)c * Ml + 1) + 16 * (size_t)tab_entries(M) + (p ? rader_last_lds(c * Ml, p, elt) : 0);
+    };
+    while (c1 > 1 && lds(c1, M1, p1) > kLds) --c1;
+    while (c2 > 1 && lds(c2, M2, p2) > kLds) --c2;
+    return lds(c1, M1, p1) <= kLds && lds(c2, M2, p2) <= kLds;
 }
 
 }  // namespace
 
-void dft_build(int M, int dtype, DftHost &h, int force) {
+void dft_build(int M, int dtype, DftHost &h, int force, bool rader_last) {
     const size_t elt = dtype == 0 ? 16 : 8;
     h = DftHost();
     h.M = M;
     phase_table(M, h.tab, h.tabf);
     const std::vector<int> pf = prime_factors(M);
     const bool prime = pf.size() == 1 && M > 13;
-    if (((force == 0 && !prime) || force == 1) && fits_rows(M, elt)) {
+    // a large prime factor as a last pass of the rows by Rader's convolution
+    // where the row, its convolution buffer and the tables fit LDS (rows of at
+    // most 8 kThreads points: the generic passes of the others hold 8 outputs
+    // per thread)
+    int prow = rader_last && !prime ? rader_last_prime(M, kRaderLastRowsMin) : 0;
+    if (prow && !(M <= 8 * kThreads &&
+                  elt * ((size_t)M + 1) + 16 * (size_t)tab_entries(M) + rader_last_lds(M, prow, elt) <= kLds))
+        prow = 0;
+    // by length: rows that would keep a generic pass of kRaderLastRowsMin or
+    // more (measured: 127 at N = 4096 in FP32) go four-step where its two
+    // lengths keep none of kRaderLastMin or more
+    bool rows_first = true;
+    if (force == 0 && !prime && rader_last && generic_prime(M, prow) >= kRaderLastRowsMin) {
+        int M1 = 0, M2 = 0, c1 = 0, c2 = 0;
+        if (four_step_split(M, elt, M1, M2, c1, c2, true) &&
+            generic_prime(M1, rader_last_prime(M1)) < kRaderLastMin &&
+            generic_prime(M2, rader_last_prime(M2)) < kRaderLastMin)
+            rows_first = false;
+    }
+    if (((force == 0 && !prime && rows_first) || force == 1) && fits_rows(M, elt)) {
         h.kind = kDftRows;
-        passes_of(M, h.radix, h.blen, h.src_pos);
+        passes_of(M, h.radix, h.blen, h.src_pos, prow);
+        if (prow) set_rader_last(h, 0, prow);
         return;
     }
     if ((force == 0 || force == 2) && prime && fits_rader(M, elt)) {
         h.kind = kDftRader;
-        const int L = M - 1;
-        passes_of(L, h.radix, h.blen, h.src_pos);
-        phase_table(L, h.ctab, h.ctabf);
-        const int g = primitive_root(M);
-        h.inslot.assign(M, 0);
-        h.outslot.assign(M, 0);
-        std::vector<int> gpow(L);
-        long long v = 1;
-        for (int q = 0; q < L; ++q) {
-            gpow[q] = (int)v;
-            h.inslot[(int)v] = q;
-            v = v * g % M;
-        }
-        for (int k = 1; k < M; ++k) h.outslot[k] = (L - h.inslot[k]) % L;
-        // spectrum of b_q = e^{sgn 2 pi i g^{-q} / M} under the sign -1
-        // transform of length L, divided by L, in digit-reversed slot order;
-        // sgn = +1 (synthesis) then -1 (analysis)
-        const long double pi = 3.141592653589793238462643383279502884L;
-        std::vector<long double> cr(L), ci(L);
-        for (int j = 0; j < L; ++j) {
-            cr[j] = cosl(2 * pi * j / L);
-            ci[j] = -sinl(2 * pi * j / L);
-        }
-        h.bspec.assign(4 * (size_t)L, 0.0);
-        h.bspecf.assign(4 * (size_t)L, 0.0f);
-        for (int si = 0; si < 2; ++si) {
-            const long double sgn = si == 0 ? 1.0L : -1.0L;
-            std::vector<long double> br(L), bi(L);
-            for (int q = 0; q < L; ++q) {
-                const int e = gpow[(L - q) % L];  // g^{-q}
-                br[q] = cosl(2 * pi * e / M);
-                bi[q] = sgn * sinl(2 * pi * e / M);
-            }
-            for (int j = 0; j < L; ++j) {
-                long double sr = 0, sim = 0;
-                long long idx = 0;
-                for (int q = 0; q < L; ++q) {
-                    sr += br[q] * cr[idx] - bi[q] * ci[idx];
-                    sim += br[q] * ci[idx] + bi[q] * cr[idx];
-                    idx += j;
-                    if (idx >= L) idx -= L;
-                }
-                const size_t o = 2 * ((size_t)si * L + h.src_pos[j]);
-                h.bspec[o] = (double)(sr / L);
-                h.bspec[o + 1] = (double)(sim / L);
-                h.bspecf[o] = (float)(sr / L);
-                h.bspecf[o + 1] = (float)(sim / L);
-            }
-        }
+        rader_tables(M, h.radix, h.blen, h.src_pos, h.ctab, h.ctabf, h.inslot, h.outslot, h.bspec, h.bspecf);
         return;
     }
     int M1 = 0, M2 = 0, c1 = 0, c2 = 0;
-    if ((force == 0 || force == 3) && !prime && four_step_split(M, elt, M1, M2, c1, c2)) {
-        h.kind = kDftFourStep;
-        h.M1 = M1;
-        h.M2 = M2;
-        h.chunk1 = c1;
-        h.chunk2 = c2;
-        passes_of(M1, h.radix, h.blen, h.src_pos);
-        passes_of(M2, h.radix2, h.blen2, h.src_pos2);
-        return;
+    if ((force == 0 || force == 3) && !prime) {
+        // with Rader last passes for large prime factors of M1 and M2 where
+        // the chunks fit, else the generic passes
+        bool rl = rader_last;
+        bool ok = four_step_split(M, elt, M1, M2, c1, c2, rl);
+        if (!ok && rl) ok = four_step_split(M, elt, M1, M2, c1, c2, rl = false);
+        if (ok) {
+            h.kind = kDftFourStep;
+            h.M1 = M1;
+            h.M2 = M2;
+            h.chunk1 = c1;
+            h.chunk2 = c2;
+            const int p1 = rl ? rader_last_prime(M1) : 0, p2 = rl ? rader_last_prime(M2) : 0;
+            passes_of(M1, h.radix, h.blen, h.src_pos, p1);
+            passes_of(M2, h.radix2, h.blen2, h.src_pos2, p2);
+            if (p1) set_rader_last(h, 0, p1);
+            if (p2) set_rader_last(h, 1, p2);
+            return;
+        }
     }
     h.kind = kDftNone;
 }

@@ -5,9 +5,14 @@ against the oracle, through the C ABI.
 * Every schedule is forced at small N, where the oracle computes the whole
   transform: forward SHT, adjoint and round trip, FP64 and FP32 (plain ALT,
   so only the DFT schedule changes).
+* A prime factor R of a four-step length (R >= 41) or of a row (R >= 80)
+  whose R - 1 splits into radices up to 13 runs as the last pass by Rader's
+  convolution (four-step 73 x 7 for M = 511, 43 x 41 for 1763 = 41 43, and
+  129 x 127 at N = 4096; rows of 267 = 3 89 and 2047 = 23 89); the plan stats
+  name it.
 * At N = 1500 the forced four-step runs with partial chunks in both kernels.
 * At N = 2048 (M = 8191 prime: Rader) and N = 4096 (M = 16383 = 3 43 127:
-  four-step in FP64, rows in FP32), where the full oracle transform takes too
+  four-step), where the full oracle transform takes too
   long, the forward SHT of coefficients that are non-zero at a few orders only
   is compared at sampled rows with the oracle's ALT of those orders followed by
   its direct phi sums; the inverse is checked by round trip and the adjoint by
@@ -40,10 +45,56 @@ def _cast(a, dtype):
     return a if dtype == torch.complex128 else a.astype(np.complex64).astype(np.complex128)
 
 
-# (N, schedule): M = 19 (prime), 63 = 3^2 7, 131 (prime), 255 = 3 5 17,
-# 519 = 3 173 (a large prime factor: generic pass / four-step 173 x 3)
+# (N, schedule): M = 19 (prime), 63 = 3^2 7, 131 (prime), 255 = 3 5 17
+# (17 as a generic pass; four-step 17 x 15), 519 = 3 173 (172 = 4 43: a
+# generic pass / four-step 173 x 3), 511 = 7 73 (73 generic in the rows, by
+# Rader's convolution in the four-step 73 x 7), 267 = 3 89 (89 by Rader's
+# convolution in the rows)
 CASES = [(5, "rows"), (5, "rader"), (16, "rows"), (16, "four_step"), (33, "rader"), (33, "rows"),
-         (64, "rows"), (64, "four_step"), (130, "rows"), (130, "four_step")]
+         (64, "rows"), (64, "four_step"), (130, "rows"), (130, "four_step"), (128, "rows"), (128, "four_step"),
+         (67, "rows")]
+
+
+@pytest.mark.parametrize("N,sched,dtype,kind,expect", [
+    (64, "rows", torch.complex128, "rows", [0, 0]),         # 17: the direct sums are as fast
+    (67, "rows", torch.complex128, "rows", [89, 0]),
+    (128, "rows", torch.complex128, "rows", [0, 0]),        # 73 in rows: the direct sums are faster
+    (128, "four_step", torch.complex128, "four_step", [73, 0]),  # M1 = 73, M2 = 7
+    (130, "rows", torch.complex128, "rows", [0, 0]),        # 173 - 1 = 4 43: no register radices
+    (441, None, torch.complex128, "rows", [0, 0]),          # 1763 = 41 43: rows with direct sums
+    (441, "four_step", torch.complex128, "four_step", [43, 41]),
+    (512, None, torch.complex128, "rows", [89, 0]),         # 2047 = 23 89: 23 stays a generic pass
+    (4096, None, torch.complex128, "four_step", [43, 127]),  # 129 x 127
+    (4096, None, torch.complex64, "four_step", [43, 127]),   # FP32 rows would keep 43 and 127 generic
+    (1024, None, torch.complex128, "rows", [0, 0]),         # 4095: register radices only
+])
+def test_rader_last_pass_schedule(N, sched, dtype, kind, expect):
+    """Which prime factor of M runs as a last pass by Rader's convolution, per
+    pass list (rows or the first four-step kernel, then the second), and the
+    schedule chosen by length."""
+    from paper_2004_11346_amd.sht import Plan
+    kw = {} if sched is None else {"dft_schedule": SCHED[sched]}
+    p = Plan(N, 1, dtype=dtype, method="dense", **kw)
+    st = p.stats()
+    assert st["dft"] == kind
+    assert st["dft_rader_last"] == expect
+
+
+def test_rader_last_pass_in_both_four_step_kernels():
+    """M = 1763 = 41 43: four-step 43 x 41 with a Rader last pass in each
+    kernel; the whole FP64 transform against the oracle."""
+    from paper_2004_11346_amd.sht import Plan
+    N = 441
+    print(f"dft four-step with two Rader last passes N={N}", flush=True)
+    p = Plan(N, 1, dtype=torch.complex128, method="dense", dft_schedule=SCHED["four_step"])
+    assert p.stats()["dft_rader_last"] == [43, 41]
+    beta = inputs.make_beta(N, 1, 21)
+    f = p.forward(torch.from_numpy(beta).cuda()).cpu().numpy()
+    assert rel_l2(f[0], oracle.sht_forward(N, beta[0])) <= TOL[torch.complex128]
+    grid = inputs.make_grid(N, 1, 22)
+    adj = p.backward(torch.from_numpy(grid).cuda()).cpu().numpy()
+    assert rel_l2(adj[0], oracle.sht_adjoint(N, grid[0])) <= TOL[torch.complex128]
+    p.close()
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
@@ -100,7 +151,8 @@ def _expected_rows(N, beta, orders, rows):
     return oracle.dft_synthesis(N, g, rows=rows)
 
 
-@pytest.mark.parametrize("N,dtype,sched", [(1500, torch.complex128, "four_step"), (2048, torch.complex128, None),
+@pytest.mark.parametrize("N,dtype,sched", [(512, torch.complex128, None), (1500, torch.complex128, "four_step"),
+                                           (2048, torch.complex128, None),
                                            (4096, torch.complex128, None), (4096, torch.complex64, None),
                                            (2048, torch.complex64, None)])
 def test_large_rows_vs_oracle(N, dtype, sched):
