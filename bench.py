@@ -48,14 +48,15 @@ def parse():
     ap.add_argument("--orders", default=None,
                     help="plan-build: order range LO:HI of the windows built (default: every order)")
     ap.add_argument("--workload", choices=["default", "n4096-orders", "n4096-every-order", "uneven", "rank-study",
-                                           "levels", "plan-build"],
+                                           "levels", "plan-build", "dft"],
                     default="default",
                     help="n4096-orders: N=4096, 8 fields, fast vs plain ALT on 64-order windows across the "
                          "order range; uneven: the grouped 64-transform workload; rank-study: ID sampling "
                          "(mock-Chebyshev vs random rows), adaptive rank r_k and tolerance sweeps at m = N; "
                          "levels: staged vs fused butterfly levels at leaf 32/64/128; n4096-every-order: the "
                          "fast ALT of every order at N=4096 in 16 shares vs the plain form; plan-build: host "
-                         "construction of the fast-form plan of every order of --N, window by window")
+                         "construction of the fast-form plan of every order of --N, window by window; dft: the "
+                         "phi DFT alone for the schedules of several lengths, against the HBM roofline")
     return ap.parse_args()
 
 
@@ -943,6 +944,60 @@ def fp32_legs(S, inputs, timer, N, batch, beta_np, no_check):
     return legs
 
 
+def dft_lengths(args):
+    """The phi DFT alone (Section 1, the phi sums of the SHT) for lengths that
+    take each schedule: rows in LDS with register radices (N = 1024), rows with
+    a Rader last pass (N = 512, 2047 = 23 x 89), a prime row by Rader's
+    convolution (N = 2048, 8191), four-step with Rader last passes (N = 4096,
+    16383 = 129 x 127, FP64 and FP32).  Plain-form plans (the DFT does not
+    depend on the ALT form); synthesis and analysis timed with the library's
+    HIP events over 3 calls each.  Algorithmic bytes: one read and one write of
+    the grid per pass through HBM (one for rows and Rader, two for four-step)."""
+    import torch
+
+    import paper_2004_11346_amd.sht as S
+    from paper_2004_11346_amd import inputs
+
+    torch.cuda.init()
+    cases = [(1024, 32, "f64"), (512, 32, "f64"), (2048, 16, "f64"), (4096, 8, "f64"), (4096, 8, "f32")]
+    out = []
+    for N, B, dt in cases:
+        cdt = torch.complex128 if dt == "f64" else torch.complex64
+        elt = 16 if dt == "f64" else 8
+        M = 4 * N - 1
+        plan = S.Plan(N, B, dtype=cdt, method="dense")
+        st = plan.stats()
+        beta = torch.from_numpy(inputs.make_beta(N, B, 2, dist="decay")).to(cdt).cuda()
+        f = plan.empty_grid()
+        bo = plan.empty_coefs()
+        plan.forward(beta, out=f)
+        plan.inverse(f, out=bo)
+        torch.cuda.synchronize()
+        rt = rel_l2(bo.cpu().numpy().astype("complex128"), beta.cpu().numpy().astype("complex128"))
+        plan.profile(True)
+        for _ in range(3):
+            plan.forward(beta, out=f)
+            plan.inverse(f, out=bo)
+        torch.cuda.synchronize()
+        rep = plan.profile_report()
+        plan.profile(False)
+        grid_bytes = elt * B * 2 * N * M
+        passes = 2 if st["dft"] == "four_step" else 1
+        r = {"N": N, "batch": B, "dtype": dt, "M": M, "schedule": st["dft"], "rader_last": st["dft_rader_last"],
+             "grid_bytes": grid_bytes, "round_trip_rel_l2": rt}
+        for d in ("synthesis", "analysis"):
+            ms = rep["k_dft_" + d]["total_ms"] / 3
+            gbs = 2 * passes * grid_bytes / (ms / 1e3) / 1e9
+            r[d] = {"ms": ms, "GB_s": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
+        print(json.dumps(r), flush=True)
+        out.append(r)
+        del f, bo, beta
+        plan.close()
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "phi DFT per direction, GB/s of one read and one write of the grid per HBM pass",
+                      "n_gpus": 1, "data": "synthetic", "cases": out}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -973,6 +1028,9 @@ def main():
         return
     if args.workload == "plan-build":
         plan_build(args)
+        return
+    if args.workload == "dft":
+        dft_lengths(args)
         return
 
     import numpy as np
