@@ -10,6 +10,8 @@ against the oracle, through the C ABI.
   convolution (four-step 73 x 7 for M = 511, 43 x 41 for 1763 = 41 43, and
   129 x 127 at N = 4096; rows of 267 = 3 89 and 2047 = 23 89); the plan stats
   name it.
+* The persistent row kernel over more rows than its workgroups (N = 16,
+  33 fields: a partial last round), both ALT forms, every field.
 * At N = 1500 the forced four-step runs with partial chunks in both kernels.
 * At N = 2048 (M = 8191 prime: Rader) and N = 4096 (M = 16383 = 3 43 127:
   four-step), where the full oracle transform takes too
@@ -116,6 +118,34 @@ def test_forced_schedule_vs_oracle(N, sched, dtype):
         assert rel_l2(fh[b], oracle.sht_forward(N, beta[b])) <= TOL[dtype], b
         assert rel_l2(ah[b], oracle.sht_adjoint(N, grid[b])) <= TOL[dtype], b
     assert rel_l2(bh, beta) <= TOL[dtype]
+    p.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("method", ["dense", "idbf"])
+def test_persistent_rows_partial_last_round(dtype, method):
+    """The persistent row kernel (rows of at most 4096 points with register
+    radices, two workgroups per CU taking rows in turn, the next row loaded
+    during the current one's passes) over 33 fields of N = 16 (M = 63 = 9 7):
+    1056 rows, so the last round of the workgroups is partial; forward,
+    inverse and adjoint against the oracle for every field."""
+    from paper_2004_11346_amd.sht import Plan
+    N, batch = 16, 33
+    print(f"dft persistent rows N={N} batch={batch} {method} {dtype}", flush=True)
+    kw = {"n0": 8, "leaf": 8} if method == "idbf" else {}
+    p = Plan(N, batch, dtype=dtype, method=method, **kw)
+    assert p.stats()["dft"] == "rows"
+    beta = _cast(inputs.make_beta(N, batch, 41), dtype)
+    grid = _cast(inputs.make_grid(N, batch, 42), dtype)
+    f = p.forward(torch.from_numpy(beta).to(dtype).cuda()).cpu().numpy()
+    bi = p.inverse(torch.from_numpy(grid).to(dtype).cuda()).cpu().numpy()
+    ba = p.backward(torch.from_numpy(grid).to(dtype).cuda()).cpu().numpy()
+    # the fast form's FP64 factors carry the 1e-12 ID tolerance
+    tol = 1e-11 if (method == "idbf" and dtype == torch.complex128) else TOL[dtype]
+    for b in range(batch):
+        assert rel_l2(f[b], oracle.sht_forward(N, beta[b])) <= tol, b
+        assert rel_l2(bi[b], oracle.sht_inverse(N, grid[b])) <= tol, b
+        assert rel_l2(ba[b], oracle.sht_adjoint(N, grid[b])) <= tol, b
     p.close()
 
 
