@@ -276,8 +276,11 @@ int sht_alt_apply(const sht_plan_t *plan, int m_lo, int m_hi, int dir,
                   const void *in, void *out, void *stream);
 
 /* Plan statistics as JSON (block counts by type, ranks, stored entries,
- * bytes, build time).  Writes at most `cap` bytes including the NUL; returns
- * the full length needed (>= 0) or a negative error. */
+ * bytes, build time; the phi DFT schedule "dft" (rows, rader, four_step or
+ * none) and "dft_rader_last", the prime of each pass list (rows or first
+ * four-step kernel, second four-step kernel; 0: none) whose last pass runs
+ * by Rader's convolution).  Writes at most `cap` bytes including the NUL;
+ * returns the full length needed (>= 0) or a negative error. */
 int sht_plan_stats(const sht_plan_t *plan, char *json, size_t cap);
 
 /* Per-kernel timing.  sht_profile(plan, 1) clears earlier records and makes
