@@ -392,6 +392,19 @@ int sht_host_plan_stats(const sht_host_plan_t *hp, char *json, size_t cap);
 /* The library's own 2N-point Gauss-Legendre rule (ascending). */
 int sht_host_gauss_legendre(int n, double *x, double *w);
 
+/* The phi DFT tables a plan of degree N, element type dtype (SHT_F64 or
+ * SHT_F32) and schedule (SHT_DFT_*) hands to its kernels, as JSON (same size
+ * convention as sht_plan_stats): "kind" (rows, rader, four_step, none), "M",
+ * the pass lists ("radix", "blen", "src_pos": radices in pass order, block
+ * length before each pass, and the slot of every output frequency after the
+ * passes; "radix2", ... for the second four-step kernel, of length M2), "M1",
+ * "M2", "chunk1", "chunk2"; for the Rader schedule "inslot", "outslot" and
+ * "bspec" ([2][M - 1] complex, sign +1 then -1, in the slots of the passes of
+ * M - 1); and "rader_last": for each pass list, {"R": prime or 0, "radix",
+ * "blen", "src_pos" of R - 1, "inslot", "outslot", "bspec"}.  Host only, no
+ * GPU; for checking the DFT schedules (Section 1, the phi sums). */
+int sht_host_dft_tables(int N, int dtype, int schedule, char *json, size_t cap);
+
 #ifdef __cplusplus
 }
 #endif

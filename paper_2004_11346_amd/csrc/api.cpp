@@ -216,6 +216,53 @@ int sht_host_gauss_legendre(int n, double *x, double *w) {
     return SHT_OK;
 }
 
+static int copy_json(const std::string &s, char *json, size_t cap);
+
+int sht_host_dft_tables(int N, int dtype, int schedule, char *json, size_t cap) {
+    if (N < 1 || N > 8192 || (dtype != SHT_F64 && dtype != SHT_F32) || schedule < SHT_DFT_AUTO ||
+        schedule > SHT_DFT_FOUR_STEP)
+        return SHT_ERR_INVALID_ARG;
+    dev::DftHost h;
+    dev::dft_build(4 * N - 1, dtype, h, schedule);
+    std::ostringstream os;
+    os.precision(17);
+    auto ints = [&](const char *name, const std::vector<int> &v) {
+        os << ",\"" << name << "\":[";
+        for (size_t i = 0; i < v.size(); ++i) os << (i ? "," : "") << v[i];
+        os << "]";
+    };
+    auto dbls = [&](const char *name, const std::vector<double> &v) {
+        os << ",\"" << name << "\":[";
+        for (size_t i = 0; i < v.size(); ++i) os << (i ? "," : "") << v[i];
+        os << "]";
+    };
+    static const char *kinds[] = {"none", "rows", "rader", "four_step"};
+    os << "{\"kind\":\"" << kinds[h.kind + 1] << "\",\"M\":" << h.M << ",\"M1\":" << h.M1 << ",\"M2\":" << h.M2
+       << ",\"chunk1\":" << h.chunk1 << ",\"chunk2\":" << h.chunk2;
+    ints("radix", h.radix);
+    ints("blen", h.blen);
+    ints("src_pos", h.src_pos);
+    ints("radix2", h.radix2);
+    ints("blen2", h.blen2);
+    ints("src_pos2", h.src_pos2);
+    ints("inslot", h.inslot);
+    ints("outslot", h.outslot);
+    dbls("bspec", h.bspec);
+    os << ",\"rader_last\":[";
+    for (int i = 0; i < 2; ++i) {
+        os << (i ? "," : "") << "{\"R\":" << h.rl_R[i];
+        ints("radix", h.rl_radix[i]);
+        ints("blen", h.rl_blen[i]);
+        ints("src_pos", h.rl_src_pos[i]);
+        ints("inslot", h.rl_inslot[i]);
+        ints("outslot", h.rl_outslot[i]);
+        dbls("bspec", h.rl_bspec[i]);
+        os << "}";
+    }
+    os << "]}";
+    return copy_json(os.str(), json, cap);
+}
+
 int sht_plan_create(int N, int batch, int dtype, int method, const sht_plan_opts *opts,
                     sht_plan_t **out) {
     if (!out) return SHT_ERR_INVALID_ARG;

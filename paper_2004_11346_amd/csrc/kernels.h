@@ -84,7 +84,7 @@ struct DftHost {
     // passes of list i (0: radix/blen, 1: radix2/blen2); rl_R[i] = 0: none.
     // Tables as for the Rader schedule with M replaced by rl_R[i].
     int rl_R[2] = {0, 0};
-    std::vector<int> rl_radix[2], rl_blen[2], rl_inslot[2], rl_outslot[2];
+    std::vector<int> rl_radix[2], rl_blen[2], rl_src_pos[2], rl_inslot[2], rl_outslot[2];
     std::vector<double> rl_ctab[2], rl_bspec[2];
     std::vector<float> rl_ctabf[2], rl_bspecf[2];
 };

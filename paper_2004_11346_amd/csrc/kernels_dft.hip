@@ -779,10 +779,9 @@ int rader_last_prime(int L, int minp = kRaderLastMin) {
 
 // fill the Rader-last tables of pass list i for prime P
 void set_rader_last(DftHost &h, int i, int P) {
-    std::vector<int> sp;
     h.rl_R[i] = P;
-    rader_tables(P, h.rl_radix[i], h.rl_blen[i], sp, h.rl_ctab[i], h.rl_ctabf[i], h.rl_inslot[i], h.rl_outslot[i],
-                 h.rl_bspec[i], h.rl_bspecf[i]);
+    rader_tables(P, h.rl_radix[i], h.rl_blen[i], h.rl_src_pos[i], h.rl_ctab[i], h.rl_ctabf[i], h.rl_inslot[i],
+                 h.rl_outslot[i], h.rl_bspec[i], h.rl_bspecf[i]);
 }
 
 // the largest prime factor of L left to a generic pass (above 13) once

@@ -36,6 +36,7 @@ EXPORTED = [
     "sht_group_tune", "sht_group_capture", "sht_group_replay", "sht_group_stats", "sht_inverse_noalloc",
     "sht_set_graph_capture", "sht_plan_cache_verify", "sht_plan_cache_path",
     "sht_forward_real", "sht_inverse_real", "sht_group_opts_default", "sht_group_create_ex",
+    "sht_host_dft_tables",
 ]
 
 
@@ -120,6 +121,7 @@ def load():
         lib.sht_host_alt_matrix.argtypes = [P, I, I, P]
         lib.sht_host_plan_stats.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
         lib.sht_host_gauss_legendre.argtypes = [I, P, P]
+        lib.sht_host_dft_tables.argtypes = [I, I, I, ctypes.c_char_p, ctypes.c_size_t]
         lib.sht_group_create.argtypes = [I, P, P, I, PP]
         lib.sht_group_opts_default.argtypes = [ctypes.POINTER(GroupOpts)]
         lib.sht_group_opts_default.restype = None
@@ -139,7 +141,7 @@ def load():
                                                    "sht_plan_info", "sht_plan_nodes",
                                                    "sht_host_plan_create", "sht_host_plan_apply",
                                                    "sht_host_alt_matrix", "sht_host_plan_stats",
-                                                   "sht_host_gauss_legendre"):
+                                                   "sht_host_gauss_legendre", "sht_host_dft_tables"):
                 f.restype = ctypes.c_int
         _lib = lib
         return lib
