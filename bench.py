@@ -134,7 +134,7 @@ TRAFFIC = {
                                                      "profile": "profiles/alt_fwd_dense_n1024_b32_f64.md"},
     ("dense", 1024, 1, "f64", "k_dense_fwd_valu"): {"bytes_per_call": 0.7513e9, "sha": "21a5dbab89ebbe02",
                                                     "profile": "profiles/alt_fwd_dense_n1024_b1_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_gen_adj"): {"bytes_per_call": 22.702e9, "sha": "a95bef2d30025b5a",
+    ("idbf", 1024, 32, "f64", "k_gen_adj"): {"bytes_per_call": 22.709e9, "sha": "a95bef2d30025b5a",
                                               "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
     ("idbf", 1024, 32, "f64", "k_gen_fwd_mfma"): {"bytes_per_call": 12.625e9, "sha": "a95bef2d30025b5a",
                                                    "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
@@ -146,9 +146,9 @@ TRAFFIC = {
                                           "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
     ("idbf", 1024, 32, "f64", "k_scatter"): {"bytes_per_call": 4.306e9, "sha": "a900dd7b71176d56",
                                              "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_dft_synthesis"): {"bytes_per_call": 8.780e9, "sha": "0417e4ec9cc46b82",
+    ("idbf", 1024, 32, "f64", "k_dft_synthesis"): {"bytes_per_call": 8.779e9, "sha": "24a9a20d9d621217",
                                                     "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
-    ("idbf", 1024, 32, "f64", "k_dft_analysis"): {"bytes_per_call": 8.780e9, "sha": "0417e4ec9cc46b82",
+    ("idbf", 1024, 32, "f64", "k_dft_analysis"): {"bytes_per_call": 8.779e9, "sha": "24a9a20d9d621217",
                                                    "profile": "profiles/traffic_sht_idbf_n1024_b32_f64.md"},
 }
 
